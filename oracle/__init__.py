@@ -1,0 +1,113 @@
+"""CPU oracle (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path never routes through it.
+
+Thin ctypes wrapper over ``mcl_oracle.c`` (the definitions and readings are in
+that file's header comment) plus its build step.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mcl_oracle.c")
+LIB = os.path.join(HERE, "libmcl_oracle.so")
+
+DTYPE_CODE = {"i16": 0, "i8": 1, "f32": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: -O2, no contraction, no fast-math."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-pthread", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        L.oracle_voxel_indices.argtypes = [P, C.c_float, P, P, C.c_int32, P, C.c_int32, P]
+        L.oracle_sensor_update.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, P, P, C.c_int32,
+                                           P, C.c_int32, C.c_float, P, P, C.c_int32]
+        L.oracle_normalize.argtypes = [P, C.c_int32, P, P, P]
+        L.oracle_resample.argtypes = [P, C.c_int32, C.c_uint64, P]
+        for f in (L.oracle_voxel_indices, L.oracle_sensor_update, L.oracle_normalize, L.oracle_resample):
+            f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _map_args(tmap):
+    dims = np.array([tmap.nx, tmap.ny, tmap.nz], np.int32)
+    origin = np.array(tmap.origin, np.float32)
+    vals = np.ascontiguousarray(tmap.values)
+    return dims, origin, vals
+
+
+def voxel_indices(tmap, points: np.ndarray, poses: np.ndarray) -> np.ndarray:
+    """int64 [N, K]: linear voxel index i + nx (j + ny k) or -1 outside the map."""
+    dims, origin, _ = _map_args(tmap)
+    pts = np.ascontiguousarray(points, np.float32)
+    ps = np.ascontiguousarray(poses, np.float32)
+    K, N = pts.shape[1], ps.shape[1]
+    out = np.empty((N, K), np.int64)
+    rc = lib().oracle_voxel_indices(_p(dims), tmap.voxel, _p(origin), _p(pts), K, _p(ps), N, _p(out))
+    assert rc == 0
+    return out
+
+
+def sensor_update(tmap, points: np.ndarray, poses: np.ndarray, sigma: float, nthreads: int = 1,
+                  return_sum: bool = False):
+    """float64 log-weights l_n (and optionally the sums of squared stored values)."""
+    dims, origin, vals = _map_args(tmap)
+    pts = np.ascontiguousarray(points, np.float32)
+    ps = np.ascontiguousarray(poses, np.float32)
+    K, N = pts.shape[1], ps.shape[1]
+    logw = np.empty(N, np.float64)
+    ssum = np.empty(N, np.float64)
+    rc = lib().oracle_sensor_update(_p(dims), tmap.voxel, _p(origin), tmap.tau, DTYPE_CODE[tmap.dtype],
+                                    _p(vals), _p(pts), K, _p(ps), N, sigma, _p(logw), _p(ssum), nthreads)
+    assert rc == 0
+    return (logw, ssum) if return_sum else logw
+
+
+def normalize(logw: np.ndarray):
+    """(w float64 [N], wq uint64 [N], log_z float)."""
+    lw = np.ascontiguousarray(logw, np.float64)
+    N = lw.shape[0]
+    w = np.empty(N, np.float64)
+    wq = np.empty(N, np.uint64)
+    lz = np.empty(1, np.float64)
+    rc = lib().oracle_normalize(_p(lw), N, _p(w), _p(wq), _p(lz))
+    assert rc == 0
+    return w, wq, float(lz[0])
+
+
+def resample(wq: np.ndarray, u: int) -> np.ndarray:
+    """int32 [N] ancestor indices (non-decreasing)."""
+    W = np.ascontiguousarray(wq, np.uint64)
+    N = W.shape[0]
+    idx = np.empty(N, np.int32)
+    rc = lib().oracle_resample(_p(W), N, C.c_uint64(int(u) & (2**64 - 1)), _p(idx))
+    assert rc == 0
+    return idx

@@ -1,0 +1,282 @@
+/*
+ * CPU oracle for the 6-DoF MCL sensor update, weight normalisation and
+ * resampling of Eisoldt et al., "Towards 6D MCL for LiDARs in 3D TSDF Maps on
+ * Embedded Systems with GPUs" (arXiv 2310.04172).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library.  The product (the HIP library) never
+ * calls it, and the two share no code.
+ *
+ * Plain and slow on purpose: one particle at a time, one scan point at a time,
+ * in the order of the definitions.  Arithmetic is float64 or exact integer,
+ * except the voxel-index step, whose float32 operation order is a fixed recipe
+ * (so that voxel indices can be compared bit for bit with any other
+ * implementation of the same recipe).  Build with -ffp-contract=off.
+ *
+ * Definitions, with the reading taken where the paper is silent:
+ *
+ *  Particle (Eq. 1, Eq. 2): p = (s, w), s a 6-DoF pose.  Handed over as the
+ *    rotation matrix R (row-major) and translation t of the sensor in the world,
+ *    12 float32 rows r00 r01 r02 r10 r11 r12 r20 r21 r22 tx ty tz, each of
+ *    length N (structure of arrays).
+ *
+ *  Map (§III): dense TSDF, voxel (i,j,k) covers [o + i v, o + (i+1) v) per axis,
+ *    values clamped to the truncation band; stored x-fastest
+ *    (index i + nx (j + ny k)) as int16 / int8 fixed point q = d / tau * Q
+ *    (Q = 32767 / 127) or float32 metres.  Reading: nearest-voxel lookup (the
+ *    voxel that contains the point, half-open cells); a point outside the map
+ *    reads +Q (+tau), truncated free space.
+ *
+ *  Voxel-index recipe (float32, IEEE round-to-nearest-even, no fused ops):
+ *      inv_v = (float)(1.0 / (double)v)                      once per map
+ *      a_jk  = r_jk * inv_v ;  b_j = (t_j - o_j) * inv_v        once per particle
+ *      g_j   = ((a_j0 px + a_j1 py) + a_j2 pz) + b_j            per point, each op rounded
+ *      valid iff 0 <= g_j < n_j for j = x, y, z ;  i_j = (int) g_j.
+ *
+ *  Sensor model (Eq. 3, endpoint model): a point's likelihood is a Gaussian in
+ *    the map distance m(x, z).  Reading: a particle's weight is the product over
+ *    the scan points (independent beams), kept in the log domain without the
+ *    constant factor (it cancels in normalisation):
+ *        l_n = -(s^2 / (2 sigma^2)) * sum_k q_k^2,   s = tau / Q (s = 1 for float32).
+ *    The sum of squares is exact (int64) for fixed-point maps and float64 for
+ *    float32 maps (each square is exact in float64).
+ *
+ *  Normalisation (§V-A sums the weights for normalisation), float64:
+ *        m = max_n l_n ;  S = sum_n exp(l_n - m) in index order ;
+ *        log Z = m + log S ;  w_n = exp(l_n - log Z) ;
+ *        W_n = floor(w_n * 2^42)  (64-bit fixed point, for an integer scan).
+ *
+ *  Resampling (§III: a new particle set is drawn from the weighted one).
+ *    Reading: low-variance (systematic) resampling on the fixed-point weights.
+ *    With C_i = W_0 + ... + W_i, T = C_{N-1} and one uniform 64-bit draw u,
+ *    the offset is r = floor(u T / 2^64) in [0, T), and output slot m takes the
+ *    particle i whose scaled cell [N C_{i-1}, N C_i) holds m T + r.  Written
+ *    below as the familiar single sweep with a moving threshold.  T = 0 (every
+ *    weight zero) is read as equal weights: slot m takes particle m.
+ */
+
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORACLE_I16 = 0, ORACLE_I8 = 1, ORACLE_F32 = 2 };
+
+typedef struct {
+    int32_t n[3];
+    float inv_v;
+    float o[3];
+} grid_t;
+
+static grid_t make_grid(const int32_t dims[3], float voxel, const float origin[3]) {
+    grid_t g;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = dims[a];
+        g.o[a] = origin[a];
+    }
+    g.inv_v = (float)(1.0 / (double)voxel);
+    return g;
+}
+
+/* Per-particle constants of the index recipe. */
+static void particle_consts(const float *poses, int64_t N, int64_t n, const grid_t *g,
+                            float a[9], float b[3]) {
+    for (int j = 0; j < 3; ++j) {
+        for (int k = 0; k < 3; ++k) {
+            float r = poses[(int64_t)(3 * j + k) * N + n];
+            a[3 * j + k] = r * g->inv_v;
+        }
+        float shifted = poses[(int64_t)(9 + j) * N + n] - g->o[j];
+        b[j] = shifted * g->inv_v;
+    }
+}
+
+/* Linear voxel index i + nx (j + ny k) of one point, or -1 outside the map. */
+static int64_t voxel_index(const float a[9], const float b[3], float px, float py, float pz,
+                           const grid_t *g) {
+    int32_t idx[3];
+    for (int j = 0; j < 3; ++j) {
+        float s = a[3 * j + 0] * px;
+        float t = a[3 * j + 1] * py;
+        s = s + t;
+        t = a[3 * j + 2] * pz;
+        s = s + t;
+        s = s + b[j];
+        if (!(s >= 0.0f && s < (float)g->n[j])) return -1; /* NaN fails too */
+        idx[j] = (int32_t)s;
+    }
+    return (int64_t)idx[0] + (int64_t)g->n[0] * ((int64_t)idx[1] + (int64_t)g->n[1] * idx[2]);
+}
+
+int oracle_voxel_indices(const int32_t dims[3], float voxel, const float origin[3],
+                         const float *points, int32_t K, const float *poses, int32_t N,
+                         int64_t *lin) {
+    if (K < 0 || N < 0) return -1;
+    grid_t g = make_grid(dims, voxel, origin);
+    for (int64_t n = 0; n < N; ++n) {
+        float a[9], b[3];
+        particle_consts(poses, N, n, &g, a, b);
+        for (int64_t k = 0; k < K; ++k)
+            lin[n * K + k] = voxel_index(a, b, points[k], points[K + k], points[2 * (int64_t)K + k], &g);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ sensor update */
+
+typedef struct {
+    grid_t g;
+    int32_t dtype;
+    const void *values;
+    double tau;
+    int32_t Q;
+    const float *points;
+    int64_t K;
+    const float *poses;
+    int64_t N;
+    double c;          /* s^2 / (2 sigma^2) */
+    double *logw;
+    double *ssum;
+    int64_t n0, n1;    /* this worker's particle range */
+} su_job_t;
+
+/* Sum of squared map values over the scan for particle n: exact for fixed point. */
+static double particle_sum_sq(const su_job_t *J, int64_t n) {
+    float a[9], b[3];
+    particle_consts(J->poses, J->N, n, &J->g, a, b);
+    const float *px = J->points, *py = J->points + J->K, *pz = J->points + 2 * J->K;
+    if (J->dtype == ORACLE_F32) {
+        const float *vals = (const float *)J->values;
+        double acc = 0.0;
+        for (int64_t k = 0; k < J->K; ++k) {
+            int64_t v = voxel_index(a, b, px[k], py[k], pz[k], &J->g);
+            double d = v < 0 ? (double)(float)J->tau : (double)vals[v];
+            acc += d * d;
+        }
+        return acc;
+    }
+    int64_t acc = 0;
+    for (int64_t k = 0; k < J->K; ++k) {
+        int64_t v = voxel_index(a, b, px[k], py[k], pz[k], &J->g);
+        int64_t q;
+        if (v < 0)
+            q = J->Q;
+        else if (J->dtype == ORACLE_I16)
+            q = ((const int16_t *)J->values)[v];
+        else
+            q = ((const int8_t *)J->values)[v];
+        acc += q * q;
+    }
+    return (double)acc; /* < 2^50, exact */
+}
+
+static void *su_worker(void *arg) {
+    su_job_t *J = (su_job_t *)arg;
+    for (int64_t n = J->n0; n < J->n1; ++n) {
+        double S = particle_sum_sq(J, n);
+        if (J->ssum) J->ssum[n] = S;
+        J->logw[n] = -(S * J->c);
+    }
+    return NULL;
+}
+
+/*
+ * l_n for every particle (see the header comment).  ssum may be NULL; else it
+ * receives the sum of squared stored values (exact integers for fixed point).
+ * nthreads > 1 splits the particles into that many contiguous groups, one
+ * thread each, as the paper's CPU implementation does (§V-A); the result does
+ * not depend on the thread count.
+ */
+int oracle_sensor_update(const int32_t dims[3], float voxel, const float origin[3], float tau,
+                         int32_t dtype, const void *values, const float *points, int32_t K,
+                         const float *poses, int32_t N, float sigma, double *logw, double *ssum,
+                         int32_t nthreads) {
+    if (K < 0 || N < 0 || dtype < 0 || dtype > 2 || !(sigma > 0.0f)) return -1;
+    su_job_t base;
+    memset(&base, 0, sizeof base);
+    base.g = make_grid(dims, voxel, origin);
+    base.dtype = dtype;
+    base.values = values;
+    base.tau = (double)tau;
+    base.Q = dtype == ORACLE_I16 ? 32767 : dtype == ORACLE_I8 ? 127 : 1;
+    base.points = points;
+    base.K = K;
+    base.poses = poses;
+    base.N = N;
+    double s = dtype == ORACLE_F32 ? 1.0 : (double)tau / (double)base.Q;
+    double sg = (double)sigma;
+    base.c = (s * s) / (2.0 * sg * sg);
+    base.logw = logw;
+    base.ssum = ssum;
+    if (nthreads <= 1 || N < 2) {
+        base.n0 = 0;
+        base.n1 = N;
+        su_worker(&base);
+        return 0;
+    }
+    if (nthreads > N) nthreads = N;
+    su_job_t *jobs = (su_job_t *)malloc(sizeof(su_job_t) * (size_t)nthreads);
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    if (!jobs || !th) {
+        free(jobs);
+        free(th);
+        return -2;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = base;
+        jobs[t].n0 = (int64_t)N * t / nthreads;
+        jobs[t].n1 = (int64_t)N * (t + 1) / nthreads;
+        pthread_create(&th[t], NULL, su_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(jobs);
+    free(th);
+    return 0;
+}
+
+/* ------------------------------------------------------------ normalisation */
+
+int oracle_normalize(const double *logw, int32_t N, double *w, uint64_t *wq, double *log_z) {
+    if (N < 1) return -1;
+    double m = logw[0];
+    for (int32_t n = 1; n < N; ++n)
+        if (logw[n] > m) m = logw[n];
+    double S = 0.0;
+    for (int32_t n = 0; n < N; ++n) S += exp(logw[n] - m);
+    double lz = m + log(S);
+    for (int32_t n = 0; n < N; ++n) {
+        double wn = exp(logw[n] - lz);
+        if (w) w[n] = wn;
+        if (wq) wq[n] = (uint64_t)floor(ldexp(wn, 42));
+    }
+    if (log_z) *log_z = lz;
+    return 0;
+}
+
+/* -------------------------------------------------------------- resampling */
+
+int oracle_resample(const uint64_t *wq, int32_t N, uint64_t u, int32_t *idx) {
+    if (N < 1) return -1;
+    uint64_t T = 0;
+    for (int32_t i = 0; i < N; ++i) T += wq[i];
+    if (T == 0) {
+        for (int32_t m = 0; m < N; ++m) idx[m] = m;
+        return 0;
+    }
+    uint64_t r = (uint64_t)(((unsigned __int128)u * T) >> 64);
+    /* Sweep the slots in order; the threshold for slot m is m T + r, and the
+       particle cursor advances past every particle whose scaled cumulative
+       weight N C_i does not exceed the threshold. */
+    int32_t i = 0;
+    uint64_t C = wq[0];
+    for (int32_t m = 0; m < N; ++m) {
+        uint64_t x = (uint64_t)m * T + r;
+        while (x >= (uint64_t)N * C) {
+            ++i;
+            C += wq[i];
+        }
+        idx[m] = i;
+    }
+    return 0;
+}
