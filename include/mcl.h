@@ -1,0 +1,139 @@
+/*
+ * mcl.h - C ABI of the MI355X (gfx950) sensor update for 6-DoF Monte Carlo
+ * localisation in TSDF maps (Eisoldt et al., "Towards 6D MCL for LiDARs in 3D
+ * TSDF Maps on Embedded Systems with GPUs", arXiv 2310.04172).
+ *
+ * One MCL iteration (§III) is motion update, sensor update, resampling; the
+ * sensor update is the costly step the paper moves to the GPU (§IV, §V-B).
+ * This library runs the sensor update, the weight normalisation and the
+ * resampling on the GPU, so particle state never leaves device memory.
+ *
+ * Conventions shared by every call:
+ *  - Device pointers are plain HIP device addresses (for example a torch
+ *    tensor's data_ptr()); the caller owns them and keeps them alive until the
+ *    stream has executed the work.  `stream` is a hipStream_t (NULL = the
+ *    default stream); every call only enqueues work on it and returns.
+ *  - Argument errors are detected on the host before anything is enqueued; a
+ *    failing call enqueues nothing.  Launch failures return MCL_EDEVICE.  The
+ *    text of the last error on the calling thread is mcl_last_error().
+ *  - Poses: 12 float32 rows of length N (structure of arrays), in this order:
+ *    r00 r01 r02 r10 r11 r12 r20 r21 r22 tx ty tz - the rotation R (row-major)
+ *    and translation t of the sensor in the map frame, the 6-DoF particle state
+ *    of Eq. (2) in matrix form.
+ *  - Scan points: 3 float32 rows x, y, z of length K in the sensor frame, in
+ *    metres.  Any order is correct; ring-major order (neighbouring beams next to
+ *    each other) makes the map reads of neighbouring lanes hit the same lines.
+ */
+#ifndef MCL_H
+#define MCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mcl_status;
+#define MCL_OK 0
+#define MCL_EINVAL (-1)  /* bad argument (NULL, size, value)                 */
+#define MCL_ENOMEM (-2)  /* device allocation failed                          */
+#define MCL_EDEVICE (-3) /* HIP runtime / launch error                        */
+#define MCL_ERANGE (-4)  /* a size beyond the limits below                    */
+
+#define MCL_MAX_PARTICLES (1 << 21) /* N per call                                */
+#define MCL_MAX_POINTS (1 << 20)    /* K per call                                */
+#define MCL_WQ_SHIFT 42             /* fixed-point weights are floor(w * 2^42)   */
+
+/* Storage type of the TSDF values. */
+typedef enum {
+    MCL_TSDF_I16 = 0, /* q = rint(d / tau * 32767), int16               */
+    MCL_TSDF_I8 = 1,  /* q = rint(d / tau * 127), int8                  */
+    MCL_TSDF_F32 = 2  /* d itself, metres, float32                      */
+} mcl_dtype;
+
+/* A dense TSDF map (§III: a voxelised truncated signed distance field; values
+ * are positive in free space, negative inside objects and clamped to the
+ * truncation band [-tau, tau]).  Voxel (i, j, k) covers the half-open box
+ * [origin + i*voxel, origin + (i+1)*voxel) per axis and holds the clamped
+ * signed distance at its centre. */
+typedef struct {
+    int32_t nx, ny, nz; /* voxels per axis, >= 1                               */
+    float voxel;        /* edge length v in metres, > 0                        */
+    float origin[3];    /* map-frame position of the min corner of voxel (0,0,0) */
+    float tau;          /* truncation distance in metres, > 0                  */
+    int32_t dtype;      /* mcl_dtype                                           */
+} mcl_map_desc;
+
+typedef struct mcl_map_s *mcl_map; /* opaque; device-resident, immutable */
+
+/* Upload a map.  host_values: HOST memory, nx*ny*nz values of the storage
+ * type, x fastest (index i + nx*(j + ny*k)).  The library copies them to the
+ * current device in its own brick layout and owns that copy; host_values may be
+ * freed when the call returns (the call synchronises `stream`).  Limit: the
+ * device copy must stay below 4 GiB.  *out receives the handle. */
+mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_values, void *stream,
+                          mcl_map *out);
+
+/* Release a map.  The caller must ensure no enqueued work still reads it. */
+mcl_status mcl_map_free(mcl_map map);
+
+/* Sensor update, endpoint model (§III, Eq. 3).  For every particle n:
+ *     logw[n] = -(1 / (2 sigma^2)) * sum_k m(x_n, z_k)^2
+ * where m(x_n, z_k) is the map value of the voxel containing the scan point z_k
+ * transformed by particle pose x_n (R p + t), and +tau for points outside the
+ * map.  This is the log of the product of Eq. (3) over the scan without its
+ * constant factor, which cancels in normalisation.
+ * The voxel of a point follows a fixed float32 recipe (round-to-nearest-even,
+ * no fused multiply-add): with inv_v = (float)(1.0 / (double)voxel),
+ *     a_jk = r_jk * inv_v,  b_j = (t_j - origin_j) * inv_v,
+ *     g_j  = ((a_j0*x + a_j1*y) + a_j2*z) + b_j,
+ * valid iff 0 <= g_j < n_j on every axis, voxel index (int)g_j.
+ * Sums of squares are accumulated in float32 in an order that depends only on
+ * K (not on N or on how the work is split), with a relative error below 3e-6.
+ *   points: device, [3][K] float32; K in [0, MCL_MAX_POINTS]; may be NULL if K = 0.
+ *   poses:  device, [12][N] float32; N in [1, MCL_MAX_PARTICLES].
+ *   sigma:  Eq. (3) standard deviation in metres, finite and > 0.
+ *   logw:   device output, [N] float32; must not overlap the inputs. */
+mcl_status mcl_sensor_update(mcl_map map, const float *points, int32_t K, const float *poses,
+                             int32_t N, float sigma, float *logw, void *stream);
+
+/* Weight normalisation (§V-A: the particle weights are summed for
+ * normalisation), float64 log-sum-exp:
+ *     log_z = max_n l_n + log sum_n exp(l_n - max l),  w_n = exp(l_n - log_z),
+ *     wq_n  = floor(w_n * 2^42)   (64-bit fixed point for an exact integer scan).
+ *   logw:  device, [N] float32, finite; N in [1, MCL_MAX_PARTICLES].
+ *   w:     device output [N] float64, or NULL.
+ *   wq:    device output [N] uint64 (required).
+ *   log_z: device output [1] float64, or NULL. */
+mcl_status mcl_normalize(const float *logw, int32_t N, double *w, uint64_t *wq, double *log_z,
+                         void *stream);
+
+/* Low-variance (systematic) resampling (§III: a new particle set is drawn from
+ * the weighted one).  With C_i = wq_0 + ... + wq_i and T = C_{N-1}, the offset
+ * is r = floor(u * T / 2^64) for the caller's uniform 64-bit draw u, and output
+ * slot m takes the particle i with N*C_{i-1} <= m*T + r < N*C_i.  Integer only:
+ * the result is exact.  T = 0 is treated as equal weights (idx[m] = m).
+ * Precondition: N * T < 2^64 (true for the output of mcl_normalize).
+ *   wq:        device, [N] uint64; N in [1, MCL_MAX_PARTICLES].
+ *   idx:       device output [N] int32, non-decreasing ancestor indices.
+ *   poses_in / poses_out: device [12][N] float32, both NULL (indices only) or
+ *              both set; poses_out[:, m] = poses_in[:, idx[m]]; no overlap. */
+mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t u, int32_t *idx,
+                        const float *poses_in, float *poses_out, void *stream);
+
+/* Test support: the voxel each (particle, point) pair reads, by the same
+ * device code as mcl_sensor_update.  lin_idx: device output [N][K] int64,
+ * i + nx*(j + ny*k), or -1 outside the map.  N*K must not exceed 2^31. */
+mcl_status mcl_debug_voxel_indices(mcl_map map, const float *points, int32_t K,
+                                   const float *poses, int32_t N, int64_t *lin_idx,
+                                   void *stream);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *mcl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCL_H */

@@ -1,0 +1,130 @@
+// TSDF map upload: dense x-fastest host array -> device brick layout + sentinels.
+#include <cmath>
+#include <new>
+
+#include "mcl_internal.h"
+
+namespace mcl {
+
+// Element e of the brick layout: brick e >> 6 = bz + nbz (bx + nbx by), value
+// e & 63 = 16 (iz & 3) + 4 (iy & 3) + (ix & 3).  Padding voxels get 0 (never read).
+template <typename T>
+__global__ __launch_bounds__(256) void brick_kernel(const T *__restrict__ dense, T *__restrict__ bricked,
+                                                    int nx, int ny, int nz, int nbx, int nbz,
+                                                    int64_t nvals) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nvals) return;
+    int64_t bi = e >> 6;
+    int w = (int)(e & 63);
+    int bz = (int)(bi % nbz);
+    int64_t r = bi / nbz;
+    int bx = (int)(r % nbx);
+    int by = (int)(r / nbx);
+    int ix = bx * 4 + (w & 3), iy = by * 4 + ((w >> 2) & 3), iz = bz * 4 + (w >> 4);
+    T v = T(0);
+    if (ix < nx && iy < ny && iz < nz) v = dense[(int64_t)ix + (int64_t)nx * ((int64_t)iy + (int64_t)ny * iz)];
+    bricked[e] = v;
+}
+
+template <typename T>
+static void fill_sentinels(char *host, T outside) {
+    *reinterpret_cast<T *>(host) = outside;          // +Q sentinel at out_off
+    *reinterpret_cast<T *>(host + 128) = T(0);       // zero sentinel at zero_off
+}
+
+}  // namespace mcl
+
+using namespace mcl;
+
+extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_values, void *stream_,
+                                     mcl_map *out) {
+    if (!desc || !host_values || !out) return fail(MCL_EINVAL, "map_upload: NULL argument");
+    *out = nullptr;
+    const mcl_map_desc &d = *desc;
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(MCL_EINVAL, "map_upload: dimensions must be >= 1");
+    if (!(std::isfinite(d.voxel) && d.voxel > 0.0f)) return fail(MCL_EINVAL, "map_upload: voxel must be finite and > 0");
+    if (!(std::isfinite(d.tau) && d.tau > 0.0f)) return fail(MCL_EINVAL, "map_upload: tau must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d.origin[a])) return fail(MCL_EINVAL, "map_upload: origin must be finite");
+    if (d.dtype < MCL_TSDF_I16 || d.dtype > MCL_TSDF_F32) return fail(MCL_EINVAL, "map_upload: unknown dtype");
+    const int es = elem_size(d.dtype);
+    const int nbx = (d.nx + 3) / 4, nby = (d.ny + 3) / 4, nbz = (d.nz + 3) / 4;
+    const int64_t nvals = (int64_t)nbx * nby * nbz * kBrickVals;
+    const int64_t data_bytes = nvals * es;
+    const int64_t total = data_bytes + 256;  // two sentinel lines
+    if (total >= ((int64_t)1 << 32)) return fail(MCL_ERANGE, "map_upload: map exceeds the 4 GiB device layout limit");
+    const int64_t cy = (int64_t)es * (16 * (int64_t)nbz * nbx - 4);
+    if (cy >= ((int64_t)1 << 24) || d.nx >= (1 << 24) || d.ny >= (1 << 24))
+        return fail(MCL_ERANGE, "map_upload: nz * nx too large for the brick addressing (need 16*nbz*nbx*esize < 2^24)");
+    const int64_t dense_vals = (int64_t)d.nx * d.ny * d.nz;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+
+    mcl_map_s *m = new (std::nothrow) mcl_map_s();
+    if (!m) return fail(MCL_ENOMEM, "map_upload: host allocation failed");
+    void *dense_dev = nullptr;
+    if (hipMalloc(&m->dev, (size_t)total) != hipSuccess) {
+        delete m;
+        return fail(MCL_ENOMEM, "map_upload: device allocation failed");
+    }
+    if (hipMalloc(&dense_dev, (size_t)(dense_vals * es)) != hipSuccess) {
+        (void)hipFree(m->dev);
+        delete m;
+        return fail(MCL_ENOMEM, "map_upload: staging allocation failed");
+    }
+    mcl_status st = MCL_OK;
+    char sent[256] = {0};
+    if (d.dtype == MCL_TSDF_I16) fill_sentinels<int16_t>(sent, (int16_t)32767);
+    else if (d.dtype == MCL_TSDF_I8) fill_sentinels<int8_t>(sent, (int8_t)127);
+    else fill_sentinels<float>(sent, d.tau);
+    if (hipMemcpyAsync(dense_dev, host_values, (size_t)(dense_vals * es), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(static_cast<char *>(m->dev) + data_bytes, sent, 256, hipMemcpyHostToDevice, stream) != hipSuccess) {
+        st = fail(MCL_EDEVICE, "map_upload: copy to device failed");
+    } else {
+        unsigned blocks = (unsigned)((nvals + 255) / 256);
+        if (d.dtype == MCL_TSDF_I16)
+            brick_kernel<int16_t><<<blocks, 256, 0, stream>>>((const int16_t *)dense_dev, (int16_t *)m->dev, d.nx, d.ny, d.nz, nbx, nbz, nvals);
+        else if (d.dtype == MCL_TSDF_I8)
+            brick_kernel<int8_t><<<blocks, 256, 0, stream>>>((const int8_t *)dense_dev, (int8_t *)m->dev, d.nx, d.ny, d.nz, nbx, nbz, nvals);
+        else
+            brick_kernel<float><<<blocks, 256, 0, stream>>>((const float *)dense_dev, (float *)m->dev, d.nx, d.ny, d.nz, nbx, nbz, nvals);
+        st = check_launch("brick_kernel");
+        if (st == MCL_OK && hipStreamSynchronize(stream) != hipSuccess) st = fail(MCL_EDEVICE, "map_upload: synchronisation failed");
+    }
+    (void)hipFree(dense_dev);
+    if (st != MCL_OK) {
+        (void)hipFree(m->dev);
+        delete m;
+        return st;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    m->device = dev;
+    m->bytes = (size_t)total;
+    m->dtype = d.dtype;
+    m->Q = d.dtype == MCL_TSDF_I16 ? 32767 : d.dtype == MCL_TSDF_I8 ? 127 : 1;
+    m->tau = d.tau;
+    m->voxel = d.voxel;
+    m->scale = d.dtype == MCL_TSDF_F32 ? 1.0 : (double)d.tau / (double)m->Q;
+    MapView &v = m->view;
+    v.base = static_cast<const char *>(m->dev);
+    v.nx = d.nx; v.ny = d.ny; v.nz = d.nz;
+    v.nbx = nbx; v.nby = nby; v.nbz = nbz;
+    v.hx = std::nextafter((float)d.nx, 0.0f);
+    v.hy = std::nextafter((float)d.ny, 0.0f);
+    v.hz = std::nextafter((float)d.nz, 0.0f);
+    v.inv_v = (float)(1.0 / (double)d.voxel);
+    v.ox = d.origin[0]; v.oy = d.origin[1]; v.oz = d.origin[2];
+    v.cx = (uint32_t)(es * (16 * nbz - 1));
+    v.cy = (uint32_t)cy;
+    v.out_off = (uint32_t)data_bytes;
+    v.zero_off = (uint32_t)(data_bytes + 128);
+    *out = m;
+    return MCL_OK;
+}
+
+extern "C" mcl_status mcl_map_free(mcl_map map) {
+    if (!map) return fail(MCL_EINVAL, "map_free: NULL map");
+    hipError_t e = hipFree(map->dev);
+    delete map;
+    return e == hipSuccess ? MCL_OK : fail(MCL_EDEVICE, "map_free: hipFree failed");
+}

@@ -1,0 +1,64 @@
+// Internal declarations of the HIP library (device layout, launch helpers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mcl.h"
+
+namespace mcl {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- map layout
+// The dense grid is padded to whole 4x4x4 bricks; one brick (64 values) is one
+// contiguous run, so a 3-D neighbourhood touches few cache lines (an int16
+// brick is one 128-byte line).  Bricks are ordered z fastest, then x, then y
+// (maps are flat: nz is the short axis), which keeps every address coefficient
+// below 2^24 for 24-bit multiplies.  Two sentinel cells follow the bricks: +Q
+// (read by points outside the map) and 0 (read by padding lanes past the end
+// of a scan, contributing nothing).
+constexpr int kBrickLog2 = 2;
+constexpr int kBrickVals = 64;
+
+struct MapView {
+    const char *base;        // device: bricked values, then the sentinels
+    int32_t nx, ny, nz;      // true dimensions
+    int32_t nbx, nby, nbz;   // bricks per axis
+    float hx, hy, hz;        // largest float below nx, ny, nz (bounds test)
+    float inv_v;             // (float)(1.0 / (double)voxel)
+    float ox, oy, oz;        // origin
+    uint32_t cx, cy;         // ESIZE (16 nbz - 1), ESIZE (16 nbz nbx - 4)
+    uint32_t out_off;        // byte offset of the +Q sentinel
+    uint32_t zero_off;       // byte offset of the 0 sentinel
+};
+
+}  // namespace mcl
+
+struct mcl_map_s {
+    mcl::MapView view;
+    void *dev;          // allocation holding bricks + sentinels
+    size_t bytes;
+    int device;
+    int32_t dtype;
+    int32_t Q;          // 32767, 127 or 1
+    float tau;
+    float voxel;
+    double scale;       // metres per stored unit: tau / Q, or 1 for float32
+};
+
+namespace mcl {
+
+// thread-local last error
+void set_error(const std::string &msg);
+mcl_status fail(mcl_status code, const std::string &msg);
+mcl_status check_launch(const char *what);
+
+// Workspace per stream, grown on demand (never shrinks until unload).
+void *workspace(hipStream_t stream, size_t bytes);
+
+inline int elem_size(int32_t dtype) { return dtype == MCL_TSDF_I16 ? 2 : dtype == MCL_TSDF_I8 ? 1 : 4; }
+
+}  // namespace mcl

@@ -1,0 +1,211 @@
+// Sensor update (§III, Eq. 3, endpoint model): for every particle, transform
+// every scan point by the particle pose, read the TSDF value of the voxel that
+// holds it, and sum the squared values; l_n = -c * sum, c = s^2 / (2 sigma^2).
+//
+// Work decomposition (gfx950, 64-lane waves):
+//  * a wave owns a group of up to 64 particles; lane p keeps particle p's pose
+//    constants in 12 registers and its running sum;
+//  * the scan is cut into chunks of 1024 points; a wave loads a chunk into
+//    registers (16 points per lane, lane l holding points l, l+64, ...), then for
+//    each particle of its group broadcasts that pose to scalar registers and
+//    evaluates the 16 points of every lane: 16 independent gathers in flight;
+//  * neighbouring lanes hold neighbouring beams, so one wave-wide gather touches
+//    few 128-byte brick lines;
+//  * a chunk's 64 lane sums are reduced across the wave by a fixed butterfly;
+//  * the scan is also split into pieces of 4 chunks (4096 points) so small
+//    particle counts still fill the GPU; pieces are combined pairwise.
+// The summation order is a function of K only (lane partials of 16 terms,
+// 6-level wave tree, 4 chunks per piece in order, pairwise over pieces): the
+// same particle gives the same bits whatever N, grid or batch it runs in.
+#include "voxel.h"
+
+namespace mcl {
+
+constexpr int kU = 16;                          // points per lane per chunk
+constexpr int kChunk = kWave * kU;              // 1024
+constexpr int kChunksPerPiece = 4;
+constexpr int kPiece = kChunk * kChunksPerPiece;  // 4096 points
+constexpr int kGroup = 64;                      // particles per wave
+constexpr int kWavesPerBlock = 4;
+
+__device__ inline float bcast(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+// Butterfly sum over the 64 lanes.  Every step adds the values of lane pairs
+// (l, l^d); IEEE addition is commutative, so both lanes of a pair hold the same
+// bits after each step and all lanes end with the same total.
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    return x;
+}
+
+template <typename T>
+__device__ inline float load_val(const char *base, uint32_t off) {
+    return (float)*reinterpret_cast<const T *>(base + off);
+}
+
+// Lane partial sum of one particle (pose in A) over this lane's kU points.
+template <typename T, bool TAIL>
+__device__ inline float lane_chunk_sum(const MapView &m, const float (&A)[12], const float (&px)[kU],
+                                       const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid) {
+    uint32_t off[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        float gx = grid_coord(A[0], A[1], A[2], A[9], px[u], py[u], pz[u]);
+        float gy = grid_coord(A[3], A[4], A[5], A[10], px[u], py[u], pz[u]);
+        float gz = grid_coord(A[6], A[7], A[8], A[11], px[u], py[u], pz[u]);
+        uint32_t o = voxel_offset<sizeof(T)>(m, gx, gy, gz);
+        if (TAIL) o = (u * kWave + lane < nvalid) ? o : m.zero_off;
+        off[u] = o;
+    }
+    float v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = load_val<T>(m.base, off[u]);
+    // keep all kU gathers in flight before the first use
+    __builtin_amdgcn_sched_barrier(0);
+    float s = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) s = __builtin_fmaf(v[u], v[u], s);
+    return s;
+}
+
+template <typename T, bool TAIL>
+__device__ inline void chunk_group(const MapView &m, const float (&pa)[12], const float (&px)[kU],
+                                   const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
+                                   int gcount, float &acc) {
+    for (int p = 0; p < gcount; ++p) {
+        float A[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) A[j] = bcast(pa[j], p);
+        float t = wave_sum(lane_chunk_sum<T, TAIL>(m, A, px, py, pz, lane, nvalid));
+        if (lane == p) acc += t;
+    }
+}
+
+// out: logw (npiece == 1) or piece partial sums [npiece][N].
+template <typename T>
+__global__ __launch_bounds__(256) void sensor_kernel(MapView m, const float *__restrict__ pts, int K,
+                                                     const float *__restrict__ poses, int N, float c,
+                                                     float *__restrict__ out, int npiece, int nitems) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (item >= nitems) return;
+    const int group = item / npiece;
+    const int piece = item - group * npiece;
+    const int n0 = group * kGroup;
+    const int gcount = min(kGroup, N - n0);
+
+    float pa[12];
+    pose_consts(poses, N, n0 + min(lane, gcount - 1), m, pa);
+
+    float acc = 0.0f;
+    const int kb = piece * kPiece;
+    const int ke = min(K, kb + kPiece);
+    for (int kc = kb; kc < ke; kc += kChunk) {
+        const int nvalid = min(kChunk, ke - kc);
+        float px[kU], py[kU], pz[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            int k = min(kc + u * kWave + lane, ke - 1);  // padding slots are masked later
+            px[u] = pts[k];
+            py[u] = pts[(size_t)K + k];
+            pz[u] = pts[(size_t)2 * K + k];
+        }
+        if (nvalid == kChunk)
+            chunk_group<T, false>(m, pa, px, py, pz, lane, nvalid, gcount, acc);
+        else
+            chunk_group<T, true>(m, pa, px, py, pz, lane, nvalid, gcount, acc);
+    }
+    if (lane < gcount) {
+        if (npiece == 1)
+            out[n0 + lane] = -(acc * c);
+        else
+            out[(size_t)piece * N + n0 + lane] = acc;
+    }
+}
+
+// Pairwise sum of the piece partials in a fixed tree (a binary counter over the
+// pieces in order), then l = -(S * c).
+__global__ __launch_bounds__(256) void combine_kernel(const float *__restrict__ part, int npiece, int N,
+                                                      float c, float *__restrict__ logw) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float stack[12];
+    int depth = 0;
+    for (int j = 0; j < npiece; ++j) {
+        float v = part[(size_t)j * N + n];
+        for (int t = j + 1; (t & 1) == 0; t >>= 1) v = stack[--depth] + v;
+        stack[depth++] = v;
+    }
+    float s = stack[--depth];
+    while (depth > 0) s = stack[--depth] + s;
+    logw[n] = -(s * c);
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ out, int n, float v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+__global__ __launch_bounds__(256) void debug_index_kernel(MapView m, const float *__restrict__ pts, int K,
+                                                          const float *__restrict__ poses, int N,
+                                                          int64_t *__restrict__ lin) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)N * K) return;
+    int n = (int)(id / K), k = (int)(id - (int64_t)n * K);
+    float pa[12];
+    pose_consts(poses, N, n, m, pa);
+    float x = pts[k], y = pts[(size_t)K + k], z = pts[(size_t)2 * K + k];
+    float gx = grid_coord(pa[0], pa[1], pa[2], pa[9], x, y, z);
+    float gy = grid_coord(pa[3], pa[4], pa[5], pa[10], x, y, z);
+    float gz = grid_coord(pa[6], pa[7], pa[8], pa[11], x, y, z);
+    uint32_t ix, iy, iz;
+    bool ok = voxel_ijk(m, gx, gy, gz, ix, iy, iz);
+    lin[id] = ok ? (int64_t)ix + (int64_t)m.nx * ((int64_t)iy + (int64_t)m.ny * iz) : -1;
+}
+
+// ------------------------------------------------------------------ host side
+int sensor_pieces(int K) { return K <= 0 ? 1 : (K + kPiece - 1) / kPiece; }
+
+mcl_status launch_sensor(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
+                         float *logw, hipStream_t stream) {
+    if (K == 0) {
+        fill_kernel<<<(N + 255) / 256, 256, 0, stream>>>(logw, N, -0.0f * c);
+        return check_launch("fill_kernel");
+    }
+    const int npiece = sensor_pieces(K);
+    const int ngroups = (N + kGroup - 1) / kGroup;
+    const int nitems = ngroups * npiece;
+    const int blocks = (nitems + kWavesPerBlock - 1) / kWavesPerBlock;
+    float *out = logw;
+    if (npiece > 1) {
+        out = static_cast<float *>(workspace(stream, (size_t)npiece * N * sizeof(float)));
+        if (!out) return fail(MCL_ENOMEM, "sensor_update: workspace allocation failed");
+    }
+    switch (map->dtype) {
+        case MCL_TSDF_I16:
+            sensor_kernel<int16_t><<<blocks, 256, 0, stream>>>(map->view, pts, K, poses, N, c, out, npiece, nitems);
+            break;
+        case MCL_TSDF_I8:
+            sensor_kernel<int8_t><<<blocks, 256, 0, stream>>>(map->view, pts, K, poses, N, c, out, npiece, nitems);
+            break;
+        default:
+            sensor_kernel<float><<<blocks, 256, 0, stream>>>(map->view, pts, K, poses, N, c, out, npiece, nitems);
+    }
+    mcl_status st = check_launch("sensor_kernel");
+    if (st != MCL_OK || npiece == 1) return st;
+    combine_kernel<<<(N + 255) / 256, 256, 0, stream>>>(out, npiece, N, c, logw);
+    return check_launch("combine_kernel");
+}
+
+mcl_status launch_debug_indices(const mcl_map_s *map, const float *pts, int K, const float *poses, int N,
+                                int64_t *lin, hipStream_t stream) {
+    int64_t total = (int64_t)N * K;
+    if (total == 0) return MCL_OK;
+    debug_index_kernel<<<(unsigned)((total + 255) / 256), 256, 0, stream>>>(map->view, pts, K, poses, N, lin);
+    return check_launch("debug_index_kernel");
+}
+
+}  // namespace mcl

@@ -1,0 +1,187 @@
+"""Python binding of libmcl.so: argument marshalling only.
+
+Every step of the sensor update, normalisation and resampling runs in the HIP
+kernels behind the C ABI (include/mcl.h).  torch supplies device memory and
+streams.  If the built library is missing this module raises at import: there
+is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmcl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2310_04172_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+_P = C.c_void_p
+_I = C.c_int32
+
+MCL_OK, MCL_EINVAL, MCL_ENOMEM, MCL_EDEVICE, MCL_ERANGE = 0, -1, -2, -3, -4
+MAX_PARTICLES = 1 << 21
+MAX_POINTS = 1 << 20
+WQ_SHIFT = 42
+DTYPE_CODE = {"i16": 0, "i8": 1, "f32": 2}
+
+
+class MapDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("voxel", C.c_float),
+                ("origin", C.c_float * 3), ("tau", C.c_float), ("dtype", C.c_int32)]
+
+
+_lib.mcl_map_upload.argtypes = [C.POINTER(MapDesc), _P, _P, C.POINTER(_P)]
+_lib.mcl_map_free.argtypes = [_P]
+_lib.mcl_sensor_update.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
+_lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
+_lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, _P, _P, _P, _P]
+_lib.mcl_debug_voxel_indices.argtypes = [_P, _P, _I, _P, _I, _P, _P]
+_lib.mcl_last_error.restype = C.c_char_p
+for _f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
+           "mcl_debug_voxel_indices"):
+    getattr(_lib, _f).restype = C.c_int32
+
+
+class MclError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = _lib.mcl_last_error().decode()
+        super().__init__(f"{what} failed with status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int, what: str):
+    if status != MCL_OK:
+        raise MclError(status, what)
+
+
+def lib():
+    return _lib
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Map:
+    """A TSDF map resident in device memory (library-owned brick layout)."""
+
+    def __init__(self, values: np.ndarray, voxel: float, origin, tau: float, dtype: str, stream=None):
+        vals = np.ascontiguousarray(values)
+        nz, ny, nx = vals.shape
+        d = MapDesc(nx, ny, nz, float(voxel), (C.c_float * 3)(*[float(o) for o in origin]), float(tau),
+                    DTYPE_CODE[dtype])
+        h = _P()
+        _check(_lib.mcl_map_upload(C.byref(d), vals.ctypes.data_as(_P), _stream(stream), C.byref(h)),
+               "mcl_map_upload")
+        self._h = h
+        self.dims = (nx, ny, nz)
+        self.dtype = dtype
+        self.voxel, self.tau = float(voxel), float(tau)
+
+    @classmethod
+    def from_tsdf(cls, tmap, stream=None) -> "Map":
+        return cls(tmap.values, tmap.voxel, tmap.origin, tmap.tau, tmap.dtype, stream)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mcl_map_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sensor_update(m: Map, points, poses, sigma: float, logw=None, stream=None):
+    """logw [N] float32 = -(1/(2 sigma^2)) sum_k m(x_n, z_k)^2 (see include/mcl.h)."""
+    import torch
+    K = points.shape[1] if points is not None else 0
+    N = poses.shape[1]
+    _dev(poses, torch.float32, (12, N), "poses")
+    if K:
+        _dev(points, torch.float32, (3, K), "points")
+    if logw is None:
+        logw = torch.empty(N, dtype=torch.float32, device=poses.device)
+    _dev(logw, torch.float32, (N,), "logw")
+    _check(_lib.mcl_sensor_update(m.handle, _ptr(points) if K else None, K, _ptr(poses), N,
+                                  float(sigma), _ptr(logw), _stream(stream)), "mcl_sensor_update")
+    return logw
+
+
+def normalize(logw, w=None, wq=None, log_z=None, want_w=True, stream=None):
+    """(w float64 [N] or None, wq uint64 [N], log_z float64 [1])."""
+    import torch
+    N = logw.shape[0]
+    _dev(logw, torch.float32, (N,), "logw")
+    dev = logw.device
+    if w is None and want_w:
+        w = torch.empty(N, dtype=torch.float64, device=dev)
+    if wq is None:
+        wq = torch.empty(N, dtype=torch.uint64, device=dev)
+    if log_z is None:
+        log_z = torch.empty(1, dtype=torch.float64, device=dev)
+    _check(_lib.mcl_normalize(_ptr(logw), N, _ptr(w), _ptr(wq), _ptr(log_z), _stream(stream)), "mcl_normalize")
+    return w, wq, log_z
+
+
+def resample(wq, u: int, poses_in=None, poses_out=None, idx=None, stream=None):
+    """(idx int32 [N], poses_out [12, N] or None)."""
+    import torch
+    N = wq.shape[0]
+    _dev(wq, torch.uint64, (N,), "wq")
+    if idx is None:
+        idx = torch.empty(N, dtype=torch.int32, device=wq.device)
+    if poses_in is not None and poses_out is None:
+        poses_out = torch.empty_like(poses_in)
+    _check(_lib.mcl_resample(_ptr(wq), N, C.c_uint64(int(u) & (2 ** 64 - 1)), _ptr(idx), _ptr(poses_in),
+                             _ptr(poses_out), _stream(stream)), "mcl_resample")
+    return idx, poses_out
+
+
+def debug_voxel_indices(m: Map, points, poses, out=None, stream=None):
+    import torch
+    K, N = points.shape[1], poses.shape[1]
+    if out is None:
+        out = torch.empty((N, K), dtype=torch.int64, device=poses.device)
+    _check(_lib.mcl_debug_voxel_indices(m.handle, _ptr(points), K, _ptr(poses), N, _ptr(out), _stream(stream)),
+           "mcl_debug_voxel_indices")
+    return out
+
+
+def score_const(m: Map, sigma: float) -> float:
+    """c = s^2 / (2 sigma^2) as the library computes it (float64, rounded to float32)."""
+    Q = {"i16": 32767, "i8": 127, "f32": 1}[m.dtype]
+    s = 1.0 if m.dtype == "f32" else float(np.float32(m.tau)) / Q
+    sg = float(np.float32(sigma))
+    return float(np.float32((s * s) / (2.0 * sg * sg)))

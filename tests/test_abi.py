@@ -1,0 +1,61 @@
+"""The C-ABI library: it loads, exports every symbol the header declares, and
+rejects bad arguments on the host before touching the device (no GPU needed)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcl.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcl_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def mcl():
+    from paper_2310_04172_amd import mcl as m
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
+              "mcl_debug_voxel_indices", "mcl_last_error"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(mcl):
+    lib = mcl.lib()
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_argument_errors_are_reported_on_the_host(mcl):
+    lib = mcl.lib()
+    P = C.c_void_p
+    fake = P(0x1000)
+    # NULL map / pointers, bad sizes, bad sigma: rejected before any device work
+    assert lib.mcl_sensor_update(None, fake, 10, fake, 10, 0.1, P(0x2000), None) == mcl.MCL_EINVAL
+    assert b"NULL map" in lib.mcl_last_error()
+    assert lib.mcl_normalize(None, 10, None, fake, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_normalize(fake, 0, None, P(0x9000), None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_normalize(fake, mcl.MAX_PARTICLES + 1, None, P(0x90000000), None, None) == mcl.MCL_ERANGE
+    assert lib.mcl_resample(fake, 10, 0, P(0x9000), fake, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_resample(fake, 0, 0, P(0x9000), None, None, None) == mcl.MCL_EINVAL
+    # overlapping output and input
+    assert lib.mcl_normalize(P(0x10000), 100, None, P(0x10010), None, None) == mcl.MCL_EINVAL
+    d = mcl.MapDesc(0, 4, 4, 0.1, (C.c_float * 3)(0, 0, 0), 0.3, 0)
+    h = P()
+    assert lib.mcl_map_upload(C.byref(d), fake, None, C.byref(h)) == mcl.MCL_EINVAL
+    d = mcl.MapDesc(4, 4, 4, -0.1, (C.c_float * 3)(0, 0, 0), 0.3, 0)
+    assert lib.mcl_map_upload(C.byref(d), fake, None, C.byref(h)) == mcl.MCL_EINVAL
+    d = mcl.MapDesc(4, 4, 4, 0.1, (C.c_float * 3)(0, 0, 0), 0.3, 7)
+    assert lib.mcl_map_upload(C.byref(d), fake, None, C.byref(h)) == mcl.MCL_EINVAL
+    d = mcl.MapDesc(65536, 65536, 4096, 0.1, (C.c_float * 3)(0, 0, 0), 0.3, 0)
+    assert lib.mcl_map_upload(C.byref(d), fake, None, C.byref(h)) == mcl.MCL_ERANGE

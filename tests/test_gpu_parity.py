@@ -1,0 +1,253 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: voxel indices and resampled indices bit-exact; log-weights within 1e-5
+relative of the float64 / exact-integer oracle; normalised weights within a few
+ulps of the oracle run on the GPU's own log-weights.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from tests.helpers import identity_poses, make_map, poses_from, random_rotations
+from workloads import configs
+from workloads.tsdf import f32
+
+pytestmark = pytest.mark.gpu
+
+RTOL_LOGW = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "a GPU is required"
+    return t
+
+
+@pytest.fixture(scope="module")
+def mcl():
+    from paper_2310_04172_amd import mcl as m
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_logw(torch, mcl, tmap, pts, poses, sigma):
+    m = mcl.Map.from_tsdf(tmap)
+    lw = mcl.sensor_update(m, dev(torch, pts), dev(torch, poses), sigma)
+    torch.cuda.synchronize()
+    return lw.cpu().numpy()
+
+
+def assert_logw_close(gpu, ref, what=""):
+    ref = np.asarray(ref, np.float64)
+    err = np.abs(gpu.astype(np.float64) - ref)
+    bad = err > RTOL_LOGW * np.abs(ref)
+    assert not bad.any(), f"{what}: {bad.sum()} particles off, worst rel {np.max(err / np.maximum(np.abs(ref), 1e-300))}"
+
+
+# ------------------------------------------------------------- sensor update
+def test_identity_pose_bit_exact(torch, mcl, oracle_lib):
+    """Small |q| keeps every float32 partial sum exact: the GPU must reproduce
+    -(S * c) bit for bit."""
+    say("case: identity pose closed form")
+    rng = np.random.default_rng(5)
+    nx, ny, nz, v = 12, 10, 9, 0.125
+    vals = rng.integers(-64, 65, size=(nz, ny, nx)).astype(np.int16)
+    tmap = make_map(vals, v, tau=0.3)
+    K = 3000
+    ii, jj, kk = rng.integers(0, nx, K), rng.integers(0, ny, K), rng.integers(0, nz, K)
+    pts = ((np.stack([ii, jj, kk]).astype(np.float64) + 0.5) * v).astype(np.float32)
+    sigma = f32(0.1)
+    lw = gpu_logw(torch, mcl, tmap, pts, identity_poses(3), sigma)
+    S = sum(int(q) ** 2 for q in vals[kk, jj, ii])
+    assert S < 2 ** 24
+    m = mcl.Map.from_tsdf(tmap)
+    c = np.float32(mcl.score_const(m, sigma))
+    expect = -(np.float32(S) * c)
+    assert np.all(lw == expect)
+
+
+def random_case(seed, dims, N, K, dtype="i16", v=0.1):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = dims[2], dims[1], dims[0]
+    if dtype == "f32":
+        vals = rng.uniform(-0.3, 0.3, size=(nz, ny, nx)).astype(np.float32)
+    else:
+        lim = 32767 if dtype == "i16" else 127
+        vals = rng.integers(-lim, lim + 1, size=(nz, ny, nx)).astype(np.int16 if dtype == "i16" else np.int8)
+    tmap = make_map(vals, v, origin=(-0.2, 0.1, -0.05), tau=0.3, dtype=dtype)
+    ext = np.array(dims) * v
+    poses = poses_from(random_rotations(rng, N), rng.uniform(0, 1, (N, 3)) * ext)
+    pts = rng.normal(0, 0.4 * ext.mean(), size=(3, K)).astype(np.float32)
+    return tmap, pts, poses
+
+
+@pytest.mark.parametrize("N,K", [(1, 1), (1, 63), (63, 1000), (65, 1025), (130, 4097), (7, 9000), (200, 64)])
+@pytest.mark.parametrize("dtype", ["i16", "i8", "f32"])
+def test_ragged_sizes(torch, mcl, oracle_lib, N, K, dtype):
+    say(f"case: ragged N={N} K={K} dtype={dtype}")
+    tmap, pts, poses = random_case(N * 131 + K, (21, 18, 13), N, K, dtype)
+    lw = gpu_logw(torch, mcl, tmap, pts, poses, f32(0.15))
+    ref = oracle_lib.sensor_update(tmap, pts, poses, f32(0.15))
+    assert_logw_close(lw, ref, f"N={N} K={K} {dtype}")
+
+
+def test_empty_scan(torch, mcl):
+    say("case: K=0")
+    tmap, pts, poses = random_case(1, (8, 8, 8), 100, 5)
+    m = mcl.Map.from_tsdf(tmap)
+    lw = mcl.sensor_update(m, None, dev(torch, poses), f32(0.1))
+    assert np.all(lw.cpu().numpy() == 0.0)
+
+
+def test_voxel_indices_bit_exact_random(torch, mcl, oracle_lib):
+    say("case: debug indices random")
+    tmap, pts, poses = random_case(77, (37, 29, 11), 150, 2000)
+    # exact face and special values too
+    extra = np.array([[0.0, -0.0, np.nan, np.inf, -np.inf, 1e30, 3.7e-3],
+                      [0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -2.5e-2],
+                      [0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0]], np.float32)
+    pts = np.ascontiguousarray(np.hstack([pts, extra]))
+    m = mcl.Map.from_tsdf(tmap)
+    got = mcl.debug_voxel_indices(m, dev(torch, pts), dev(torch, poses)).cpu().numpy()
+    ref = oracle_lib.voxel_indices(tmap, pts, poses)
+    assert np.array_equal(got, ref)
+    assert 0.05 < np.mean(ref >= 0) < 0.95
+
+
+def test_permutation_and_determinism(torch, mcl):
+    """Bit-identical results for the same particle whatever its slot, N or run."""
+    say("case: determinism")
+    tmap, pts, poses = random_case(9, (40, 40, 20), 300, 9000)
+    m = mcl.Map.from_tsdf(tmap)
+    P = dev(torch, poses)
+    X = dev(torch, pts)
+    a = mcl.sensor_update(m, X, P, f32(0.2)).cpu().numpy()
+    b = mcl.sensor_update(m, X, P, f32(0.2)).cpu().numpy()
+    assert np.array_equal(a, b)
+    perm = np.random.default_rng(0).permutation(300)
+    c = mcl.sensor_update(m, X, dev(torch, poses[:, perm]), f32(0.2)).cpu().numpy()
+    assert np.array_equal(c, a[perm])
+    d = mcl.sensor_update(m, X, dev(torch, poses[:, 17:18]), f32(0.2)).cpu().numpy()
+    assert d[0] == a[17]
+
+
+# --------------------------------------------------------- workload configs
+@pytest.fixture(scope="module")
+def cfg1():
+    return configs.config1()
+
+
+def test_config1_full(torch, mcl, oracle_lib, cfg1):
+    w = cfg1
+    say(f"case: plain-small all particles N={w.N} K={w.K}")
+    lw = gpu_logw(torch, mcl, w.tmap, w.points, w.poses, w.sigma)
+    ref = oracle_lib.sensor_update(w.tmap, w.points, w.poses, w.sigma)
+    assert_logw_close(lw, ref, "config1")
+    m = mcl.Map.from_tsdf(w.tmap)
+    got = mcl.debug_voxel_indices(m, dev(torch, w.points), dev(torch, w.poses)).cpu().numpy()
+    assert np.array_equal(got, oracle_lib.voxel_indices(w.tmap, w.points, w.poses))
+
+
+def full_chain(torch, mcl, w):
+    m = mcl.Map.from_tsdf(w.tmap)
+    P = dev(torch, w.poses)
+    lw = mcl.sensor_update(m, dev(torch, w.points), P, w.sigma)
+    wt, wq, lz = mcl.normalize(lw)
+    idx, pout = mcl.resample(wq, w.u, P)
+    torch.cuda.synchronize()
+    return (lw.cpu().numpy(), wt.cpu().numpy(), wq.cpu().numpy(), float(lz.cpu().numpy()[0]),
+            idx.cpu().numpy(), pout.cpu().numpy())
+
+
+def check_weights(oracle_lib, lw, wt, wq, lz, idx, pout, poses, u):
+    """Normalisation within ulps of the oracle run on the GPU's log-weights;
+    resampling bit-exact given the GPU's fixed-point weights."""
+    w_ref, wq_ref, lz_ref = oracle_lib.normalize(lw.astype(np.float64))
+    assert abs(lz - lz_ref) <= 8 * np.spacing(abs(lz_ref)) + 1e-300
+    np.testing.assert_allclose(wt, w_ref, rtol=1e-12, atol=1e-300)
+    diff = np.abs(wq.astype(np.int64) - wq_ref.astype(np.int64))
+    assert np.all(diff <= 1 + 1e-10 * wq_ref.astype(np.float64))
+    idx_ref = oracle_lib.resample(wq, u)
+    assert np.array_equal(idx, idx_ref)
+    assert np.array_equal(pout, poses[:, idx_ref])
+
+
+def test_config1_chain(torch, mcl, oracle_lib, cfg1):
+    w = cfg1
+    say("case: plain-small chain")
+    lw, wt, wq, lz, idx, pout = full_chain(torch, mcl, w)
+    check_weights(oracle_lib, lw, wt, wq, lz, idx, pout, w.poses, w.u)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return configs.config2()
+
+
+def test_config2_full_size_sampled(torch, mcl, oracle_lib, cfg2):
+    """The global-localisation workload at full size (N = 10^6, the benchmark's
+    launch): a seeded 4,096-particle subset of the log-weights against the oracle,
+    and the whole normalise + resample chain."""
+    w = cfg2
+    say(f"case: plain-global full size N={w.N} K={w.K}")
+    lw, wt, wq, lz, idx, pout = full_chain(torch, mcl, w)
+    sub = configs.subset_indices(2, w.N)
+    ref = oracle_lib.sensor_update(w.tmap, w.points, np.ascontiguousarray(w.poses[:, sub]), w.sigma, nthreads=8)
+    assert_logw_close(lw[sub], ref, "config2 subset")
+    check_weights(oracle_lib, lw, wt, wq, lz, idx, pout, w.poses, w.u)
+    # voxel indices of 32 sampled particles, bit for bit
+    m = mcl.Map.from_tsdf(w.tmap)
+    ps = np.ascontiguousarray(w.poses[:, sub[:32]])
+    got = mcl.debug_voxel_indices(m, dev(torch, w.points), dev(torch, ps)).cpu().numpy()
+    assert np.array_equal(got, oracle_lib.voxel_indices(w.tmap, w.points, ps))
+
+
+@pytest.mark.parametrize("dtype", ["i16", "i8", "f32"])
+def test_config3_sampled(torch, mcl, oracle_lib, dtype):
+    w = configs.config3(dtype=dtype)
+    say(f"case: precision {dtype} full size N={w.N} K={w.K}")
+    lw = gpu_logw(torch, mcl, w.tmap, w.points, w.poses, w.sigma)
+    sub = configs.subset_indices(3, w.N, 1024)
+    ref = oracle_lib.sensor_update(w.tmap, w.points, np.ascontiguousarray(w.poses[:, sub]), w.sigma, nthreads=8)
+    assert_logw_close(lw[sub], ref, f"config3 {dtype}")
+
+
+# ------------------------------------------------------------ weights edges
+def test_normalize_resample_edges(torch, mcl, oracle_lib):
+    say("case: weight edge cases")
+    rng = np.random.default_rng(3)
+    for N in (1, 2, 4095, 4096, 4097, 70001):
+        lw = (-np.abs(rng.normal(0, 300, N)) - 1e4).astype(np.float32)
+        wt, wq, lz = mcl.normalize(dev(torch, lw))
+        wt, wq, lz = wt.cpu().numpy(), wq.cpu().numpy(), float(lz.cpu().numpy()[0])
+        idx, _ = mcl.resample(dev(torch, wq), 0xDEADBEEF12345678)
+        w_ref, wq_ref, lz_ref = oracle_lib.normalize(lw.astype(np.float64))
+        np.testing.assert_allclose(wt, w_ref, rtol=1e-12, atol=1e-300)
+        assert np.array_equal(idx.cpu().numpy(), oracle_lib.resample(wq, 0xDEADBEEF12345678))
+    # all-zero fixed-point weights: equal weights, identity
+    N = 5000
+    idx, _ = mcl.resample(dev(torch, np.zeros(N, np.uint64)), 12345)
+    assert np.array_equal(idx.cpu().numpy(), np.arange(N))
+    # one dominating particle
+    lw = np.full(N, -1e5, np.float32)
+    lw[4321] = -10.0
+    wt, wq, lz = mcl.normalize(dev(torch, lw))
+    assert wq.cpu().numpy()[4321] == 2 ** 42 and int(wq.cpu().numpy().sum()) == 2 ** 42
+    idx, _ = mcl.resample(wq, 2 ** 64 - 1)
+    assert np.all(idx.cpu().numpy() == 4321)
+    # largest N
+    N = mcl.MAX_PARTICLES
+    wq = dev(torch, np.full(N, 2 ** 21, np.uint64))
+    idx, _ = mcl.resample(wq, 2 ** 64 - 1)
+    assert np.array_equal(idx.cpu().numpy(), np.arange(N))
