@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is a design "
@@ -124,6 +126,15 @@ def main():
     algo_bytes = evals * 2 + N * (48 + 4) + K * 12   # int16 TSDF read per eval, pose in, logw out, scan
     achieved = algo_bytes / (sensor_ms * 1e-3) / 1e9
     log(f"step {ms_step:.3f} ms, sensor kernel {sensor_ms:.3f} ms")
+    if args.copy_calib_mib:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.copy_calib_mib} MiB read + {args.copy_calib_mib} MiB written")
+        del src, dst
 
     out = {
         "metric": "particle-point evals/s (G/s), plain single-filter global localisation",

@@ -26,10 +26,33 @@ __global__ __launch_bounds__(256) void brick_kernel(const T *__restrict__ dense,
     bricked[e] = v;
 }
 
+// Class byte of every brick: kClassTrunc if all its voxels inside the map
+// hold +-Q (padding voxels beyond the map are ignored), else kClassMixed.
 template <typename T>
-static void fill_sentinels(char *host, T outside) {
-    *reinterpret_cast<T *>(host) = outside;          // +Q sentinel at out_off
-    *reinterpret_cast<T *>(host + 128) = T(0);       // zero sentinel at zero_off
+__global__ __launch_bounds__(256) void brick_class_kernel(const T *__restrict__ bricked, uint8_t *__restrict__ cls,
+                                                          int nx, int ny, int nz, int nbx, int nbz, int64_t nbricks,
+                                                          T qpos, T qneg) {
+    int64_t bi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= nbricks) return;
+    int bz = (int)(bi % nbz);
+    int64_t r = bi / nbz;
+    int bx = (int)(r % nbx);
+    int by = (int)(r / nbx);
+    const T *b = bricked + bi * 64;
+    bool trunc = true;
+    for (int w = 0; w < 64; ++w) {
+        int ix = bx * 4 + (w & 3), iy = by * 4 + ((w >> 2) & 3), iz = bz * 4 + (w >> 4);
+        if (ix < nx && iy < ny && iz < nz) trunc &= (b[w] == qpos) | (b[w] == qneg);
+    }
+    cls[bi] = trunc ? kClassTrunc : kClassMixed;
+}
+
+template <typename T>
+static void fill_sentinels(char *host, T outside, int es) {
+    for (int w = 0; w < 64; ++w) {
+        reinterpret_cast<T *>(host)[w] = outside;          // +Q sentinel brick at out_off
+        reinterpret_cast<T *>(host + 64 * es)[w] = T(0);  // zero sentinel brick at zero_off
+    }
 }
 
 }  // namespace mcl
@@ -51,7 +74,10 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     const int nbx = (d.nx + 3) / 4, nby = (d.ny + 3) / 4, nbz = (d.nz + 3) / 4;
     const int64_t nvals = (int64_t)nbx * nby * nbz * kBrickVals;
     const int64_t data_bytes = nvals * es;
-    const int64_t total = data_bytes + 256;  // two sentinel lines
+    const int64_t nbricks = nvals / kBrickVals;
+    const int64_t sent_bytes = 128 * es;                           // two sentinel bricks
+    const int64_t cls_off = (data_bytes + sent_bytes + 255) / 256 * 256;
+    const int64_t total = cls_off + (nbricks + 2 + 255) / 256 * 256;
     if (total >= ((int64_t)1 << 32)) return fail(MCL_ERANGE, "map_upload: map exceeds the 4 GiB device layout limit");
     const int64_t cy = (int64_t)es * (16 * (int64_t)nbz * nbx - 4);
     if (cy >= ((int64_t)1 << 24) || d.nx >= (1 << 24) || d.ny >= (1 << 24))
@@ -72,12 +98,16 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
         return fail(MCL_ENOMEM, "map_upload: staging allocation failed");
     }
     mcl_status st = MCL_OK;
-    char sent[256] = {0};
-    if (d.dtype == MCL_TSDF_I16) fill_sentinels<int16_t>(sent, (int16_t)32767);
-    else if (d.dtype == MCL_TSDF_I8) fill_sentinels<int8_t>(sent, (int8_t)127);
-    else fill_sentinels<float>(sent, d.tau);
+    char sent[512] = {0};
+    if (d.dtype == MCL_TSDF_I16) fill_sentinels<int16_t>(sent, (int16_t)32767, es);
+    else if (d.dtype == MCL_TSDF_I8) fill_sentinels<int8_t>(sent, (int8_t)127, es);
+    else fill_sentinels<float>(sent, d.tau, es);
+    const uint8_t sent_cls[2] = {kClassTrunc, kClassZero};
+    char *base = static_cast<char *>(m->dev);
+    uint8_t *cls = reinterpret_cast<uint8_t *>(base + cls_off);
     if (hipMemcpyAsync(dense_dev, host_values, (size_t)(dense_vals * es), hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(static_cast<char *>(m->dev) + data_bytes, sent, 256, hipMemcpyHostToDevice, stream) != hipSuccess) {
+        hipMemcpyAsync(base + data_bytes, sent, (size_t)sent_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(cls + nbricks, sent_cls, 2, hipMemcpyHostToDevice, stream) != hipSuccess) {
         st = fail(MCL_EDEVICE, "map_upload: copy to device failed");
     } else {
         unsigned blocks = (unsigned)((nvals + 255) / 256);
@@ -88,6 +118,16 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
         else
             brick_kernel<float><<<blocks, 256, 0, stream>>>((const float *)dense_dev, (float *)m->dev, d.nx, d.ny, d.nz, nbx, nbz, nvals);
         st = check_launch("brick_kernel");
+        unsigned cblocks = (unsigned)((nbricks + 255) / 256);
+        if (st == MCL_OK) {
+            if (d.dtype == MCL_TSDF_I16)
+                brick_class_kernel<int16_t><<<cblocks, 256, 0, stream>>>((const int16_t *)m->dev, cls, d.nx, d.ny, d.nz, nbx, nbz, nbricks, (int16_t)32767, (int16_t)-32767);
+            else if (d.dtype == MCL_TSDF_I8)
+                brick_class_kernel<int8_t><<<cblocks, 256, 0, stream>>>((const int8_t *)m->dev, cls, d.nx, d.ny, d.nz, nbx, nbz, nbricks, (int8_t)127, (int8_t)-127);
+            else
+                brick_class_kernel<float><<<cblocks, 256, 0, stream>>>((const float *)m->dev, cls, d.nx, d.ny, d.nz, nbx, nbz, nbricks, d.tau, -d.tau);
+            st = check_launch("brick_class_kernel");
+        }
         if (st == MCL_OK && hipStreamSynchronize(stream) != hipSuccess) st = fail(MCL_EDEVICE, "map_upload: synchronisation failed");
     }
     (void)hipFree(dense_dev);
@@ -117,7 +157,9 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     v.cx = (uint32_t)(es * (16 * nbz - 1));
     v.cy = (uint32_t)cy;
     v.out_off = (uint32_t)data_bytes;
-    v.zero_off = (uint32_t)(data_bytes + 128);
+    v.zero_off = (uint32_t)(data_bytes + 64 * es);
+    v.cls = reinterpret_cast<const uint8_t *>(static_cast<const char *>(m->dev) + cls_off);
+    v.qf = d.dtype == MCL_TSDF_F32 ? d.tau : (float)m->Q;
     *out = m;
     return MCL_OK;
 }

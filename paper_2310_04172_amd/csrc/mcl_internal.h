@@ -17,11 +17,18 @@ constexpr int kWave = 64;
 // contiguous run, so a 3-D neighbourhood touches few cache lines (an int16
 // brick is one 128-byte line).  Bricks are ordered z fastest, then x, then y
 // (maps are flat: nz is the short axis), which keeps every address coefficient
-// below 2^24 for 24-bit multiplies.  Two sentinel cells follow the bricks: +Q
-// (read by points outside the map) and 0 (read by padding lanes past the end
-// of a scan, contributing nothing).
+// below 2^24 for 24-bit multiplies.  Two sentinel bricks follow: +Q (read by
+// points outside the map) and 0 (read by padding lanes past the end of a scan,
+// contributing nothing).
+//
+// Beside the values sits one class byte per brick (the coarse level of the
+// map): 1 if every voxel of the brick holds +-Q (the truncation value: free
+// space or solid beyond the band), 0 if the brick has any value inside the
+// band, 2 for the zero sentinel.  Only q^2 enters the score, so a class-1 brick
+// scores Q^2 for any point without reading its values.
 constexpr int kBrickLog2 = 2;
 constexpr int kBrickVals = 64;
+constexpr uint8_t kClassMixed = 0, kClassTrunc = 1, kClassZero = 2;
 
 struct MapView {
     const char *base;        // device: bricked values, then the sentinels
@@ -31,8 +38,10 @@ struct MapView {
     float inv_v;             // (float)(1.0 / (double)voxel)
     float ox, oy, oz;        // origin
     uint32_t cx, cy;         // ESIZE (16 nbz - 1), ESIZE (16 nbz nbx - 4)
-    uint32_t out_off;        // byte offset of the +Q sentinel
-    uint32_t zero_off;       // byte offset of the 0 sentinel
+    uint32_t out_off;        // byte offset of the +Q sentinel brick
+    uint32_t zero_off;       // byte offset of the 0 sentinel brick
+    const uint8_t *cls;      // device: class byte per brick, indexed by byte offset >> (6 + log2 esize)
+    float qf;                // Q as float (tau for float32 maps)
 };
 
 }  // namespace mcl

@@ -46,7 +46,13 @@ __device__ inline float load_val(const char *base, uint32_t off) {
     return (float)*reinterpret_cast<const T *>(base + off);
 }
 
+template <typename T>
+constexpr int class_shift() { return 6 + (sizeof(T) == 1 ? 0 : sizeof(T) == 2 ? 1 : 2); }
+
 // Lane partial sum of one particle (pose in A) over this lane's kU points.
+// Coarse level first: the class byte of each point's brick; only points in
+// bricks with values inside the truncation band read the fine value (lanes
+// masked, the load skipped when no lane of the wave needs it).
 template <typename T, bool TAIL>
 __device__ inline float lane_chunk_sum(const MapView &m, const float (&A)[12], const float (&px)[kU],
                                        const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid) {
@@ -60,10 +66,16 @@ __device__ inline float lane_chunk_sum(const MapView &m, const float (&A)[12], c
         if (TAIL) o = (u * kWave + lane < nvalid) ? o : m.zero_off;
         off[u] = o;
     }
+    uint32_t cls[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) cls[u] = m.cls[off[u] >> class_shift<T>()];
+    __builtin_amdgcn_sched_barrier(0);
     float v[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) v[u] = load_val<T>(m.base, off[u]);
-    // keep all kU gathers in flight before the first use
+    for (int u = 0; u < kU; ++u) {
+        v[u] = (cls[u] == kClassTrunc) ? m.qf : 0.0f;
+        if (cls[u] == kClassMixed) v[u] = load_val<T>(m.base, off[u]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     float s = 0.0f;
 #pragma unroll
