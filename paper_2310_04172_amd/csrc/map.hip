@@ -1,5 +1,6 @@
 // TSDF map upload: dense x-fastest host array -> device brick layout + sentinels.
 #include <cmath>
+#include <cstring>
 #include <new>
 
 #include "mcl_internal.h"
@@ -149,9 +150,12 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     v.base = static_cast<const char *>(m->dev);
     v.nx = d.nx; v.ny = d.ny; v.nz = d.nz;
     v.nbx = nbx; v.nby = nby; v.nbz = nbz;
-    v.hx = std::nextafter((float)d.nx, 0.0f);
-    v.hy = std::nextafter((float)d.ny, 0.0f);
-    v.hz = std::nextafter((float)d.nz, 0.0f);
+    {
+        float fx = (float)d.nx, fy = (float)d.ny, fz = (float)d.nz;
+        std::memcpy(&v.bx, &fx, 4);
+        std::memcpy(&v.by, &fy, 4);
+        std::memcpy(&v.bz, &fz, 4);
+    }
     v.inv_v = (float)(1.0 / (double)d.voxel);
     v.ox = d.origin[0]; v.oy = d.origin[1]; v.oz = d.origin[2];
     v.cx = (uint32_t)(es * (16 * nbz - 1));
@@ -160,6 +164,8 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     v.zero_off = (uint32_t)(data_bytes + 64 * es);
     v.cls = reinterpret_cast<const uint8_t *>(static_cast<const char *>(m->dev) + cls_off);
     v.qf = d.dtype == MCL_TSDF_F32 ? d.tau : (float)m->Q;
+    if (d.dtype == MCL_TSDF_F32) std::memcpy(&v.qraw, &d.tau, 4);
+    else v.qraw = m->Q;
     *out = m;
     return MCL_OK;
 }

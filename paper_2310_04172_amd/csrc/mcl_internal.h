@@ -6,7 +6,7 @@
 
 #include <string>
 
-#include "../../include/mcl.h"
+#include "mcl.h"
 
 namespace mcl {
 
@@ -34,7 +34,7 @@ struct MapView {
     const char *base;        // device: bricked values, then the sentinels
     int32_t nx, ny, nz;      // true dimensions
     int32_t nbx, nby, nbz;   // bricks per axis
-    float hx, hy, hz;        // largest float below nx, ny, nz (bounds test)
+    uint32_t bx, by, bz;     // bit patterns of (float)nx, ny, nz (bounds test)
     float inv_v;             // (float)(1.0 / (double)voxel)
     float ox, oy, oz;        // origin
     uint32_t cx, cy;         // ESIZE (16 nbz - 1), ESIZE (16 nbz nbx - 4)
@@ -42,6 +42,7 @@ struct MapView {
     uint32_t zero_off;       // byte offset of the 0 sentinel brick
     const uint8_t *cls;      // device: class byte per brick, indexed by byte offset >> (6 + log2 esize)
     float qf;                // Q as float (tau for float32 maps)
+    int32_t qraw;            // +Q as the raw register value a gather returns (float bits for float32)
 };
 
 }  // namespace mcl

@@ -32,18 +32,43 @@ __device__ inline float bcast(float x, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
-// Butterfly sum over the 64 lanes.  Every step adds the values of lane pairs
-// (l, l^d); IEEE addition is commutative, so both lanes of a pair hold the same
-// bits after each step and all lanes end with the same total.
+// Butterfly sum over the 64 lanes without LDS: DPP quad permutations (xor 1,
+// xor 2), half-row and row mirrors (pairing lane i with 7-i, 15-i once the
+// groups below are uniform) and the gfx950 row / half-wave swaps (xor 16,
+// xor 32).  Each step adds a lane's value and its partner's; IEEE addition is
+// commutative, so both lanes of a pair hold the same bits after every step and
+// all 64 lanes end with the same total, in a fixed order.
+template <int CTRL>
+__device__ inline float dpp_add(float x) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
 __device__ inline float wave_sum(float x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-    return x;
+    x = dpp_add<0xB1>(x);   // quad_perm [1,0,3,2]
+    x = dpp_add<0x4E>(x);   // quad_perm [2,3,0,1]
+    x = dpp_add<0x141>(x);  // row_half_mirror
+    x = dpp_add<0x140>(x);  // row_mirror
+    auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+    auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
+}
+
+// Raw map value as a 32-bit register (sign-extended integer or float bits).
+template <typename T>
+__device__ inline int load_raw(const char *base, uint32_t off) {
+    if constexpr (sizeof(T) == 4)
+        return __float_as_int(*reinterpret_cast<const float *>(base + off));
+    else
+        return (int)*reinterpret_cast<const T *>(base + off);
 }
 
 template <typename T>
-__device__ inline float load_val(const char *base, uint32_t off) {
-    return (float)*reinterpret_cast<const T *>(base + off);
+__device__ inline float as_value(int raw) {
+    if constexpr (sizeof(T) == 4)
+        return __int_as_float(raw);
+    else
+        return (float)raw;
 }
 
 template <typename T>
@@ -51,8 +76,7 @@ constexpr int class_shift() { return 6 + (sizeof(T) == 1 ? 0 : sizeof(T) == 2 ? 
 
 // Lane partial sum of one particle (pose in A) over this lane's kU points.
 // Coarse level first: the class byte of each point's brick; only points in
-// bricks with values inside the truncation band read the fine value (lanes
-// masked, the load skipped when no lane of the wave needs it).
+// bricks with values inside the truncation band read their own fine value.
 template <typename T, bool TAIL>
 __device__ inline float lane_chunk_sum(const MapView &m, const float (&A)[12], const float (&px)[kU],
                                        const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid) {
@@ -70,16 +94,24 @@ __device__ inline float lane_chunk_sum(const MapView &m, const float (&A)[12], c
 #pragma unroll
     for (int u = 0; u < kU; ++u) cls[u] = m.cls[off[u] >> class_shift<T>()];
     __builtin_amdgcn_sched_barrier(0);
-    float v[kU];
+    // Lanes whose brick is not mixed read the sentinel brick of their class
+    // instead (class 1 -> the +Q brick at out_off, class 2 -> the zero brick
+    // right after it): one line every such lane shares, so the gathers need no
+    // branches and all kU of them stay in flight.
+    int raw[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-        v[u] = (cls[u] == kClassTrunc) ? m.qf : 0.0f;
-        if (cls[u] == kClassMixed) v[u] = load_val<T>(m.base, off[u]);
+        // without padding lanes the zero class cannot occur: one sentinel
+        uint32_t sent = TAIL ? m.out_off + (cls[u] - 1u) * (64u * (uint32_t)sizeof(T)) : m.out_off;
+        raw[u] = load_raw<T>(m.base, cls[u] == kClassMixed ? off[u] : sent);
     }
     __builtin_amdgcn_sched_barrier(0);
     float s = 0.0f;
 #pragma unroll
-    for (int u = 0; u < kU; ++u) s = __builtin_fmaf(v[u], v[u], s);
+    for (int u = 0; u < kU; ++u) {
+        float f = as_value<T>(raw[u]);
+        s = __builtin_fmaf(f, f, s);
+    }
     return s;
 }
 

@@ -18,9 +18,12 @@ __device__ inline void pose_consts(const float *__restrict__ poses, int N, int n
     float dx = poses[(size_t)9 * N + n] - m.ox;
     float dy = poses[(size_t)10 * N + n] - m.oy;
     float dz = poses[(size_t)11 * N + n] - m.oz;
-    pa[9] = dx * m.inv_v;
-    pa[10] = dy * m.inv_v;
-    pa[11] = dz * m.inv_v;
+    // adding +0.0 turns a -0.0 offset into +0.0 and leaves every other value
+    // unchanged; then g = s + b is never -0.0 (see voxel_ijk), while the voxel
+    // selected is the same as without it (-0.0 and +0.0 select voxel 0 alike)
+    pa[9] = dx * m.inv_v + 0.0f;
+    pa[10] = dy * m.inv_v + 0.0f;
+    pa[11] = dz * m.inv_v + 0.0f;
 }
 
 // One grid coordinate: ((a0 x + a1 y) + a2 z) + b, every operation rounded.
@@ -35,19 +38,19 @@ __device__ inline float grid_coord(float a0, float a1, float a2, float b, float 
 }
 
 // Voxel (ix, iy, iz) holding grid coordinates g, if 0 <= g < n on every axis
-// (NaN is outside).  g is clamped into [0, h] with h the largest float below n:
-// a coordinate inside [0, n) is left unchanged (and -0.0 compares equal to its
-// clamp, as -0.0 >= 0), anything else changes, NaN compares unequal; the clamped
-// value converts to the voxel index exactly as (int)g would.
+// (NaN is outside).  For a float g that is not -0.0, 0 <= g < n holds exactly
+// when its bit pattern, read as an unsigned integer, is below that of n:
+// non-negative floats order like their bit patterns, and negative values and
+// NaNs of either sign have patterns above any finite positive n.  The pose
+// prologue makes g = -0.0 impossible.  The integer coordinates are (int)g;
+// for a point outside the map they are meaningless and the caller must not
+// use them (voxel_offset replaces the address by the sentinel's).
 __device__ inline bool voxel_ijk(const MapView &m, float gx, float gy, float gz, uint32_t &ix,
                                  uint32_t &iy, uint32_t &iz) {
-    float cx = __builtin_amdgcn_fmed3f(gx, 0.0f, m.hx);
-    float cy = __builtin_amdgcn_fmed3f(gy, 0.0f, m.hy);
-    float cz = __builtin_amdgcn_fmed3f(gz, 0.0f, m.hz);
-    bool ok = (cx == gx) & (cy == gy) & (cz == gz);
-    ix = (uint32_t)(int)cx;
-    iy = (uint32_t)(int)cy;
-    iz = (uint32_t)(int)cz;
+    bool ok = (__float_as_uint(gx) < m.bx) & (__float_as_uint(gy) < m.by) & (__float_as_uint(gz) < m.bz);
+    ix = (uint32_t)(int)gx;
+    iy = (uint32_t)(int)gy;
+    iz = (uint32_t)(int)gz;
     return ok;
 }
 
@@ -59,9 +62,8 @@ __device__ inline bool voxel_ijk(const MapView &m, float gx, float gy, float gz,
 // cx, cy hold the two coefficients times ESIZE; the upload keeps them below 2^24.
 template <int ESIZE>
 __device__ inline uint32_t brick_offset(const MapView &m, uint32_t ix, uint32_t iy, uint32_t iz) {
-    uint32_t a = __umul24(ix & ~3u, m.cx) + iz * (16u * ESIZE);
-    uint32_t b = __umul24(iy & ~3u, m.cy) + a;
-    return b + ix * (uint32_t)ESIZE + iy * (4u * ESIZE);
+    uint32_t lin = (ix + (iy << 2) + (iz << 4)) * (uint32_t)ESIZE;  // ESIZE (ix + 4 iy + 16 iz)
+    return __umul24(ix & ~3u, m.cx) + (__umul24(iy & ~3u, m.cy) + lin);
 }
 
 // Byte offset read for grid coordinates g: the voxel's, or the +Q sentinel outside.

@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libmcl.so")
+LIB_PATH = os.environ.get("MCL_LIBRARY") or os.path.join(PKG, "libmcl.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2310_04172_amd.build`")

@@ -156,6 +156,22 @@ def test_voxel_indices_bit_exact_random(torch, mcl, oracle_lib):
     assert 0.05 < np.mean(ref >= 0) < 0.95
 
 
+def test_negative_zero_coordinates(torch, mcl, oracle_lib):
+    """A pose translation of -0.0 at a zero origin with points of -0.0 makes the
+    grid coordinate -0.0, which the recipe counts as inside (voxel 0)."""
+    say("case: -0.0 coordinates")
+    tmap = make_map(np.arange(4 * 4 * 4, dtype=np.int16).reshape(4, 4, 4) * 100, 0.125)
+    poses = identity_poses(2)
+    poses[9:, 0] = -0.0
+    pts = np.array([[-0.0, 0.0, -0.0, 0.0625], [-0.0, 0.0, 0.0, -0.0], [-0.0, -0.0, 0.0, -0.0]], np.float32)
+    m = mcl.Map.from_tsdf(tmap)
+    got = mcl.debug_voxel_indices(m, dev(torch, pts), dev(torch, poses)).cpu().numpy()
+    ref = oracle_lib.voxel_indices(tmap, pts, poses)
+    assert np.array_equal(got, ref) and np.all(ref == 0)
+    lw = mcl.sensor_update(m, dev(torch, pts), dev(torch, poses), f32(0.1)).cpu().numpy()
+    assert np.all(lw == 0.0)
+
+
 def test_permutation_and_determinism(torch, mcl):
     """Bit-identical results for the same particle whatever its slot, N or run."""
     say("case: determinism")

@@ -72,6 +72,15 @@ def test_cell_faces_are_half_open(oracle_lib):
     assert list(lin) == [0, 1 + nx * (0 + ny * 1), 3 + nx * (2 + ny * 1), -1, 0, -1, -1]
 
 
+def test_negative_zero_grid_coordinate_is_inside(oracle_lib):
+    """g = -0.0 (translation -0.0, zero origin, point -0.0) compares >= 0: voxel 0."""
+    tmap = make_map(np.zeros((2, 2, 2), np.int16), 0.125)
+    poses = identity_poses(1)
+    poses[9:, 0] = -0.0
+    pts = np.array([[-0.0], [-0.0], [-0.0]], np.float32)
+    assert oracle_lib.voxel_indices(tmap, pts, poses)[0, 0] == 0
+
+
 # ---------------------------------------------------------------- closed forms
 @pytest.mark.parametrize("dtype", ["i16", "i8", "f32"])
 def test_identity_pose_exact_score(oracle_lib, dtype):
