@@ -122,6 +122,67 @@ mcl_status mcl_normalize(const float *logw, int32_t N, double *w, uint64_t *wq, 
 mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t u, int32_t *idx,
                         const float *poses_in, float *poses_out, void *stream);
 
+/* ------------------------------------------------------------- batching
+ * One MCL update of many filters at once (the filters may use different maps,
+ * particle counts and scan sizes).  mcl_tick runs, for every filter, exactly
+ * mcl_sensor_update, then mcl_normalize, then mcl_resample: each stage is one
+ * launch over all filters together, and every filter's results are bit for
+ * bit those of the three single-filter calls.  Buffers follow the rules of the
+ * single-filter calls; all buffers of all jobs must be distinct. */
+#define MCL_MAX_JOBS 4096
+
+typedef struct {
+    mcl_map map;            /* the filter's map                                   */
+    const float *points;    /* device [3][K]; may be NULL if K = 0                */
+    int32_t K;              /* scan points, [0, MCL_MAX_POINTS]                   */
+    const float *poses;     /* device [12][N] particle poses                      */
+    int32_t N;              /* particles, [1, MCL_MAX_PARTICLES]                  */
+    float sigma;            /* Eq. (3) sigma, metres                              */
+    float *logw;            /* device out [N]                                     */
+    double *w;              /* device out [N], or NULL                            */
+    uint64_t *wq;           /* device out [N]                                     */
+    double *log_z;          /* device out [1], or NULL                            */
+    uint64_t u;             /* uniform 64-bit draw for the resampling offset      */
+    int32_t *idx;           /* device out [N] ancestor indices                    */
+    float *poses_out;       /* device out [12][N] resampled poses, or NULL        */
+} mcl_filter_job;
+
+/* Flag for mcl_tick: the launch chain is captured into a HIP graph the first
+ * time (per stream and per mix of map storage types) and replayed afterwards;
+ * job tables are copied to the device before each replay.  Needs a
+ * non-default stream. */
+#define MCL_TICK_GRAPH 1
+
+/* Run one tick for n_jobs filters (1..MCL_MAX_JOBS) on `stream`.  The job array
+ * is read during the call (it may be reused when the call returns).  Returns
+ * the first argument error with the failing job's index in mcl_last_error(). */
+mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32_t flags, void *stream);
+
+/* Device bytes one filter of N particles and K points needs in a tick: the
+ * caller's buffers (poses in and out, logw, w, wq, idx, scan) plus the
+ * library's workspace for it.  For admission control; 0 for invalid sizes. */
+size_t mcl_job_bytes(int32_t N, int32_t K);
+
+/* --------------------------------------------------------------- tuning
+ * Launch shape of the sensor kernel: waves per workgroup (2, 4, 8) and, for a
+ * persistent grid, workgroups per compute unit (0 = one wave per work item).
+ * The shape never changes results (the summation order depends only on K). */
+typedef struct {
+    int32_t waves_per_block;
+    int32_t blocks_per_cu;
+} mcl_launch_config;
+
+/* Time every launch shape on the given filter (synchronises `stream`), keep
+ * the fastest for its storage type and size class (K and N rounded to powers
+ * of two) for later mcl_sensor_update / mcl_tick calls, and return it in *best
+ * (may be NULL).  logw_scratch: device [N] float32 the trials write. */
+mcl_status mcl_autotune(mcl_map map, const float *points, int32_t K, const float *poses, int32_t N, float sigma,
+                        float *logw_scratch, void *stream, mcl_launch_config *best);
+
+/* Set (or with NULL clear) the shape used for a storage type and size class,
+ * as mcl_autotune would. */
+mcl_status mcl_set_launch_config(int32_t dtype, int32_t K, int32_t N, const mcl_launch_config *cfg);
+
 /* Test support: the voxel each (particle, point) pair reads, by the same
  * device code as mcl_sensor_update.  lin_idx: device output [N][K] int64,
  * i + nx*(j + ny*k), or -1 outside the map.  N*K must not exceed 2^31. */

@@ -1,0 +1,110 @@
+// Per-filter work descriptions shared by the single-filter entry points and the
+// batched tick.  A kernel reads its filters through a job source: either one
+// job passed by value (single filter) or a table in device memory (batch),
+// searched by the prefix offsets each job carries.
+#pragma once
+
+#include "mcl_internal.h"
+
+namespace mcl {
+
+// Sensor-update decomposition.  The summation order depends only on these
+// constants and K (see sensor.hip), never on the launch shape.
+constexpr int kU = 16;                            // points per lane per chunk
+constexpr int kChunk = kWave * kU;                // 1024
+constexpr int kChunksPerPiece = 4;
+constexpr int kPiece = kChunk * kChunksPerPiece;  // 4096 points
+constexpr int kGroup = 64;                        // particles per wave item
+
+inline int sensor_pieces(int K) { return K <= 0 ? 1 : (K + kPiece - 1) / kPiece; }
+
+struct SensorJob {
+    MapView map;
+    const float *pts;     // [3][K]
+    const float *poses;   // [12][N]
+    float *logw;          // [N] output
+    float *part;          // [npiece][N] piece partials (npiece > 1)
+    int64_t item0;        // first work item of this job in the launch
+    int64_t elem0;        // first particle of this job in the launch
+    float c;              // s^2 / (2 sigma^2)
+    int32_t K, N, npiece, ngroups;
+};
+
+// Weight normalisation and resampling of one filter.
+constexpr int kWThreads = 256;
+constexpr int kWPer = 16;
+constexpr int kWBlock = kWThreads * kWPer;  // 4096 particles per block
+
+inline int weight_blocks(int N) { return (N + kWBlock - 1) / kWBlock; }
+
+struct WeightJob {
+    const float *logw;    // [N]
+    double *w;            // [N] or null
+    uint64_t *wq;         // [N]
+    double *log_z;        // [1] or null (output)
+    int32_t *idx;         // [N] or null (normalise only)
+    const float *pin;     // [12][N] or null
+    float *pout;          // [12][N] or null
+    double *lse_part;     // workspace [2 nblk]
+    double *lz;           // workspace [1]
+    uint64_t *bsum;       // workspace [nblk]
+    uint64_t *total;      // workspace [1]
+    uint64_t *C;          // workspace [N]
+    uint64_t u;           // resampling draw
+    int64_t elem0;        // first particle of this job in the launch
+    int32_t blk0;         // first weight block of this job in the launch
+    int32_t nblk, N, pad_;
+};
+
+// ------------------------------------------------------------ job sources
+// Totals of a launch: jobs, sensor work items, particles, weight blocks.
+struct Counts {
+    int64_t njobs, items, elems, blocks;
+};
+
+template <typename J>
+struct OneJob {
+    J job;
+    Counts n;
+    __device__ const J &get(int) const { return job; }
+    __device__ int count() const { return 1; }
+    __device__ int64_t items() const { return n.items; }
+    __device__ int64_t elems() const { return n.elems; }
+    __device__ int64_t blocks() const { return n.blocks; }
+};
+
+// Jobs and totals in device memory, so one captured launch chain serves any
+// job set written there before it runs.
+template <typename J>
+struct JobTable {
+    const J *jobs;
+    const Counts *n;
+    __device__ const J &get(int j) const { return jobs[j]; }
+    __device__ int count() const { return (int)n->njobs; }
+    __device__ int64_t items() const { return n->items; }
+    __device__ int64_t elems() const { return n->elems; }
+    __device__ int64_t blocks() const { return n->blocks; }
+};
+
+// Index of the last job whose key(job) <= x (jobs sorted by key); wave-uniform.
+template <typename Src, typename Key>
+__device__ inline int find_job(const Src &src, int64_t x, Key key) {
+    int lo = 0, hi = src.count() - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (key(src.get(mid)) <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Launch shape of the sensor kernel; any shape gives bit-identical results.
+struct LaunchCfg {
+    int waves_per_block;  // 2, 4 or 8
+    int blocks_per_cu;    // 0: one wave per work item; else a persistent grid
+};
+
+LaunchCfg tuned_config(int32_t dtype, int K, int N);
+int device_cus();
+
+}  // namespace mcl

@@ -17,16 +17,12 @@
 // The summation order is a function of K only (lane partials of 16 terms,
 // 6-level wave tree, 4 chunks per piece in order, pairwise over pieces): the
 // same particle gives the same bits whatever N, grid or batch it runs in.
+#include <algorithm>
+
+#include "jobs.h"
 #include "voxel.h"
 
 namespace mcl {
-
-constexpr int kU = 16;                          // points per lane per chunk
-constexpr int kChunk = kWave * kU;              // 1024
-constexpr int kChunksPerPiece = 4;
-constexpr int kPiece = kChunk * kChunksPerPiece;  // 4096 points
-constexpr int kGroup = 64;                      // particles per wave
-constexpr int kWavesPerBlock = 4;
 
 __device__ inline float bcast(float x, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
@@ -128,21 +124,20 @@ __device__ inline void chunk_group(const MapView &m, const float (&pa)[12], cons
     }
 }
 
-// out: logw (npiece == 1) or piece partial sums [npiece][N].
+// One work item: particles [64 g, 64 g + 64) of a job against points
+// [4096 piece, 4096 piece + 4096).  Output: l directly (one piece) or the
+// piece's partial sums.
 template <typename T>
-__global__ __launch_bounds__(256) void sensor_kernel(MapView m, const float *__restrict__ pts, int K,
-                                                     const float *__restrict__ poses, int N, float c,
-                                                     float *__restrict__ out, int npiece, int nitems) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (item >= nitems) return;
-    const int group = item / npiece;
-    const int piece = item - group * npiece;
+__device__ inline void sensor_item(const SensorJob &J, int local, int lane) {
+    const int group = local / J.npiece;
+    const int piece = local - group * J.npiece;
     const int n0 = group * kGroup;
-    const int gcount = min(kGroup, N - n0);
+    const int gcount = min(kGroup, J.N - n0);
+    const MapView &m = J.map;
+    const int K = J.K;
 
     float pa[12];
-    pose_consts(poses, N, n0 + min(lane, gcount - 1), m, pa);
+    pose_consts(J.poses, J.N, n0 + min(lane, gcount - 1), m, pa);
 
     float acc = 0.0f;
     const int kb = piece * kPiece;
@@ -153,9 +148,9 @@ __global__ __launch_bounds__(256) void sensor_kernel(MapView m, const float *__r
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             int k = min(kc + u * kWave + lane, ke - 1);  // padding slots are masked later
-            px[u] = pts[k];
-            py[u] = pts[(size_t)K + k];
-            pz[u] = pts[(size_t)2 * K + k];
+            px[u] = J.pts[k];
+            py[u] = J.pts[(size_t)K + k];
+            pz[u] = J.pts[(size_t)2 * K + k];
         }
         if (nvalid == kChunk)
             chunk_group<T, false>(m, pa, px, py, pz, lane, nvalid, gcount, acc);
@@ -163,29 +158,49 @@ __global__ __launch_bounds__(256) void sensor_kernel(MapView m, const float *__r
             chunk_group<T, true>(m, pa, px, py, pz, lane, nvalid, gcount, acc);
     }
     if (lane < gcount) {
-        if (npiece == 1)
-            out[n0 + lane] = -(acc * c);
+        if (J.npiece == 1)
+            J.logw[n0 + lane] = -(acc * J.c);
         else
-            out[(size_t)piece * N + n0 + lane] = acc;
+            J.part[(size_t)piece * J.N + n0 + lane] = acc;
+    }
+}
+
+// Waves stride over the work items of all jobs of the launch (one item per
+// wave for a full grid, several for a persistent one).
+template <typename T, int WPB, typename Src>
+__global__ __launch_bounds__(WPB * 64) void sensor_kernel(Src src) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nitems = src.items();
+    const int64_t stride = (int64_t)gridDim.x * WPB;
+    for (int64_t item = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems;
+         item += stride) {
+        const int j = find_job(src, item, [](const SensorJob &J) { return J.item0; });
+        const SensorJob &J = src.get(j);
+        sensor_item<T>(J, (int)(item - J.item0), lane);
     }
 }
 
 // Pairwise sum of the piece partials in a fixed tree (a binary counter over the
-// pieces in order), then l = -(S * c).
-__global__ __launch_bounds__(256) void combine_kernel(const float *__restrict__ part, int npiece, int N,
-                                                      float c, float *__restrict__ logw) {
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float stack[12];
-    int depth = 0;
-    for (int j = 0; j < npiece; ++j) {
-        float v = part[(size_t)j * N + n];
-        for (int t = j + 1; (t & 1) == 0; t >>= 1) v = stack[--depth] + v;
-        stack[depth++] = v;
+// pieces in order), then l = -(S * c).  Jobs with one piece are done already.
+template <typename Src>
+__global__ __launch_bounds__(256) void combine_kernel(Src src) {
+    const int64_t nelems = src.elems();
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nelems; e += (int64_t)gridDim.x * 256) {
+        const int j = find_job(src, e, [](const SensorJob &J) { return J.elem0; });
+        const SensorJob &J = src.get(j);
+        if (J.npiece == 1) continue;
+        const int n = (int)(e - J.elem0);
+        float stack[12];
+        int depth = 0;
+        for (int p = 0; p < J.npiece; ++p) {
+            float v = J.part[(size_t)p * J.N + n];
+            for (int t = p + 1; (t & 1) == 0; t >>= 1) v = stack[--depth] + v;
+            stack[depth++] = v;
+        }
+        float s = stack[--depth];
+        while (depth > 0) s = stack[--depth] + s;
+        J.logw[n] = -(s * J.c);
     }
-    float s = stack[--depth];
-    while (depth > 0) s = stack[--depth] + s;
-    logw[n] = -(s * c);
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ out, int n, float v) {
@@ -211,37 +226,88 @@ __global__ __launch_bounds__(256) void debug_index_kernel(MapView m, const float
 }
 
 // ------------------------------------------------------------------ host side
-int sensor_pieces(int K) { return K <= 0 ? 1 : (K + kPiece - 1) / kPiece; }
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            cus = p.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
 
-mcl_status launch_sensor(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
-                         float *logw, hipStream_t stream) {
+// nitems: the item count when known on the host (sizes a one-wave-per-item
+// grid); a persistent grid does not need it.
+template <typename T, typename Src>
+static void launch_sensor_t(const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream) {
+    const int wpb = cfg.waves_per_block;
+    int64_t blocks = (nitems + wpb - 1) / wpb;
+    if (cfg.blocks_per_cu > 0) blocks = std::min<int64_t>(blocks, (int64_t)device_cus() * cfg.blocks_per_cu);
+    if (blocks < 1) blocks = 1;
+    switch (wpb) {
+        case 2: sensor_kernel<T, 2><<<(unsigned)blocks, 128, 0, stream>>>(src); break;
+        case 8: sensor_kernel<T, 8><<<(unsigned)blocks, 512, 0, stream>>>(src); break;
+        default: sensor_kernel<T, 4><<<(unsigned)blocks, 256, 0, stream>>>(src); break;
+    }
+}
+
+template <typename Src>
+mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int64_t nelems, bool combine,
+                             LaunchCfg cfg, hipStream_t stream) {
+    if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t>(src, nitems, cfg, stream);
+    else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t>(src, nitems, cfg, stream);
+    else launch_sensor_t<float>(src, nitems, cfg, stream);
+    mcl_status st = check_launch("sensor_kernel");
+    if (st != MCL_OK || !combine) return st;
+    int64_t blocks = std::min<int64_t>((nelems + 255) / 256, (int64_t)device_cus() * 16);
+    combine_kernel<<<(unsigned)std::max<int64_t>(blocks, 1), 256, 0, stream>>>(src);
+    return check_launch("combine_kernel");
+}
+
+template mcl_status launch_sensor_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t, int64_t,
+                                                           bool, LaunchCfg, hipStream_t);
+template mcl_status launch_sensor_src<OneJob<SensorJob>>(int32_t, const OneJob<SensorJob> &, int64_t, int64_t,
+                                                         bool, LaunchCfg, hipStream_t);
+
+SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
+                          float *logw, float *part) {
+    SensorJob J{};
+    J.map = map->view;
+    J.pts = pts;
+    J.poses = poses;
+    J.logw = logw;
+    J.part = part;
+    J.c = c;
+    J.K = K;
+    J.N = N;
+    J.npiece = sensor_pieces(K);
+    J.ngroups = (N + kGroup - 1) / kGroup;
+    return J;
+}
+
+mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
+                             float *logw, LaunchCfg cfg, hipStream_t stream) {
     if (K == 0) {
-        fill_kernel<<<(N + 255) / 256, 256, 0, stream>>>(logw, N, -0.0f * c);
+        fill_kernel<<<(N + 255) / 256, 256, 0, stream>>>(logw, N, -(0.0f * c));
         return check_launch("fill_kernel");
     }
     const int npiece = sensor_pieces(K);
-    const int ngroups = (N + kGroup - 1) / kGroup;
-    const int nitems = ngroups * npiece;
-    const int blocks = (nitems + kWavesPerBlock - 1) / kWavesPerBlock;
-    float *out = logw;
+    float *part = nullptr;
     if (npiece > 1) {
-        out = static_cast<float *>(workspace(stream, (size_t)npiece * N * sizeof(float)));
-        if (!out) return fail(MCL_ENOMEM, "sensor_update: workspace allocation failed");
+        part = static_cast<float *>(workspace(stream, (size_t)npiece * N * sizeof(float)));
+        if (!part) return fail(MCL_ENOMEM, "sensor_update: workspace allocation failed");
     }
-    switch (map->dtype) {
-        case MCL_TSDF_I16:
-            sensor_kernel<int16_t><<<blocks, 256, 0, stream>>>(map->view, pts, K, poses, N, c, out, npiece, nitems);
-            break;
-        case MCL_TSDF_I8:
-            sensor_kernel<int8_t><<<blocks, 256, 0, stream>>>(map->view, pts, K, poses, N, c, out, npiece, nitems);
-            break;
-        default:
-            sensor_kernel<float><<<blocks, 256, 0, stream>>>(map->view, pts, K, poses, N, c, out, npiece, nitems);
-    }
-    mcl_status st = check_launch("sensor_kernel");
-    if (st != MCL_OK || npiece == 1) return st;
-    combine_kernel<<<(N + 255) / 256, 256, 0, stream>>>(out, npiece, N, c, logw);
-    return check_launch("combine_kernel");
+    OneJob<SensorJob> src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
+    const int64_t nitems = (int64_t)src.job.ngroups * npiece;
+    src.n = Counts{1, nitems, N, 0};
+    return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream);
+}
+
+mcl_status launch_sensor(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
+                         float *logw, hipStream_t stream) {
+    return launch_sensor_cfg(map, pts, K, poses, N, c, logw, tuned_config(map->dtype, K, N), stream);
 }
 
 mcl_status launch_debug_indices(const mcl_map_s *map, const float *pts, int K, const float *poses, int N,

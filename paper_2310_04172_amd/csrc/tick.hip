@@ -1,0 +1,264 @@
+// Batched tick: sensor update, normalisation and resampling of many filters in
+// one launch per stage.  Job tables and totals live in device memory, so the
+// launch chain does not depend on the job set: it is captured once into a HIP
+// graph (per stream, per storage-type mix and launch shape) and replayed every
+// tick after the tables are copied in.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "jobs.h"
+
+namespace mcl {
+
+SensorJob make_sensor_job(const mcl_map_s *, const float *, int, const float *, int, float, float *, float *);
+template <typename Src>
+mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t);
+template <typename Src>
+mcl_status launch_normalize_src(const Src &, int, int64_t, int64_t, hipStream_t);
+template <typename Src>
+mcl_status launch_resample_src(const Src &, int64_t, int64_t, hipStream_t);
+size_t weight_ws_bytes(int N);
+void bind_weight_ws(WeightJob &J, void *ws);
+
+constexpr int kMaxJobs = MCL_MAX_JOBS;
+constexpr int kGroups = 3;  // storage types
+
+static constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device/staging layout: Counts[kGroups + 1] | SensorJob[kGroups][kMaxJobs] | WeightJob[kMaxJobs].
+// Each storage type has its own sensor table at a fixed place, so a captured
+// chain stays valid however the jobs of a tick split among the types.
+static constexpr size_t kCountsBytes = align256(sizeof(Counts) * (kGroups + 1));
+static constexpr size_t kSensorTblOff = kCountsBytes;
+static constexpr size_t kSensorTblBytes = align256(sizeof(SensorJob) * kMaxJobs);
+static constexpr size_t kWeightTblOff = kSensorTblOff + kGroups * kSensorTblBytes;
+static constexpr size_t kTablesBytes = kWeightTblOff + align256(sizeof(WeightJob) * kMaxJobs);
+
+namespace {
+
+struct GraphKey {
+    int mask;
+    int wpb, bpc;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(mask, wpb, bpc) < std::tie(o.mask, o.wpb, o.bpc);
+    }
+};
+
+struct TickState {
+    char *dev = nullptr;      // tables + per-job workspace
+    size_t dev_bytes = 0;
+    char *host = nullptr;     // pinned staging copy of the tables
+    hipEvent_t copied = nullptr;
+    bool pending = false;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::map<GraphKey, hipGraph_t> graph_defs;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, TickState> g_state;
+
+void drop_graphs(TickState &S) {
+    for (auto &kv : S.graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : S.graph_defs) (void)hipGraphDestroy(kv.second);
+    S.graphs.clear();
+    S.graph_defs.clear();
+}
+
+size_t job_ws_bytes(int N, int K) {
+    const int np = sensor_pieces(K);
+    size_t b = align256(weight_ws_bytes(N));
+    if (np > 1) b += align256((size_t)np * N * sizeof(float));
+    return b;
+}
+
+}  // namespace
+
+size_t tick_job_bytes(int N, int K) { return job_ws_bytes(N, K); }
+
+mcl_status check_job(const mcl_filter_job &J, int j) {
+    std::string at = "tick: job " + std::to_string(j) + ": ";
+    if (!J.map) return fail(MCL_EINVAL, at + "NULL map");
+    if (!J.poses || !J.logw || !J.wq || !J.idx) return fail(MCL_EINVAL, at + "NULL poses, logw, wq or idx");
+    if (J.K < 0 || J.N < 1) return fail(MCL_EINVAL, at + "need K >= 0 and N >= 1");
+    if (J.K > MCL_MAX_POINTS || J.N > MCL_MAX_PARTICLES) return fail(MCL_ERANGE, at + "K or N above the limit");
+    if (J.K > 0 && !J.points) return fail(MCL_EINVAL, at + "NULL points with K > 0");
+    if (!(std::isfinite(J.sigma) && J.sigma > 0.0f)) return fail(MCL_EINVAL, at + "sigma must be finite and > 0");
+    return MCL_OK;
+}
+
+}  // namespace mcl
+
+using namespace mcl;
+
+extern "C" size_t mcl_job_bytes(int32_t N, int32_t K) {
+    if (N < 1 || K < 0) return 0;
+    // caller buffers: poses in + out, logw, w, wq, idx, scan; then library workspace
+    size_t caller = (size_t)N * (48 + 48 + 4 + 8 + 8 + 4) + (size_t)K * 12;
+    return caller + tick_job_bytes(N, K) + sizeof(SensorJob) + sizeof(WeightJob);
+}
+
+extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32_t flags, void *stream_) {
+    if (!jobs || n_jobs < 1) return fail(MCL_EINVAL, "tick: need at least one job");
+    if (n_jobs > kMaxJobs) return fail(MCL_ERANGE, "tick: more jobs than MCL_MAX_JOBS");
+    for (int j = 0; j < n_jobs; ++j) {
+        mcl_status st = check_job(jobs[j], j);
+        if (st != MCL_OK) return st;
+    }
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const bool use_graph = (flags & MCL_TICK_GRAPH) != 0;
+    if (use_graph && stream == nullptr) return fail(MCL_EINVAL, "tick: graph replay needs a non-default stream");
+
+    // storage-type groups: one sensor launch per type present
+    std::vector<int> order(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].map->dtype < jobs[b].map->dtype; });
+    int g_begin[kGroups + 1] = {0, 0, 0, 0};
+    for (int g = 0; g < kGroups; ++g) {
+        int c = 0;
+        for (int j = 0; j < n_jobs; ++j) c += jobs[j].map->dtype == g;
+        g_begin[g + 1] = g_begin[g] + c;
+    }
+    int mask = 0;
+    for (int g = 0; g < kGroups; ++g) mask |= (g_begin[g + 1] > g_begin[g]) << g;
+
+    size_t need = kTablesBytes;
+    for (int j = 0; j < n_jobs; ++j) need += job_ws_bytes(jobs[j].N, jobs[j].K);
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MCL_EDEVICE, "tick: no device");
+    std::lock_guard<std::mutex> lk(g_mu);
+    TickState &S = g_state[{dev, stream}];
+    if (!S.host) {
+        if (hipHostMalloc((void **)&S.host, kTablesBytes, hipHostMallocDefault) != hipSuccess)
+            return fail(MCL_ENOMEM, "tick: pinned staging allocation failed");
+        if (hipEventCreateWithFlags(&S.copied, hipEventDisableTiming) != hipSuccess)
+            return fail(MCL_EDEVICE, "tick: event creation failed");
+    }
+    if (S.dev_bytes < need) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return fail(MCL_EDEVICE, "tick: synchronisation failed");
+        drop_graphs(S);
+        if (S.dev) (void)hipFree(S.dev);
+        S.dev = nullptr;
+        S.dev_bytes = 0;
+        size_t want = need + need / 4;
+        if (hipMalloc((void **)&S.dev, want) != hipSuccess) return fail(MCL_ENOMEM, "tick: workspace allocation failed");
+        S.dev_bytes = want;
+    }
+    // the previous tick's table copy must have left the staging buffer
+    if (S.pending && hipEventSynchronize(S.copied) != hipSuccess) return fail(MCL_EDEVICE, "tick: event wait failed");
+
+    Counts *cnt = reinterpret_cast<Counts *>(S.host);
+    WeightJob *wtbl = reinterpret_cast<WeightJob *>(S.host + kWeightTblOff);
+    std::memset(cnt, 0, kCountsBytes);
+    char *ws = S.dev + kTablesBytes;
+    bool combine[kGroups] = {false, false, false};
+    int64_t wblk = 0, welem = 0;
+    for (int g = 0; g < kGroups; ++g) {
+        int64_t items = 0, elems = 0;
+        SensorJob *stbl = reinterpret_cast<SensorJob *>(S.host + kSensorTblOff + g * kSensorTblBytes) - g_begin[g];
+        for (int s = g_begin[g]; s < g_begin[g + 1]; ++s) {
+            const mcl_filter_job &F = jobs[order[s]];
+            const mcl_map_s *m = F.map;
+            const double sc = m->scale, sg = (double)F.sigma;
+            const float c = (float)((sc * sc) / (2.0 * sg * sg));
+            const int np = sensor_pieces(F.K);
+            WeightJob &W = wtbl[s];
+            std::memset(&W, 0, sizeof W);
+            W.N = F.N;
+            bind_weight_ws(W, ws);
+            ws += align256(weight_ws_bytes(F.N));
+            float *part = nullptr;
+            if (np > 1) {
+                part = reinterpret_cast<float *>(ws);
+                ws += align256((size_t)np * F.N * sizeof(float));
+                combine[g] = true;
+            }
+            SensorJob &J = stbl[s];
+            J = make_sensor_job(m, F.points, F.K, F.poses, F.N, c, F.logw, part);
+            J.item0 = items;
+            J.elem0 = elems;
+            items += (int64_t)J.ngroups * J.npiece;
+            elems += F.N;
+            W.logw = F.logw;
+            W.w = F.w;
+            W.wq = F.wq;
+            W.log_z = F.log_z;
+            W.idx = F.idx;
+            W.pin = F.poses_out ? F.poses : nullptr;
+            W.pout = F.poses_out;
+            W.u = F.u;
+            W.elem0 = welem;
+            W.blk0 = (int32_t)wblk;
+            welem += F.N;
+            wblk += W.nblk;
+        }
+        cnt[g] = Counts{g_begin[g + 1] - g_begin[g], items, elems, 0};
+    }
+    cnt[kGroups] = Counts{n_jobs, 0, welem, wblk};
+
+    bool ok = hipMemcpyAsync(S.dev, S.host, kCountsBytes, hipMemcpyHostToDevice, stream) == hipSuccess;
+    for (int g = 0; g < kGroups && ok; ++g) {
+        const size_t off = kSensorTblOff + g * kSensorTblBytes;
+        const size_t n = (size_t)(g_begin[g + 1] - g_begin[g]) * sizeof(SensorJob);
+        if (n) ok = hipMemcpyAsync(S.dev + off, S.host + off, n, hipMemcpyHostToDevice, stream) == hipSuccess;
+    }
+    ok = ok && hipMemcpyAsync(S.dev + kWeightTblOff, S.host + kWeightTblOff, (size_t)n_jobs * sizeof(WeightJob),
+                              hipMemcpyHostToDevice, stream) == hipSuccess;
+    if (!ok || hipEventRecord(S.copied, stream) != hipSuccess) return fail(MCL_EDEVICE, "tick: table copy failed");
+    S.pending = true;
+
+    // One launch chain for every tick: sizes come from the device tables.
+    int big = 0;
+    for (int j = 1; j < n_jobs; ++j)
+        if ((int64_t)jobs[j].N * jobs[j].K > (int64_t)jobs[big].N * jobs[big].K) big = j;
+    LaunchCfg cfg = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
+    if (use_graph && cfg.blocks_per_cu == 0) cfg.blocks_per_cu = 8;  // the grid must not depend on the job set
+    const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
+    const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
+    auto chain = [&]() -> mcl_status {
+        for (int g = 0; g < kGroups; ++g) {
+            if (!(mask >> g & 1)) continue;
+            JobTable<SensorJob> src{reinterpret_cast<const SensorJob *>(S.dev + kSensorTblOff + g * kSensorTblBytes),
+                                    dcnt + g};
+            // under a graph every group may combine (a job with one piece is skipped inside)
+            mcl_status st = launch_sensor_src(g, src, use_graph ? (int64_t)1 << 40 : cnt[g].items, cnt[g].elems,
+                                              use_graph || combine[g], cfg, stream);
+            if (st != MCL_OK) return st;
+        }
+        JobTable<WeightJob> wsrc{dwt, dcnt + kGroups};
+        mcl_status st = launch_normalize_src(wsrc, use_graph ? kMaxJobs : n_jobs, use_graph ? (int64_t)1 << 40 : wblk,
+                                             use_graph ? (int64_t)1 << 40 : welem, stream);
+        if (st != MCL_OK) return st;
+        return launch_resample_src(wsrc, use_graph ? (int64_t)1 << 40 : wblk, use_graph ? (int64_t)1 << 40 : welem,
+                                   stream);
+    };
+    if (!use_graph) return chain();
+
+    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu};
+    auto it = S.graphs.find(key);
+    if (it == S.graphs.end()) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(MCL_EDEVICE, "tick: stream capture failed to begin");
+        mcl_status st = chain();
+        hipError_t e = hipStreamEndCapture(stream, &graph);
+        if (st != MCL_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(MCL_EDEVICE, "tick: graph capture or instantiation failed");
+        }
+        S.graph_defs[key] = graph;
+        it = S.graphs.emplace(key, exec).first;
+    }
+    if (hipGraphLaunch(it->second, stream) != hipSuccess) return fail(MCL_EDEVICE, "tick: graph launch failed");
+    return MCL_OK;
+}

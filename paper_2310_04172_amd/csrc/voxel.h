@@ -47,7 +47,7 @@ __device__ inline float grid_coord(float a0, float a1, float a2, float b, float 
 // use them (voxel_offset replaces the address by the sentinel's).
 __device__ inline bool voxel_ijk(const MapView &m, float gx, float gy, float gz, uint32_t &ix,
                                  uint32_t &iy, uint32_t &iz) {
-    bool ok = (__float_as_uint(gx) < m.bx) & (__float_as_uint(gy) < m.by) & (__float_as_uint(gz) < m.bz);
+    bool ok = (int)(__float_as_uint(gx) < m.bx) & (int)(__float_as_uint(gy) < m.by) & (int)(__float_as_uint(gz) < m.bz);
     ix = (uint32_t)(int)gx;
     iy = (uint32_t)(int)gy;
     iz = (uint32_t)(int)gz;

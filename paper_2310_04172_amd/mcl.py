@@ -24,6 +24,8 @@ _P = C.c_void_p
 _I = C.c_int32
 
 MCL_OK, MCL_EINVAL, MCL_ENOMEM, MCL_EDEVICE, MCL_ERANGE = 0, -1, -2, -3, -4
+MAX_JOBS = 4096
+TICK_GRAPH = 1
 MAX_PARTICLES = 1 << 21
 MAX_POINTS = 1 << 20
 WQ_SHIFT = 42
@@ -35,15 +37,30 @@ class MapDesc(C.Structure):
                 ("origin", C.c_float * 3), ("tau", C.c_float), ("dtype", C.c_int32)]
 
 
+class FilterJob(C.Structure):
+    _fields_ = [("map", _P), ("points", _P), ("K", C.c_int32), ("poses", _P), ("N", C.c_int32),
+                ("sigma", C.c_float), ("logw", _P), ("w", _P), ("wq", _P), ("log_z", _P), ("u", C.c_uint64),
+                ("idx", _P), ("poses_out", _P)]
+
+
+class LaunchConfig(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
 _lib.mcl_map_upload.argtypes = [C.POINTER(MapDesc), _P, _P, C.POINTER(_P)]
 _lib.mcl_map_free.argtypes = [_P]
 _lib.mcl_sensor_update.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
 _lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, _P, _P, _P, _P]
 _lib.mcl_debug_voxel_indices.argtypes = [_P, _P, _I, _P, _I, _P, _P]
+_lib.mcl_tick.argtypes = [C.POINTER(FilterJob), _I, _I, _P]
+_lib.mcl_job_bytes.argtypes = [_I, _I]
+_lib.mcl_job_bytes.restype = C.c_size_t
+_lib.mcl_autotune.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P, C.POINTER(LaunchConfig)]
+_lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_last_error.restype = C.c_char_p
 for _f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
-           "mcl_debug_voxel_indices"):
+           "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config"):
     getattr(_lib, _f).restype = C.c_int32
 
 
@@ -185,3 +202,70 @@ def score_const(m: Map, sigma: float) -> float:
     s = 1.0 if m.dtype == "f32" else float(np.float32(m.tau)) / Q
     sg = float(np.float32(sigma))
     return float(np.float32((s * s) / (2.0 * sg * sg)))
+
+
+class Filter:
+    """Device buffers of one filter for a batched tick (see include/mcl.h, mcl_tick).
+
+    poses, poses_out: [12, N] float32; points: [3, K] float32 or None.  Output
+    buffers are allocated here unless given.
+    """
+
+    def __init__(self, m: Map, points, poses, sigma: float, u: int, want_w: bool = True, resample_poses: bool = True):
+        import torch
+        self.map = m
+        self.points = points
+        self.poses = poses
+        self.sigma = float(sigma)
+        self.u = int(u)
+        N = poses.shape[1]
+        dev = poses.device
+        self.logw = torch.empty(N, dtype=torch.float32, device=dev)
+        self.w = torch.empty(N, dtype=torch.float64, device=dev) if want_w else None
+        self.wq = torch.empty(N, dtype=torch.uint64, device=dev)
+        self.log_z = torch.empty(1, dtype=torch.float64, device=dev)
+        self.idx = torch.empty(N, dtype=torch.int32, device=dev)
+        self.poses_out = torch.empty_like(poses) if resample_poses else None
+
+    @property
+    def N(self):
+        return self.poses.shape[1]
+
+    @property
+    def K(self):
+        return 0 if self.points is None else self.points.shape[1]
+
+    def job(self) -> FilterJob:
+        import torch
+        _dev(self.poses, torch.float32, (12, self.N), "poses")
+        if self.K:
+            _dev(self.points, torch.float32, (3, self.K), "points")
+        return FilterJob(self.map.handle, _ptr(self.points) if self.K else None, self.K, _ptr(self.poses), self.N,
+                         self.sigma, _ptr(self.logw), _ptr(self.w), _ptr(self.wq), _ptr(self.log_z),
+                         self.u & (2 ** 64 - 1), _ptr(self.idx), _ptr(self.poses_out))
+
+
+def tick(filters, graph: bool = False, stream=None):
+    """One batched update (sensor, normalise, resample) of every filter."""
+    arr = (FilterJob * len(filters))(*[f.job() for f in filters])
+    _check(_lib.mcl_tick(arr, len(filters), TICK_GRAPH if graph else 0, _stream(stream)), "mcl_tick")
+
+
+def job_bytes(N: int, K: int) -> int:
+    return int(_lib.mcl_job_bytes(N, K))
+
+
+def autotune(m: Map, points, poses, sigma: float, stream=None):
+    import torch
+    N, K = poses.shape[1], points.shape[1]
+    scratch = torch.empty(N, dtype=torch.float32, device=poses.device)
+    best = LaunchConfig()
+    _check(_lib.mcl_autotune(m.handle, _ptr(points), K, _ptr(poses), N, float(sigma), _ptr(scratch),
+                             _stream(stream), C.byref(best)), "mcl_autotune")
+    return best.waves_per_block, best.blocks_per_cu
+
+
+def set_launch_config(dtype: str, K: int, N: int, cfg=None):
+    """cfg = (waves_per_block, blocks_per_cu), or None to clear."""
+    c = None if cfg is None else C.byref(LaunchConfig(*cfg))
+    _check(_lib.mcl_set_launch_config(DTYPE_CODE[dtype], K, N, c), "mcl_set_launch_config")

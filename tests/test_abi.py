@@ -26,7 +26,8 @@ def mcl():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
-              "mcl_debug_voxel_indices", "mcl_last_error"):
+              "mcl_debug_voxel_indices", "mcl_last_error", "mcl_tick", "mcl_job_bytes", "mcl_autotune",
+              "mcl_set_launch_config"):
         assert f in names
 
 
@@ -59,3 +60,23 @@ def test_argument_errors_are_reported_on_the_host(mcl):
     assert lib.mcl_map_upload(C.byref(d), fake, None, C.byref(h)) == mcl.MCL_EINVAL
     d = mcl.MapDesc(65536, 65536, 4096, 0.1, (C.c_float * 3)(0, 0, 0), 0.3, 0)
     assert lib.mcl_map_upload(C.byref(d), fake, None, C.byref(h)) == mcl.MCL_ERANGE
+
+
+def test_tick_and_tuning_argument_errors(mcl):
+    lib = mcl.lib()
+    P = C.c_void_p
+    assert lib.mcl_tick(None, 1, 0, None) == mcl.MCL_EINVAL
+    jobs = (mcl.FilterJob * 2)()
+    jobs[0] = mcl.FilterJob(P(0x1000), P(0x2000), 10, P(0x3000), 10, 0.1, P(0x4000), None, P(0x5000), None, 7,
+                            P(0x6000), None)
+    jobs[1] = mcl.FilterJob(P(0x1000), P(0x2000), 10, P(0x3000), 10, -1.0, P(0x4000), None, P(0x5000), None, 7,
+                            P(0x6000), None)
+    assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL
+    assert b"job 1" in lib.mcl_last_error()
+    assert lib.mcl_tick(jobs, mcl.MAX_JOBS + 1, 0, None) == mcl.MCL_ERANGE
+    assert lib.mcl_job_bytes(0, 5) == 0
+    assert lib.mcl_job_bytes(1000, 28800) > 1000 * 120
+    bad = mcl.LaunchConfig(3, 0)
+    assert lib.mcl_set_launch_config(0, 1000, 1000, C.byref(bad)) == mcl.MCL_EINVAL
+    assert lib.mcl_set_launch_config(5, 1000, 1000, None) == mcl.MCL_EINVAL
+    assert lib.mcl_autotune(None, None, 0, None, 0, 0.1, None, None, None) == mcl.MCL_EINVAL

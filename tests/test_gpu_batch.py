@@ -1,0 +1,154 @@
+"""Batched tick (mcl_tick), graph replay and launch-shape tuning, through the C ABI.
+
+The contract: every filter in a tick gets bit for bit the results of the three
+single-filter calls, eagerly or replayed from a captured graph, and no launch
+shape changes any result.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from tests.helpers import make_map, poses_from, random_rotations
+from workloads import configs
+from workloads.tsdf import f32
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "a GPU is required"
+    return t
+
+
+@pytest.fixture(scope="module")
+def mcl():
+    from paper_2310_04172_amd import mcl as m
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def small_map(rng, dtype, dims=(40, 36, 20), v=0.1):
+    nx, ny, nz = dims
+    if dtype == "f32":
+        vals = rng.uniform(-0.3, 0.3, size=(nz, ny, nx)).astype(np.float32)
+        vals[:, :, : nx // 2] = 0.3
+    else:
+        lim = 32767 if dtype == "i16" else 127
+        vals = rng.integers(-lim, lim + 1, size=(nz, ny, nx)).astype(np.int16 if dtype == "i16" else np.int8)
+        vals[:, :, : nx // 2] = lim
+    return make_map(vals, v, origin=(-0.5, 0.25, -0.1), tau=0.3, dtype=dtype)
+
+
+def job_set(torch, mcl, seed, maps, specs):
+    rng = np.random.default_rng(seed)
+    filters = []
+    for (mi, N, K) in specs:
+        tmap, m = maps[mi]
+        ext = np.array(tmap.dims) * tmap.voxel
+        poses = poses_from(random_rotations(rng, N), rng.uniform(0, 1, (N, 3)) * ext)
+        pts = rng.normal(0, 0.3 * ext.mean(), size=(3, K)).astype(np.float32) if K else None
+        f = mcl.Filter(m, dev(torch, pts) if K else None, dev(torch, poses), f32(0.1 + 0.05 * mi),
+                       int(rng.integers(0, 2 ** 63)))
+        filters.append(f)
+    return filters
+
+
+def single(torch, mcl, f):
+    lw = mcl.sensor_update(f.map, f.points, f.poses, f.sigma)
+    w, wq, lz = mcl.normalize(lw)
+    idx, pout = mcl.resample(wq, f.u, f.poses)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in (lw, w, wq, lz, idx, pout)]
+
+
+def outputs(torch, f):
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in (f.logw, f.w, f.wq, f.log_z, f.idx, f.poses_out)]
+
+
+def assert_same(a, b, what):
+    names = ("logw", "w", "wq", "log_z", "idx", "poses_out")
+    for n, x, y in zip(names, a, b):
+        assert x.dtype == y.dtype and np.array_equal(x.view(np.uint8), y.view(np.uint8)), f"{what}: {n} differs"
+
+
+@pytest.fixture(scope="module")
+def maps(torch, mcl):
+    rng = np.random.default_rng(1)
+    out = []
+    for dtype in ("i16", "i8", "f32", "i16"):
+        t = small_map(rng, dtype)
+        out.append((t, mcl.Map.from_tsdf(t)))
+    return out
+
+
+SPECS = [(0, 1, 1), (1, 63, 1025), (2, 65, 9000), (0, 1000, 5000), (3, 130, 0), (1, 5000, 4096),
+         (2, 7, 4097), (0, 4097, 300), (3, 2000, 12000)]
+
+
+def test_tick_matches_single_calls(torch, mcl, maps):
+    say("case: tick eager vs single calls, mixed storage types")
+    filters = job_set(torch, mcl, 3, maps, SPECS)
+    mcl.tick(filters)
+    got = [outputs(torch, f) for f in filters]
+    for i, f in enumerate(filters):
+        assert_same(got[i], single(torch, mcl, f), f"job {i} (N={f.N}, K={f.K})")
+
+
+def test_tick_graph_replay(torch, mcl, maps):
+    """A captured chain replays correctly for new job contents and a different
+    job count, with eager work and synchronisation between replays."""
+    say("case: tick graph replay")
+    s = torch.cuda.Stream()
+    for rep, (seed, specs) in enumerate([(10, SPECS), (11, SPECS[::-1]), (12, SPECS[2:7]), (13, SPECS)]):
+        filters = job_set(torch, mcl, seed, maps, specs)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            mcl.tick(filters, graph=True, stream=s)
+        s.synchronize()
+        got = [outputs(torch, f) for f in filters]
+        # eager work on the default stream between replays
+        _ = torch.ones(1 << 20, device="cuda").sum().item()
+        for i, f in enumerate(filters):
+            assert_same(got[i], single(torch, mcl, f), f"replay {rep} job {i}")
+
+
+def test_launch_shapes_are_bit_identical(torch, mcl):
+    say("case: launch shapes")
+    w = configs.config1()
+    m = mcl.Map.from_tsdf(w.tmap)
+    P, X = dev(torch, w.poses), dev(torch, w.points)
+    ref = mcl.sensor_update(m, X, P, w.sigma).cpu().numpy()
+    try:
+        for wpb in (2, 4, 8):
+            for bpc in (0, 1, 2, 8, 32):
+                mcl.set_launch_config("i16", w.K, w.N, (wpb, bpc))
+                got = mcl.sensor_update(m, X, P, w.sigma).cpu().numpy()
+                assert np.array_equal(got, ref), (wpb, bpc)
+        best = mcl.autotune(m, X, P, w.sigma)
+        assert best[0] in (2, 4, 8) and best[1] in (0, 2, 4, 8, 16)
+        assert np.array_equal(mcl.sensor_update(m, X, P, w.sigma).cpu().numpy(), ref)
+    finally:
+        mcl.set_launch_config("i16", w.K, w.N, None)
+
+
+def test_tick_alone_equals_in_mix(torch, mcl, maps):
+    """A filter gives the same bits alone and inside a larger batch."""
+    say("case: alone vs mix")
+    filters = job_set(torch, mcl, 21, maps, SPECS)
+    mcl.tick(filters)
+    mixed = [outputs(torch, f) for f in filters]
+    for i in (0, 3, 8):
+        mcl.tick([filters[i]])
+        assert_same(outputs(torch, filters[i]), mixed[i], f"job {i} alone")
