@@ -11,6 +11,10 @@ Prints one JSON line.  `value` is particle-point evaluations per second
 (G/s) over whole steps; `roofline` describes the dominant kernel (the sensor
 update) measured with HIP events on its stream; `cpu_baseline` times the CPU
 oracle on a bounded particle sample of the same workload.
+
+Other workloads (not the default line): --workload small (1,000 particles in a
+small office map), --workload batched (64 filters: sequential single-filter
+calls vs one batched tick, eager and graph-replayed).
 """
 
 from __future__ import annotations
@@ -28,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "particle-point evals/s (G/s) + p99 update latency, batched/served vs plain"
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk
 
 
 def log(*a):
@@ -66,27 +72,23 @@ def cpu_baseline(w, target_s: float = 10.0) -> dict:
             "sample": f"{n} of {w.N} particles x {w.K} points (sensor update + normalise + resample), {dt:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calib-mib", type=int, default=0,
-                    help="after timing, run one plain device copy of this size (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is a design "
-                                   "(particles split across GPUs), not implemented", "n_gpus": args.gpus}))
-        sys.exit(2)
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
+
+def base_record(args, metric, value, ms_step, config, dtype="f32"):
+    return {"metric": metric, "value": value, "unit": "G particle-point evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic (seeded procedural scenes, raycast LiDAR-shaped scans, sampled particles)",
+            "config": config}
+
+
+def run_single(args, w, workload_key, with_roofline=True):
+    """A plain single-filter update: sensor update + normalise + resample, timed."""
     import torch
     from paper_2310_04172_amd import mcl
-    from workloads import configs
 
-    t0 = time.perf_counter()
-    w = configs.config2()
-    log(f"workload built in {time.perf_counter() - t0:.1f} s: N={w.N} K={w.K}")
     dev = torch.device("cuda:0")
     m = mcl.Map.from_tsdf(w.tmap)
     pts = torch.from_numpy(w.points).to(dev)
@@ -98,7 +100,8 @@ def main():
     idx = torch.empty(N, dtype=torch.int32, device=dev)
     poses_out = torch.empty_like(poses)
     stream = torch.cuda.current_stream()
-
+    if args.autotune:
+        log(f"autotuned launch shape: {mcl.autotune(m, pts, poses, w.sigma)}")
     ev = []
 
     def step(timed: bool):
@@ -115,16 +118,18 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
+    lat = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        t1 = time.perf_counter()
         step(True)
+        torch.cuda.synchronize()   # per-update latency: launch to resampled particles ready
+        lat.append((time.perf_counter() - t1) * 1e3)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt / args.steps * 1e3
     evals = N * K
     sensor_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    algo_bytes = evals * 2 + N * (48 + 4) + K * 12   # int16 TSDF read per eval, pose in, logw out, scan
-    achieved = algo_bytes / (sensor_ms * 1e-3) / 1e9
     log(f"step {ms_step:.3f} ms, sensor kernel {sensor_ms:.3f} ms")
     if args.copy_calib_mib:
         n = args.copy_calib_mib * (1 << 20) // 4
@@ -135,30 +140,113 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.copy_calib_mib} MiB read + {args.copy_calib_mib} MiB written")
         del src, dst
+    out = base_record(args, METRIC,
+                      evals / (ms_step * 1e-3) / 1e9, ms_step,
+                      {"workload": w.name, "N": N, "K": K, "map_dtype": w.tmap.dtype,
+                       "step": "sensor update + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
+                       "workload_key": workload_key, "sensor_update_ms": sensor_ms})
+    out["latency_ms"] = {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}
+    if with_roofline:
+        flops = 20.0 * evals   # 9 mul + 9 add transform, 1 mul + 1 add score, per evaluation
+        achieved = flops / (sensor_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                           "kernel": "sensor_kernel", "algorithmic_flops_per_launch": flops,
+                           "algorithmic_tsdf_bytes_per_launch": 2.0 * evals}
+    return out
 
-    out = {
-        "metric": "particle-point evals/s (G/s), plain single-filter global localisation",
-        "value": evals / (ms_step * 1e-3) / 1e9,
-        "unit": "G particle-point evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded procedural warehouse, raycast VLP-16-shaped scan, uniform particles)",
-        "config": {"workload": w.name, "N": N, "K": K, "map": "1024x1024x128 int16, 0.05 m, tau 0.15 m",
-                   "step": "sensor update + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
-                   "sensor_update_ms": sensor_ms},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sensor_kernel<int16_t>",
-                     "algorithmic_bytes_per_launch": algo_bytes},
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+
+def run_batched(args):
+    """64 filters on one map: sequential plain calls vs one tick (eager, and graph-replayed)."""
+    import torch
+    from paper_2310_04172_amd import mcl
+    from workloads import configs
+
+    t0 = time.perf_counter()
+    tmap, specs = configs.config4(n_scale=args.batch_scale)
+    log(f"batched workload built in {time.perf_counter() - t0:.1f} s: {len(specs)} filters, "
+        f"sum N {sum(f.N for f in specs)}")
+    dev = torch.device("cuda:0")
+    m = mcl.Map.from_tsdf(tmap)
+    filters = [mcl.Filter(m, torch.from_numpy(f.points).to(dev), torch.from_numpy(f.poses).to(dev), f.sigma, f.u,
+                          want_w=False) for f in specs]
+    evals = sum(f.N * f.K for f in specs)
+    big = max(range(len(filters)), key=lambda i: specs[i].N * specs[i].K)
+    if args.autotune:
+        log(f"autotuned launch shape: {mcl.autotune(m, filters[big].points, filters[big].poses, specs[big].sigma)}")
+    side = torch.cuda.Stream()
+
+    def plain():
+        for f in filters:
+            mcl.sensor_update(m, f.points, f.poses, f.sigma, f.logw)
+            mcl.normalize(f.logw, None, f.wq, f.log_z, want_w=False)
+            mcl.resample(f.wq, f.u, f.poses, f.poses_out, f.idx)
+
+    def eager():
+        mcl.tick(filters)
+
+    def graph():
+        with torch.cuda.stream(side):
+            mcl.tick(filters, graph=True, stream=side)
+
+    def timed(fn, sync_stream=None):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t1) * 1e3)
+        return (time.perf_counter() - t0) / args.steps * 1e3, lat
+
+    ms_plain, lat_plain = timed(plain)
+    ms_eager, lat_eager = timed(eager)
+    ms_graph, lat_graph = timed(graph)
+    log(f"plain {ms_plain:.2f} ms, tick eager {ms_eager:.2f} ms, tick graph {ms_graph:.2f} ms")
+    out = base_record(args, METRIC + " [batched 64-filter tick, graph-replayed]",
+                      evals / (ms_graph * 1e-3) / 1e9, ms_graph,
+                      {"workload": "batched: 64 filters on the 1024x1024x128@0.05m int16 warehouse, N log-uniform "
+                                   "[2048, 524288], scans alternating 16x1800 / 64x1024",
+                       "filters": len(specs), "sum_N": int(sum(f.N for f in specs)), "evals_per_tick": int(evals)})
+    out["latency_ms"] = {"p50": percentile(lat_graph, 50), "p99": percentile(lat_graph, 99)}
+    out["vs_plain"] = {"plain_sequential": {"value": evals / (ms_plain * 1e-3) / 1e9, "ms": ms_plain,
+                                            "p50_ms": percentile(lat_plain, 50), "p99_ms": percentile(lat_plain, 99)},
+                       "tick_eager": {"value": evals / (ms_eager * 1e-3) / 1e9, "ms": ms_eager},
+                       "throughput_gain_vs_plain": ms_plain / ms_graph}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="global", choices=["global", "small", "batched"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="tune the sensor kernel's launch shape first")
+    ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the batched workload's particle counts")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this size (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is a design "
+                                   "(particles split across GPUs), not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    from workloads import configs
+
+    if args.workload == "batched":
+        out = run_batched(args)
+    else:
+        t0 = time.perf_counter()
+        w = configs.config2() if args.workload == "global" else configs.config1()
+        log(f"workload built in {time.perf_counter() - t0:.1f} s: N={w.N} K={w.K}")
+        out = run_single(args, w, args.workload)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 
 

@@ -57,6 +57,21 @@ struct WeightJob {
 };
 
 // ------------------------------------------------------------ job sources
+// Copy a wave-uniform descriptor out of memory into scalar registers: every
+// lane reads the same words, readfirstlane makes the copy provably uniform.
+template <typename T>
+__device__ __attribute__((always_inline)) inline T load_uniform(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor size must be a multiple of 4");
+    union {
+        T v;
+        int w[sizeof(T) / 4];
+    } u;
+    const int *q = reinterpret_cast<const int *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) u.w[i] = __builtin_amdgcn_readfirstlane(q[i]);
+    return u.v;
+}
+
 // Totals of a launch: jobs, sensor work items, particles, weight blocks.
 struct Counts {
     int64_t njobs, items, elems, blocks;
@@ -67,6 +82,7 @@ struct OneJob {
     J job;
     Counts n;
     __device__ const J &get(int) const { return job; }
+    __device__ J load(int) const { return job; }
     __device__ int count() const { return 1; }
     __device__ int64_t items() const { return n.items; }
     __device__ int64_t elems() const { return n.elems; }
@@ -80,13 +96,16 @@ struct JobTable {
     const J *jobs;
     const Counts *n;
     __device__ const J &get(int j) const { return jobs[j]; }
+    __device__ J load(int j) const { return load_uniform(jobs + j); }
     __device__ int count() const { return (int)n->njobs; }
     __device__ int64_t items() const { return n->items; }
     __device__ int64_t elems() const { return n->elems; }
     __device__ int64_t blocks() const { return n->blocks; }
 };
 
-// Index of the last job whose key(job) <= x (jobs sorted by key); wave-uniform.
+// Index of the last job whose key(job) <= x (jobs sorted by key), per lane:
+// for element-indexed work, where lanes of one wave may belong to different
+// jobs.
 template <typename Src, typename Key>
 __device__ inline int find_job(const Src &src, int64_t x, Key key) {
     int lo = 0, hi = src.count() - 1;
@@ -96,6 +115,22 @@ __device__ inline int find_job(const Src &src, int64_t x, Key key) {
         else hi = mid - 1;
     }
     return lo;
+}
+
+// The same for an x that is equal on all lanes of the wave (a work item or a
+// block index): the search and its result are provably wave-uniform.
+template <typename Src, typename Key>
+__device__ inline int find_job_uniform(const Src &src, int64_t x, Key key) {
+    int lo = 0, hi = src.count() - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        int64_t k = key(src.get(mid));
+        k = ((int64_t)__builtin_amdgcn_readfirstlane((int)(k >> 32)) << 32) |
+            (uint32_t)__builtin_amdgcn_readfirstlane((int)(k & 0xffffffff));
+        if (k <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
 }
 
 // Launch shape of the sensor kernel; any shape gives bit-identical results.

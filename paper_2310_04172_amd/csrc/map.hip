@@ -163,9 +163,6 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     v.out_off = (uint32_t)data_bytes;
     v.zero_off = (uint32_t)(data_bytes + 64 * es);
     v.cls = reinterpret_cast<const uint8_t *>(static_cast<const char *>(m->dev) + cls_off);
-    v.qf = d.dtype == MCL_TSDF_F32 ? d.tau : (float)m->Q;
-    if (d.dtype == MCL_TSDF_F32) std::memcpy(&v.qraw, &d.tau, 4);
-    else v.qraw = m->Q;
     *out = m;
     return MCL_OK;
 }

@@ -41,8 +41,6 @@ struct MapView {
     uint32_t out_off;        // byte offset of the +Q sentinel brick
     uint32_t zero_off;       // byte offset of the 0 sentinel brick
     const uint8_t *cls;      // device: class byte per brick, indexed by byte offset >> (6 + log2 esize)
-    float qf;                // Q as float (tau for float32 maps)
-    int32_t qraw;            // +Q as the raw register value a gather returns (float bits for float32)
 };
 
 }  // namespace mcl

@@ -74,7 +74,7 @@ constexpr int class_shift() { return 6 + (sizeof(T) == 1 ? 0 : sizeof(T) == 2 ? 
 // Coarse level first: the class byte of each point's brick; only points in
 // bricks with values inside the truncation band read their own fine value.
 template <typename T, bool TAIL>
-__device__ inline float lane_chunk_sum(const MapView &m, const float (&A)[12], const float (&px)[kU],
+__device__ __attribute__((always_inline)) inline float lane_chunk_sum(const MapView &m, const float (&A)[12], const float (&px)[kU],
                                        const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid) {
     uint32_t off[kU];
 #pragma unroll
@@ -112,7 +112,7 @@ __device__ inline float lane_chunk_sum(const MapView &m, const float (&A)[12], c
 }
 
 template <typename T, bool TAIL>
-__device__ inline void chunk_group(const MapView &m, const float (&pa)[12], const float (&px)[kU],
+__device__ __attribute__((always_inline)) inline void chunk_group(const MapView &m, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
                                    int gcount, float &acc) {
     for (int p = 0; p < gcount; ++p) {
@@ -125,10 +125,9 @@ __device__ inline void chunk_group(const MapView &m, const float (&pa)[12], cons
 }
 
 // One work item: particles [64 g, 64 g + 64) of a job against points
-// [4096 piece, 4096 piece + 4096).  Output: l directly (one piece) or the
-// piece's partial sums.
+// [4096 piece, 4096 piece + 4096).  Returns lane p's sum for particle 64 g + p.
 template <typename T>
-__device__ inline void sensor_item(const SensorJob &J, int local, int lane) {
+__device__ __attribute__((always_inline)) inline float sensor_item(const SensorJob &J, int local, int lane) {
     const int group = local / J.npiece;
     const int piece = local - group * J.npiece;
     const int n0 = group * kGroup;
@@ -157,7 +156,16 @@ __device__ inline void sensor_item(const SensorJob &J, int local, int lane) {
         else
             chunk_group<T, true>(m, pa, px, py, pz, lane, nvalid, gcount, acc);
     }
-    if (lane < gcount) {
+    return acc;
+}
+
+// Output of a work item: l directly (one piece) or the piece's partial sums.
+__device__ __attribute__((always_inline)) inline void sensor_store(const SensorJob &J, int local, int lane,
+                                                                   float acc) {
+    const int group = local / J.npiece;
+    const int piece = local - group * J.npiece;
+    const int n0 = group * kGroup;
+    if (lane < min(kGroup, J.N - n0)) {
         if (J.npiece == 1)
             J.logw[n0 + lane] = -(acc * J.c);
         else
@@ -166,17 +174,26 @@ __device__ inline void sensor_item(const SensorJob &J, int local, int lane) {
 }
 
 // Waves stride over the work items of all jobs of the launch (one item per
-// wave for a full grid, several for a persistent one).
+// wave for a full grid, several for a persistent one).  The job descriptor is
+// read into scalar registers per item and read again for the store, so it need
+// not stay live across the item.
 template <typename T, int WPB, typename Src>
-__global__ __launch_bounds__(WPB * 64) void sensor_kernel(Src src) {
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4))) void sensor_kernel(Src src) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nitems = src.items();
     const int64_t stride = (int64_t)gridDim.x * WPB;
     for (int64_t item = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems;
          item += stride) {
-        const int j = find_job(src, item, [](const SensorJob &J) { return J.item0; });
-        const SensorJob &J = src.get(j);
-        sensor_item<T>(J, (int)(item - J.item0), lane);
+        const int j = find_job_uniform(src, item, [](const SensorJob &J) { return J.item0; });
+        float acc;
+        int local;
+        {
+            const SensorJob J = src.load(j);
+            local = (int)(item - J.item0);
+            acc = sensor_item<T>(J, local, lane);
+        }
+        const SensorJob J = src.load(j);
+        sensor_store(J, local, lane, acc);
     }
 }
 

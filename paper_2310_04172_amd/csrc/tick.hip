@@ -41,13 +41,22 @@ static constexpr size_t kTablesBytes = kWeightTblOff + align256(sizeof(WeightJob
 
 namespace {
 
+// A captured chain serves every tick whose totals fit its power-of-two buckets.
 struct GraphKey {
     int mask;
     int wpb, bpc;
+    int64_t items[3], elems, blocks;
     bool operator<(const GraphKey &o) const {
-        return std::tie(mask, wpb, bpc) < std::tie(o.mask, o.wpb, o.bpc);
+        return std::tie(mask, wpb, bpc, items[0], items[1], items[2], elems, blocks) <
+               std::tie(o.mask, o.wpb, o.bpc, o.items[0], o.items[1], o.items[2], o.elems, o.blocks);
     }
 };
+
+int64_t bucket(int64_t x) {
+    int64_t b = 1;
+    while (b < x) b <<= 1;
+    return b;
+}
 
 struct TickState {
     char *dev = nullptr;      // tables + per-job workspace
@@ -212,35 +221,37 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     if (!ok || hipEventRecord(S.copied, stream) != hipSuccess) return fail(MCL_EDEVICE, "tick: table copy failed");
     S.pending = true;
 
-    // One launch chain for every tick: sizes come from the device tables.
+    // The launch chain reads every size from the device tables; grids are sized
+    // for the totals (under a graph, for their power-of-two buckets, so a
+    // replay serves any tick that fits; surplus waves exit at once).
     int big = 0;
     for (int j = 1; j < n_jobs; ++j)
         if ((int64_t)jobs[j].N * jobs[j].K > (int64_t)jobs[big].N * jobs[big].K) big = j;
     LaunchCfg cfg = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
-    if (use_graph && cfg.blocks_per_cu == 0) cfg.blocks_per_cu = 8;  // the grid must not depend on the job set
     const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
     const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
+    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu, {0, 0, 0}, 0, 0};
+    for (int g = 0; g < kGroups; ++g) key.items[g] = use_graph ? bucket(cnt[g].items) : cnt[g].items;
+    key.elems = use_graph ? bucket(welem) : welem;
+    key.blocks = use_graph ? bucket(wblk) : wblk;
     auto chain = [&]() -> mcl_status {
         for (int g = 0; g < kGroups; ++g) {
             if (!(mask >> g & 1)) continue;
             JobTable<SensorJob> src{reinterpret_cast<const SensorJob *>(S.dev + kSensorTblOff + g * kSensorTblBytes),
                                     dcnt + g};
             // under a graph every group may combine (a job with one piece is skipped inside)
-            mcl_status st = launch_sensor_src(g, src, use_graph ? (int64_t)1 << 40 : cnt[g].items, cnt[g].elems,
-                                              use_graph || combine[g], cfg, stream);
+            mcl_status st = launch_sensor_src(g, src, key.items[g], key.elems, use_graph || combine[g], cfg, stream);
             if (st != MCL_OK) return st;
         }
         JobTable<WeightJob> wsrc{dwt, dcnt + kGroups};
-        mcl_status st = launch_normalize_src(wsrc, use_graph ? kMaxJobs : n_jobs, use_graph ? (int64_t)1 << 40 : wblk,
-                                             use_graph ? (int64_t)1 << 40 : welem, stream);
+        mcl_status st = launch_normalize_src(wsrc, use_graph ? kMaxJobs : n_jobs, key.blocks, key.elems, stream);
         if (st != MCL_OK) return st;
-        return launch_resample_src(wsrc, use_graph ? (int64_t)1 << 40 : wblk, use_graph ? (int64_t)1 << 40 : welem,
-                                   stream);
+        return launch_resample_src(wsrc, key.blocks, key.elems, stream);
     };
     if (!use_graph) return chain();
 
-    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu};
     auto it = S.graphs.find(key);
+    if (it == S.graphs.end() && S.graphs.size() >= 32) drop_graphs(S);  // bound the cache
     if (it == S.graphs.end()) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;

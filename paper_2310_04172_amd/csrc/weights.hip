@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kWThreads) void lse_partial_kernel(Src src) {
     __shared__ float shf[kWThreads];
     __shared__ double shd[kWThreads];
     for (int64_t gb = blockIdx.x; gb < nblocks; gb += gridDim.x) {
-        const WeightJob &J = src.get(find_job(src, gb, BlkKey()));
+        const WeightJob &J = src.get(find_job_uniform(src, gb, BlkKey()));
         const int b = (int)(gb - J.blk0);
         const int base = b * kWBlock + threadIdx.x;
         float mx = -INFINITY;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kWThreads) void rs_blocksum_kernel(Src src) {
     const int64_t nblocks = src.blocks();
     __shared__ uint64_t sh[kWThreads];
     for (int64_t gb = blockIdx.x; gb < nblocks; gb += gridDim.x) {
-        const WeightJob &J = src.get(find_job(src, gb, BlkKey()));
+        const WeightJob &J = src.get(find_job_uniform(src, gb, BlkKey()));
         const int b = (int)(gb - J.blk0);
         const int base = b * kWBlock + threadIdx.x;
         uint64_t s = 0;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kWThreads) void rs_scan_kernel(Src src) {
     __shared__ uint64_t sh[kWThreads];
     const int t = threadIdx.x;
     for (int64_t gb = blockIdx.x; gb < nblocks; gb += gridDim.x) {
-        const WeightJob &J = src.get(find_job(src, gb, BlkKey()));
+        const WeightJob &J = src.get(find_job_uniform(src, gb, BlkKey()));
         const int b = (int)(gb - J.blk0);
         uint64_t pre = 0, tot = 0;
         for (int j = t; j < J.nblk; j += kWThreads) {

@@ -231,3 +231,45 @@ def config3(n_particles=262_144, dtype="i16") -> Workload:
 def subset_indices(cfg: int, n_total: int, n_sub: int = 4096) -> np.ndarray:
     """Seeded, sorted particle subset the oracle checks at full size."""
     return np.sort(rng(cfg, 4).choice(n_total, size=min(n_sub, n_total), replace=False))
+
+
+@dataclass
+class FilterSpec:
+    points: np.ndarray            # [3, K] float32
+    poses: np.ndarray             # [12, N] float32
+    sigma: float
+    u: int
+    gt: tuple
+
+    @property
+    def N(self):
+        return self.poses.shape[1]
+
+    @property
+    def K(self):
+        return self.points.shape[1]
+
+
+def config4(n_filters: int = 64, n_scale: float = 1.0):
+    """64 filters on the warehouse map: particle counts log-uniform in
+    [2048, 524288] (scaled by n_scale), even filters VLP-16 16x1800 scans, odd
+    ones OS0-64 64x1024, each from its own ground-truth pose; Gaussian particles
+    below 65,536, uniform over free space above."""
+    sc, tmap = warehouse_map(2)
+    Ns = np.round(np.exp(rng(4, 3).uniform(math.log(2048), math.log(524288), size=n_filters)) * n_scale)
+    Ns = np.maximum(Ns.astype(int), 1)
+    out = []
+    for f in range(n_filters):
+        gxyz, grpy = ground_truth_pose(rng(4, 1, f), sc, (1.0, 1.0), (50.2, 50.2), sc.floor_z)
+        R, t = pose_matrix(gxyz, grpy)
+        if f % 2 == 0:
+            pts = raycast_scan(sc, tmap, R, t, beam_dirs(azimuths=1800, **VLP16), 100.0, 0.03, rng(4, 2, f))
+        else:
+            pts = raycast_scan(sc, tmap, R, t, beam_dirs(azimuths=1024, **OS0_64), 50.0, 0.02, rng(4, 2, f))
+        N = int(Ns[f])
+        if N < 65536:
+            xyz, rpy = gaussian_particles(rng(4, 5, f), gxyz, grpy, N)
+        else:
+            xyz, rpy = free_voxel_particles(rng(4, 5, f), tmap, N)
+        out.append(FilterSpec(pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), draw_u(4, f), (gxyz, grpy)))
+    return tmap, out

@@ -96,45 +96,53 @@ def sphere_sdf(p: np.ndarray, s: np.ndarray) -> np.ndarray:
     return np.sqrt(np.sum((p - s[:3]) ** 2, axis=-1)) - s[3]
 
 
-def _ray_boxes(o, d, boxes, chunk=16):
-    best = np.full(d.shape[0], np.inf)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        inv = 1.0 / d                                     # +-inf on axis-parallel rays
-    for s in range(0, len(boxes), chunk):
-        b = boxes[s:s + chunk]
-        t1 = (b[None, :, :3] - o) * inv[:, None, :]
-        t2 = (b[None, :, 3:] - o) * inv[:, None, :]
-        # an axis-parallel ray outside a slab gives nan (0*inf); treat as a miss
-        tmin = np.where(np.isnan(t1) | np.isnan(t2), np.inf, np.minimum(t1, t2))
-        tmax = np.where(np.isnan(t1) | np.isnan(t2), -np.inf, np.maximum(t1, t2))
-        t_enter = tmin.max(axis=2)
-        t_exit = tmax.min(axis=2)
-        hit = (t_enter <= t_exit) & (t_enter >= 0)
-        best = np.minimum(best, np.where(hit, t_enter, np.inf).min(axis=1))
-    return best
+def _ray_boxes(o, d, boxes, chunk=8192):
+    """Slab test of every ray against every box (float64, torch CPU threads)."""
+    import torch
+    O = torch.as_tensor(o, dtype=torch.float64)
+    B = torch.as_tensor(boxes, dtype=torch.float64)
+    lo, hi = B[:, :3] - O, B[:, 3:] - O                     # [nb, 3]
+    out = np.empty(d.shape[0])
+    for s in range(0, d.shape[0], chunk):
+        D = torch.as_tensor(d[s:s + chunk], dtype=torch.float64)
+        inv = 1.0 / D                                          # +-inf on axis-parallel rays
+        t1 = lo[None] * inv[:, None]                           # [r, nb, 3]
+        t2 = hi[None] * inv[:, None]
+        bad = torch.isnan(t1) | torch.isnan(t2)                # 0*inf: axis-parallel ray outside a slab
+        tmin = torch.where(bad, torch.inf, torch.minimum(t1, t2)).amax(dim=2)
+        tmax = torch.where(bad, -torch.inf, torch.maximum(t1, t2)).amin(dim=2)
+        hit = (tmin <= tmax) & (tmin >= 0)
+        out[s:s + chunk] = torch.where(hit, tmin, torch.inf).amin(dim=1).numpy()
+    return out
 
 
-def _ray_cylinders(o, d, cyl):
-    cx, cy, r, z0, z1 = (cyl[:, i][None, :] for i in range(5))
-    ox, oy = o[0] - cx, o[1] - cy
-    dx, dy, dz = d[:, 0:1], d[:, 1:2], d[:, 2:3]
-    a = dx * dx + dy * dy
-    b = 2.0 * (ox * dx + oy * dy)
-    c = ox * ox + oy * oy - r * r
-    disc = b * b - 4 * a * c
-    with np.errstate(divide="ignore", invalid="ignore"):
-        t = (-b - np.sqrt(disc)) / (2 * a)
-    z = o[2] + t * dz
-    ok = (disc >= 0) & (a > 0) & (t >= 0) & (z >= z0) & (z <= z1)
-    best = np.where(ok, t, np.inf).min(axis=1)
-    # caps: a ray leaving the side range can enter through the top or bottom disc
-    for zc in (z0, z1):
-        with np.errstate(divide="ignore", invalid="ignore"):
-            tc = (zc - o[2]) / dz
-        px, py = ox + tc * dx, oy + tc * dy
-        okc = (tc >= 0) & (px * px + py * py <= r * r)
-        best = np.minimum(best, np.where(okc, tc, np.inf).min(axis=1))
-    return best
+def _ray_cylinders(o, d, cyl, chunk=16384):
+    """Side and cap intersections of every ray with every vertical cylinder."""
+    import torch
+    C = torch.as_tensor(cyl, dtype=torch.float64)
+    cx, cy, r, z0, z1 = (C[:, i][None, :] for i in range(5))
+    ox, oy, oz = float(o[0]), float(o[1]), float(o[2])
+    out = np.empty(d.shape[0])
+    for s in range(0, d.shape[0], chunk):
+        D = torch.as_tensor(d[s:s + chunk], dtype=torch.float64)
+        dx, dy, dz = D[:, 0:1], D[:, 1:2], D[:, 2:3]
+        px, py = ox - cx, oy - cy
+        a = dx * dx + dy * dy
+        b = 2.0 * (px * dx + py * dy)
+        c = px * px + py * py - r * r
+        disc = b * b - 4 * a * c
+        t = (-b - torch.sqrt(disc)) / (2 * a)
+        z = oz + t * dz
+        ok = (disc >= 0) & (a > 0) & (t >= 0) & (z >= z0) & (z <= z1)
+        best = torch.where(ok, t, torch.inf).amin(dim=1)
+        # caps: a ray leaving the side range can enter through the top or bottom disc
+        for zc in (z0, z1):
+            tc = (zc - oz) / dz
+            qx, qy = px + tc * dx, py + tc * dy
+            okc = (tc >= 0) & (qx * qx + qy * qy <= r * r)
+            best = torch.minimum(best, torch.where(okc, tc, torch.inf).amin(dim=1))
+        out[s:s + chunk] = best.numpy()
+    return out
 
 
 def _ray_spheres(o, d, sph):
