@@ -14,7 +14,8 @@ oracle on a bounded particle sample of the same workload.
 
 Other workloads (not the default line): --workload small (1,000 particles in a
 small office map), --workload batched (64 filters: sequential single-filter
-calls vs one batched tick, eager and graph-replayed).
+calls vs one batched tick, eager and graph-replayed), --workload served (256
+robots at 10 Hz over 4 maps: continuous batching vs one request at a time).
 """
 
 from __future__ import annotations
@@ -219,12 +220,81 @@ def run_batched(args):
     return out
 
 
+def served_setup(args, sw, torch, mcl, served):
+    dev = torch.device("cuda:0")
+    maps = [mcl.Map.from_tsdf(t) for t in sw.tmaps]
+    vals = [torch.from_numpy(t.values).to(dev) for t in sw.tmaps]
+    scans = [[torch.from_numpy(p).to(dev) for p in lst] for lst in sw.scans]
+    specs = sw.robots
+
+    def make_robots():
+        from paper_2310_04172_amd.serve import Robot
+        return [Robot(sp.rid, maps[sp.map_idx], scans[sp.map_idx][sp.scan_idx], served.sigma_for(sw.tmaps[sp.map_idx]),
+                      [(sw.global_updates, "global"), (None, "track")]) for sp in specs]
+
+    def init_particles(r, phase, probe=False):
+        sp = specs[r.rid]
+        n = sp.n_global if phase == "global" else sp.n_track
+        if probe:
+            return n
+        return served.device_particles(torch, sw.tmaps[sp.map_idx], vals[sp.map_idx], n, phase, sp.gt,
+                                       seed=(r.rid << 1) | (phase == "track"), device=dev)
+
+    return make_robots, init_particles
+
+
+def run_served(args):
+    """256 robots at 10 Hz over 4 resident maps: continuous batching vs the same
+    trace served one request at a time with the single-filter calls."""
+    import torch
+    from paper_2310_04172_amd import mcl
+    from paper_2310_04172_amd.serve import Engine
+    from workloads import served
+
+    t0 = time.perf_counter()
+    sw = served.build(n_robots=args.robots, trace_s=args.trace_seconds)
+    log(f"served workload built in {time.perf_counter() - t0:.1f} s: {len(sw.robots)} robots, "
+        f"{len(sw.trace)} requests over {args.trace_seconds} s")
+    make_robots, init_particles = served_setup(args, sw, torch, mcl, served)
+    budget = int(args.budget_gib * (1 << 30))
+    res = {}
+    for name, kw in (("served", dict(plain=False, graph=args.graph)), ("plain_sequential", dict(plain=True))):
+        eng = Engine(make_robots(), init_particles, budget_bytes=budget, max_evals_per_tick=args.tick_evals, seed=5,
+                     **kw)
+        st = eng.run(sw.trace)
+        res[name] = st.summary()
+        log(f"{name}: {json.dumps(res[name])}")
+        del eng
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    sv, pl = res["served"], res["plain_sequential"]
+    out = base_record(args, METRIC + " [served: 256 robots at 10 Hz, continuous batching]",
+                      sv["evals_per_s"] / 1e9, sv["mean_ms"],
+                      {"workload": "served: 4 resident int16 maps (512x512x64, 1024x1024x128, 2048x2048x128 at "
+                                   "0.05 m; 1024x1024x256 at 0.1 m), 256 robots, Poisson 10 Hz, first 5 updates "
+                                   "global (N 262k-1M) then tracking (N 4k-32k), 16x1800 / 64x1024 scans",
+                       "trace_s": args.trace_seconds, "robots": len(sw.robots), "budget_GiB": args.budget_gib,
+                       "graph": args.graph, "tick_evals_cap": args.tick_evals})
+    out["steps"] = sv["completed"]
+    out["warmup"] = 0
+    out["latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"]}
+    out["served"] = sv
+    out["vs_plain"] = {"plain_sequential": pl, "throughput_gain_vs_plain": sv["evals_per_s"] / max(pl["evals_per_s"], 1e-9),
+                       "p99_ratio_vs_plain": sv["p99_ms"] / max(pl["p99_ms"], 1e-9)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="global", choices=["global", "small", "batched"])
+    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served"])
+    ap.add_argument("--robots", type=int, default=256)
+    ap.add_argument("--trace-seconds", type=float, default=30.0)
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--graph", action="store_true", help="served: replay ticks from captured graphs")
+    ap.add_argument("--tick-evals", type=float, default=3e10, help="served: cap on particle-point evals per tick")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the sensor kernel's launch shape first")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the batched workload's particle counts")
@@ -240,6 +310,8 @@ def main():
 
     if args.workload == "batched":
         out = run_batched(args)
+    elif args.workload == "served":
+        out = run_served(args)
     else:
         t0 = time.perf_counter()
         w = configs.config2() if args.workload == "global" else configs.config1()

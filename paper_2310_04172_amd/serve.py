@@ -1,0 +1,237 @@
+"""Serving: continuous batching of sensor updates from many robots.
+
+Requests (a robot's new scan) arrive over time.  The engine keeps every
+admitted robot's particle set resident in device memory and, whenever one of
+its streams is free, gathers the waiting requests of robots that are not
+already on the GPU into one batched tick (``mcl_tick``: sensor update,
+normalisation and resampling of every filter in one launch per stage).  Two
+streams let a new tick start while the previous one still runs, so requests
+that arrive meanwhile are admitted as slots and memory free up and their work
+overlaps on the device.
+
+* Latest wins: a robot keeps at most one waiting request; a newer scan replaces
+  an older one that has not started (counted as dropped, as a localiser drops
+  stale scans).  A robot has at most one update in flight.
+* Admission: a robot becomes resident when its device state (``mcl_job_bytes``)
+  fits the memory budget; until then its request waits.
+* Latency is measured from a request's arrival to the GPU completion of its
+  tick, read from device events against a reference event.
+
+The particle sets themselves (initial distributions, phase changes) come from a
+caller-supplied function: particle initialisation is not part of this path.
+"""
+
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import mcl
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 (Steele, Lea, Flood 2014): one 64-bit output for a 64-bit state."""
+    x = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    z = x
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    return z ^ (z >> 31)
+
+
+def update_draw(seed: int, robot: int, update: int) -> int:
+    """Resampling draw of a robot's n-th update: independent of batching and timing."""
+    return splitmix64(splitmix64(seed ^ (robot << 20)) ^ update)
+
+
+@dataclass
+class Robot:
+    rid: int
+    map: "mcl.Map"
+    points: object              # device [3, K]
+    sigma: float
+    phases: list                # [(n_updates or None for the rest, phase name)]
+    completed: int = 0
+    phase_i: int = 0
+    poses: object = None        # device [12, N] current particle set
+    spare: object = None        # device [12, N] resample target
+    filt: object = None
+    bytes: int = 0
+    pending: float | None = None
+    in_flight: float | None = None
+    evals_done: int = 0
+
+    @property
+    def K(self):
+        return self.points.shape[1]
+
+    @property
+    def phase(self):
+        return self.phases[self.phase_i][1]
+
+
+@dataclass
+class ServeStats:
+    latencies_ms: list = field(default_factory=list)
+    completed: int = 0
+    dropped: int = 0
+    arrived: int = 0
+    evals: int = 0
+    ticks: int = 0
+    max_resident_bytes: int = 0
+    wall_s: float = 0.0
+
+    def summary(self) -> dict:
+        lat = np.asarray(self.latencies_ms) if self.latencies_ms else np.zeros(1)
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "completed": self.completed, "arrived": self.arrived,
+                "dropped": self.dropped, "drop_rate": self.dropped / max(1, self.arrived),
+                "evals_per_s": self.evals / max(self.wall_s, 1e-9), "ticks": self.ticks,
+                "max_resident_GiB": self.max_resident_bytes / 2 ** 30, "wall_s": self.wall_s}
+
+
+class Engine:
+    """Continuous-batching server over mcl_tick (or, with plain=True, the same
+    trace served one request at a time with the single-filter calls)."""
+
+    def __init__(self, robots, init_particles, budget_bytes: int = 64 << 30, max_evals_per_tick: float = 1.2e11,
+                 n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0):
+        import torch
+        self.torch = torch
+        self.robots = robots
+        self.init_particles = init_particles
+        self.budget = int(budget_bytes)
+        self.max_evals = float(max_evals_per_tick)
+        self.plain = plain
+        self.graph = graph and not plain
+        self.seed = seed
+        self.streams = [torch.cuda.Stream() for _ in range(1 if plain else n_streams)]
+        self.used = 0
+        self.stats = ServeStats()
+
+    # -------------------------------------------------------------- state
+    def _admit(self, r: Robot) -> bool:
+        if r.filt is not None:
+            return True
+        N = self.init_particles(r, r.phase, probe=True)
+        need = mcl.job_bytes(N, r.K)
+        if self.used + need > self.budget:
+            return False
+        r.poses = self.init_particles(r, r.phase)
+        r.spare = self.torch.empty_like(r.poses)
+        r.filt = mcl.Filter(r.map, r.points, r.poses, r.sigma, 0, want_w=False)
+        r.filt.poses_out = r.spare
+        r.bytes = need
+        self.used += need
+        self.stats.max_resident_bytes = max(self.stats.max_resident_bytes, self.used)
+        return True
+
+    def _release(self, r: Robot):
+        r.filt = None
+        r.poses = r.spare = None
+        self.used -= r.bytes
+        r.bytes = 0
+
+    def _finish(self, r: Robot, t_done: float):
+        self.stats.latencies_ms.append((t_done - r.in_flight) * 1e3)
+        self.stats.completed += 1
+        n_evals = r.poses.shape[1] * r.K
+        self.stats.evals += n_evals
+        r.evals_done += n_evals
+        r.in_flight = None
+        r.completed += 1
+        r.poses, r.spare = r.spare, r.poses          # the resampled set is the new particle set
+        r.filt.poses, r.filt.poses_out = r.poses, r.spare
+        limit = self.phases_limit(r)
+        if limit is not None and r.completed >= limit:
+            self._release(r)
+            r.phase_i += 1
+
+    @staticmethod
+    def phases_limit(r: Robot):
+        n = 0
+        for i, (count, _) in enumerate(r.phases):
+            if count is None:
+                return None
+            n += count
+            if i == r.phase_i:
+                return n
+        return None
+
+    # ---------------------------------------------------------------- run
+    def run(self, trace, drain: bool = True) -> ServeStats:
+        torch = self.torch
+        st = self.stats
+        ref = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref.record()
+        ref.synchronize()
+        t_ref = time.perf_counter() - t0
+        inflight = collections.deque()        # (event, robots, stream index)
+        busy = [False] * len(self.streams)
+        ptr = 0
+        while True:
+            now = time.perf_counter() - t0
+            progressed = False
+            while ptr < len(trace) and trace[ptr][0] <= now:
+                t, rid = trace[ptr]
+                r = self.robots[rid]
+                if r.pending is not None:
+                    st.dropped += 1
+                r.pending = t
+                st.arrived += 1
+                ptr += 1
+                progressed = True
+            for item in list(inflight):
+                ev, rs, si = item
+                if ev.query():
+                    t_done = t_ref + ref.elapsed_time(ev) * 1e-3
+                    for r in rs:
+                        self._finish(r, t_done)
+                    inflight.remove(item)
+                    busy[si] = False
+                    progressed = True
+            free = [i for i, b in enumerate(busy) if not b]
+            if free:
+                cands = sorted((r for r in self.robots if r.pending is not None and r.in_flight is None),
+                               key=lambda r: r.pending)
+                batch, evals = [], 0.0
+                for r in cands:
+                    if not self._admit(r):
+                        continue
+                    e = r.poses.shape[1] * r.K
+                    if batch and (self.plain or evals + e > self.max_evals):
+                        break
+                    batch.append(r)
+                    evals += e
+                if batch:
+                    si = free[0]
+                    s = self.streams[si]
+                    for r in batch:
+                        r.in_flight, r.pending = r.pending, None
+                        r.filt.u = update_draw(self.seed, r.rid, r.completed)
+                    with torch.cuda.stream(s):
+                        if self.plain:
+                            f = batch[0].filt
+                            mcl.sensor_update(f.map, f.points, f.poses, f.sigma, f.logw, s)
+                            mcl.normalize(f.logw, None, f.wq, f.log_z, want_w=False, stream=s)
+                            mcl.resample(f.wq, f.u, f.poses, f.poses_out, f.idx, s)
+                        else:
+                            mcl.tick([r.filt for r in batch], graph=self.graph, stream=s)
+                        ev = torch.cuda.Event(enable_timing=True)
+                        ev.record(s)
+                    inflight.append((ev, batch, si))
+                    busy[si] = True
+                    st.ticks += 1
+                    progressed = True
+            if ptr >= len(trace) and not inflight and (not drain or not any(
+                    r.pending is not None for r in self.robots)):
+                break
+            if not progressed:
+                time.sleep(0.0002)
+        torch.cuda.synchronize()
+        st.wall_s = time.perf_counter() - t0
+        return st
