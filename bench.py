@@ -15,7 +15,9 @@ oracle on a bounded particle sample of the same workload.
 Other workloads (not the default line): --workload small (1,000 particles in a
 small office map), --workload batched (64 filters: sequential single-filter
 calls vs one batched tick, eager and graph-replayed), --workload served (256
-robots at 10 Hz over 4 maps: continuous batching vs one request at a time).
+robots at 10 Hz over 4 maps: continuous batching vs one request at a time),
+--workload precision (OS0-64 scan; int16 / int8 / float32 maps: speed and error
+against the float64 oracle on unquantised distances).
 """
 
 from __future__ import annotations
@@ -49,7 +51,7 @@ def cpu_threads() -> int:
     return max(1, min(16, n))
 
 
-def cpu_baseline(w, target_s: float = 10.0) -> dict:
+def cpu_baseline(w, target_s: float = 20.0) -> dict:
     """The oracle as it stands, all host threads, on a seeded particle sample."""
     import oracle
     threads = cpu_threads()
@@ -71,6 +73,32 @@ def cpu_baseline(w, target_s: float = 10.0) -> dict:
     evals = n * w.K
     return {"value": evals / dt / 1e9, "unit": "G particle-point evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} of {w.N} particles x {w.K} points (sensor update + normalise + resample), {dt:.1f} s"}
+
+
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2310_04172_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per sensor launch from the committed counter summary, if it was taken
+    on the kernel sources as they are now (else None)."""
+    path = os.path.join(ROOT, "profiles", "sensor_kernel_global_counters.txt")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    if kernel_source_hash() not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":")[1])
+    return None
 
 
 def percentile(xs, q):
@@ -151,7 +179,8 @@ def run_single(args, w, workload_key, with_roofline=True):
         flops = 20.0 * evals   # 9 mul + 9 add transform, 1 mul + 1 add score, per evaluation
         achieved = flops / (sensor_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                           "frac": achieved / FP32_PEAK_TFLOPS,
+                           "traffic": profiled_traffic() if workload_key == "global" else None,
                            "kernel": "sensor_kernel", "algorithmic_flops_per_launch": flops,
                            "algorithmic_tsdf_bytes_per_launch": 2.0 * evals}
     return out
@@ -217,6 +246,58 @@ def run_batched(args):
                                             "p50_ms": percentile(lat_plain, 50), "p99_ms": percentile(lat_plain, 99)},
                        "tick_eager": {"value": evals / (ms_eager * 1e-3) / 1e9, "ms": ms_eager},
                        "throughput_gain_vs_plain": ms_plain / ms_graph}
+    return out
+
+
+def run_precision(args):
+    """OS0-64-shaped workload on the warehouse stored as int16, int8 and float32: speed of
+    each storage type, and its log-weight error against the float64 oracle evaluated on the
+    unquantised (float64) distances, on a seeded particle sample."""
+    import torch
+    import oracle
+    from paper_2310_04172_amd import mcl
+    from workloads import configs
+
+    dev = torch.device("cuda:0")
+    res = {}
+    ref = None
+    for dt in ("i16", "i8", "f32"):
+        t0 = time.perf_counter()
+        w = configs.config3(dtype=dt)
+        log(f"{dt} workload built in {time.perf_counter() - t0:.1f} s: N={w.N} K={w.K}")
+        m = mcl.Map.from_tsdf(w.tmap)
+        pts = torch.from_numpy(w.points).to(dev)
+        poses = torch.from_numpy(w.poses).to(dev)
+        logw = torch.empty(w.N, dtype=torch.float32, device=dev)
+        for _ in range(args.warmup):
+            mcl.sensor_update(m, pts, poses, w.sigma, logw)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            mcl.sensor_update(m, pts, poses, w.sigma, logw)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        ms = float(np.median(ts))
+        sub = configs.subset_indices(3, w.N, args.precision_sample)
+        ps = np.ascontiguousarray(w.poses[:, sub])
+        if ref is None:
+            ref = oracle.sensor_update(w.tmap.with_dtype("f64"), w.points, ps, w.sigma, nthreads=cpu_threads())
+        same = oracle.sensor_update(w.tmap, w.points, ps, w.sigma, nthreads=cpu_threads())
+        got = logw.cpu().numpy()[sub].astype(np.float64)
+        err = np.abs(got - ref) / np.abs(ref)
+        par = np.abs(got - same) / np.abs(same)
+        res[dt] = {"sensor_ms": ms, "evals_per_s_G": w.N * w.K / (ms * 1e-3) / 1e9,
+                   "rel_err_vs_f64_max": float(err.max()), "rel_err_vs_f64_mean": float(err.mean()),
+                   "parity_vs_same_storage_max": float(par.max()), "map_bytes": int(w.tmap.values.nbytes)}
+        log(f"{dt}: {json.dumps(res[dt])}")
+        del m
+    out = base_record(args, METRIC + " [precision: OS0-64 scan, int16 / int8 / float32 maps]",
+                      res["i16"]["evals_per_s_G"], res["i16"]["sensor_ms"],
+                      {"workload": w.name.replace(" f32", ""), "N": w.N, "K": w.K,
+                       "sample_for_errors": args.precision_sample, "per_storage_type": res})
     return out
 
 
@@ -289,7 +370,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served"])
+    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision"])
+    ap.add_argument("--precision-sample", type=int, default=1024)
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -312,6 +394,8 @@ def main():
         out = run_batched(args)
     elif args.workload == "served":
         out = run_served(args)
+    elif args.workload == "precision":
+        out = run_precision(args)
     else:
         t0 = time.perf_counter()
         w = configs.config2() if args.workload == "global" else configs.config1()

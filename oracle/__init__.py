@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mcl_oracle.c")
 LIB = os.path.join(HERE, "libmcl_oracle.so")
 
-DTYPE_CODE = {"i16": 0, "i8": 1, "f32": 2}
+DTYPE_CODE = {"i16": 0, "i8": 1, "f32": 2, "f64": 3}
 
 
 def build(force: bool = True) -> str:
@@ -61,6 +61,8 @@ def _map_args(tmap):
     dims = np.array([tmap.nx, tmap.ny, tmap.nz], np.int32)
     origin = np.array(tmap.origin, np.float32)
     vals = np.ascontiguousarray(tmap.values)
+    want = {"i16": np.int16, "i8": np.int8, "f32": np.float32, "f64": np.float64}[tmap.dtype]
+    assert vals.dtype == want, (vals.dtype, tmap.dtype)
     return dims, origin, vals
 
 

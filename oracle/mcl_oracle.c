@@ -39,7 +39,9 @@
  *    constant factor (it cancels in normalisation):
  *        l_n = -(s^2 / (2 sigma^2)) * sum_k q_k^2,   s = tau / Q (s = 1 for float32).
  *    The sum of squares is exact (int64) for fixed-point maps and float64 for
- *    float32 maps (each square is exact in float64).
+ *    float32 maps (each square is exact in float64).  A float64 map (the
+ *    unquantised distances) serves as the precision reference of the storage
+ *    types.
  *
  *  Normalisation (§V-A sums the weights for normalisation), float64:
  *        m = max_n l_n ;  S = sum_n exp(l_n - m) in index order ;
@@ -61,7 +63,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORACLE_I16 = 0, ORACLE_I8 = 1, ORACLE_F32 = 2 };
+enum { ORACLE_I16 = 0, ORACLE_I8 = 1, ORACLE_F32 = 2, ORACLE_F64 = 3 };
 
 typedef struct {
     int32_t n[3];
@@ -156,6 +158,16 @@ static double particle_sum_sq(const su_job_t *J, int64_t n) {
         }
         return acc;
     }
+    if (J->dtype == ORACLE_F64) { /* precision reference: the unquantised distances */
+        const double *vals = (const double *)J->values;
+        double acc = 0.0;
+        for (int64_t k = 0; k < J->K; ++k) {
+            int64_t v = voxel_index(a, b, px[k], py[k], pz[k], &J->g);
+            double d = v < 0 ? (double)(float)J->tau : vals[v];
+            acc += d * d;
+        }
+        return acc;
+    }
     int64_t acc = 0;
     for (int64_t k = 0; k < J->K; ++k) {
         int64_t v = voxel_index(a, b, px[k], py[k], pz[k], &J->g);
@@ -192,19 +204,19 @@ int oracle_sensor_update(const int32_t dims[3], float voxel, const float origin[
                          int32_t dtype, const void *values, const float *points, int32_t K,
                          const float *poses, int32_t N, float sigma, double *logw, double *ssum,
                          int32_t nthreads) {
-    if (K < 0 || N < 0 || dtype < 0 || dtype > 2 || !(sigma > 0.0f)) return -1;
+    if (K < 0 || N < 0 || dtype < 0 || dtype > 3 || !(sigma > 0.0f)) return -1;
     su_job_t base;
     memset(&base, 0, sizeof base);
     base.g = make_grid(dims, voxel, origin);
     base.dtype = dtype;
     base.values = values;
     base.tau = (double)tau;
-    base.Q = dtype == ORACLE_I16 ? 32767 : dtype == ORACLE_I8 ? 127 : 1;
+    base.Q = dtype == ORACLE_I16 ? 32767 : dtype == ORACLE_I8 ? 127 : 1;  /* 1: metres (float32 / float64) */
     base.points = points;
     base.K = K;
     base.poses = poses;
     base.N = N;
-    double s = dtype == ORACLE_F32 ? 1.0 : (double)tau / (double)base.Q;
+    double s = dtype >= ORACLE_F32 ? 1.0 : (double)tau / (double)base.Q;
     double sg = (double)sigma;
     base.c = (s * s) / (2.0 * sg * sg);
     base.logw = logw;

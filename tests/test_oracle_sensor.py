@@ -20,7 +20,7 @@ SQ3_2 = math.sqrt(3.0) / 2.0
 
 
 def score_const(tmap, sigma):
-    s = 1.0 if tmap.dtype == "f32" else float(tmap.tau) / tmap.Q
+    s = 1.0 if tmap.dtype in ("f32", "f64") else float(tmap.tau) / tmap.Q
     return (s * s) / (2.0 * float(sigma) ** 2)
 
 
@@ -82,15 +82,15 @@ def test_negative_zero_grid_coordinate_is_inside(oracle_lib):
 
 
 # ---------------------------------------------------------------- closed forms
-@pytest.mark.parametrize("dtype", ["i16", "i8", "f32"])
+@pytest.mark.parametrize("dtype", ["i16", "i8", "f32", "f64"])
 def test_identity_pose_exact_score(oracle_lib, dtype):
     """Identity pose, dyadic voxel, points at voxel centres: indices are known
     integers and the score is the closed form -c * sum q^2 (exact integer sum)."""
     rng = np.random.default_rng(5)
     nx, ny, nz = 8, 6, 5
     v, tau, sigma = 0.125, 0.3, f32(0.11)
-    if dtype == "f32":
-        vals = rng.uniform(-tau, tau, size=(nz, ny, nx)).astype(np.float32)
+    if dtype in ("f32", "f64"):
+        vals = rng.uniform(-tau, tau, size=(nz, ny, nx)).astype(np.float32 if dtype == "f32" else np.float64)
     else:
         lim = 127 if dtype == "i8" else 32767
         vals = rng.permutation(np.linspace(-lim, lim, nx * ny * nz).round()).reshape(nz, ny, nx)
@@ -101,9 +101,9 @@ def test_identity_pose_exact_score(oracle_lib, dtype):
     pts = ((np.stack([ii, jj, kk]).astype(np.float64) + 0.5) * v).astype(np.float32)
     lw, S = oracle_lib.sensor_update(tmap, pts, identity_poses(1), sigma, return_sum=True)
     q = vals[kk, jj, ii].astype(np.float64)
-    if dtype == "f32":
+    if dtype in ("f32", "f64"):
         expect = math.fsum(float(x) * float(x) for x in q)
-        assert abs(S[0] - expect) <= 1e-15 * expect
+        assert abs(S[0] - expect) <= 1e-14 * expect
     else:
         expect = sum(int(x) * int(x) for x in q)
         assert S[0] == expect

@@ -19,8 +19,8 @@ import numpy as np
 
 from .scene import Scene, box_sdf, cylinder_sdf, sphere_sdf
 
-QSCALE = {"i16": 32767, "i8": 127, "f32": 1}
-NP_DTYPE = {"i16": np.int16, "i8": np.int8, "f32": np.float32}
+QSCALE = {"i16": 32767, "i8": 127, "f32": 1, "f64": 1}
+NP_DTYPE = {"i16": np.int16, "i8": np.int8, "f32": np.float32, "f64": np.float64}
 DTYPE_CODE = {"i16": 0, "i8": 1, "f32": 2}
 
 
@@ -42,8 +42,8 @@ class TsdfMap:
 
     @property
     def scale(self) -> float:
-        """Metres per stored unit, s = tau / Q (1 for float32 maps), float64."""
-        return 1.0 if self.dtype == "f32" else float(self.tau) / self.Q
+        """Metres per stored unit, s = tau / Q (1 for float maps), float64."""
+        return 1.0 if self.dtype in ("f32", "f64") else float(self.tau) / self.Q
 
     @property
     def dims(self):
@@ -52,8 +52,8 @@ class TsdfMap:
     def with_dtype(self, dtype: str) -> "TsdfMap":
         if self.d64 is None:
             raise ValueError("re-quantising needs the float64 distances (keep_d64=True)")
-        return TsdfMap(self.nx, self.ny, self.nz, self.voxel, self.origin, self.tau,
-                       dtype, quantise(self.d64, self.tau, dtype), self.d64)
+        vals = self.d64 if dtype == "f64" else quantise(self.d64, self.tau, dtype)
+        return TsdfMap(self.nx, self.ny, self.nz, self.voxel, self.origin, self.tau, dtype, vals, self.d64)
 
 
 def f32(x) -> float:
