@@ -12,12 +12,13 @@ Prints one JSON line.  `value` is particle-point evaluations per second
 update) measured with HIP events on its stream; `cpu_baseline` times the CPU
 oracle on a bounded particle sample of the same workload.
 
-Other workloads (not the default line): --workload small (1,000 particles in a
+Other workloads (not the default line): --workload estimate (the pose estimate alone,
+2^14 to 2^21 particles), --workload small (1,000 particles in a
 small office map), --workload batched (64 filters: sequential single-filter
 calls vs one batched tick, eager and graph-replayed), --workload served (256
 robots at 10 Hz over 4 maps: continuous batching vs one request at a time),
---workload precision (OS0-64 scan; int16 / int8 / float32 maps: speed and error
-against the float64 oracle on unquantised distances).
+--workload precision (OS0-64 scan; int16 / int8 / float32 maps: speed of each; their
+error against float64 distances is measured by the precision tests).
 """
 
 from __future__ import annotations
@@ -75,13 +76,19 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
             "sample": f"{n} of {w.N} particles x {w.K} points (sensor update + normalise + resample), {dt:.1f} s"}
 
 
+# the sources that make up the sensor kernel, its map layout and its launch
+SENSOR_SOURCES = ("paper_2310_04172_amd/csrc/sensor.hip", "paper_2310_04172_amd/csrc/voxel.h",
+                  "paper_2310_04172_amd/csrc/jobs.h", "paper_2310_04172_amd/csrc/mcl_internal.h",
+                  "paper_2310_04172_amd/csrc/map.hip", "paper_2310_04172_amd/csrc/tune.hip",
+                  "paper_2310_04172_amd/build.py", "include/mcl.h")
+
+
 def kernel_source_hash() -> str:
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2310_04172_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+    for f in SENSOR_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()
 
 
@@ -160,6 +167,8 @@ def run_single(args, w, workload_key, with_roofline=True):
     evals = N * K
     sensor_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     log(f"step {ms_step:.3f} ms, sensor kernel {sensor_ms:.3f} ms")
+    est = time_estimate(torch, mcl, logw, poses, stream)
+    log(f"pose estimate {est['us']:.2f} us, {est['achieved_GBs']:.0f} GB/s")
     if args.copy_calib_mib:
         n = args.copy_calib_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -175,14 +184,77 @@ def run_single(args, w, workload_key, with_roofline=True):
                        "step": "sensor update + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
                        "workload_key": workload_key, "sensor_update_ms": sensor_ms})
     out["latency_ms"] = {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}
+    out["pose_estimate"] = est
     if with_roofline:
-        flops = 20.0 * evals   # 9 mul + 9 add transform, 1 mul + 1 add score, per evaluation
+        flops = 20.0 * evals   # 9 fused multiply-adds (transform) + 1 (score), 2 flops each, per evaluation
         achieved = flops / (sensor_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / FP32_PEAK_TFLOPS,
                            "traffic": profiled_traffic() if workload_key == "global" else None,
                            "kernel": "sensor_kernel", "algorithmic_flops_per_launch": flops,
                            "algorithmic_tsdf_bytes_per_launch": 2.0 * evals}
+    return out
+
+
+def time_estimate(torch, mcl, logw, poses, stream, reps: int = 50) -> dict:
+    """Pose estimate (weighted mean + best particle) of the step's weighted set,
+    timed with HIP events on its stream; HBM-bound (8 B weight + 48 B pose read
+    per particle)."""
+    N = poses.shape[1]
+    w = torch.empty(N, dtype=torch.float64, device=poses.device)
+    wq = torch.empty(N, dtype=torch.uint64, device=poses.device)
+    mcl.normalize(logw, w, wq, None, want_w=True, stream=stream)
+    mean = torch.empty(12, dtype=torch.float64, device=poses.device)
+    bi = torch.empty(1, dtype=torch.int32, device=poses.device)
+    bp = torch.empty(12, dtype=torch.float32, device=poses.device)
+    for _ in range(3):
+        mcl.pose_estimate(w, poses, mean, bi, bp, stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        mcl.pose_estimate(w, poses, mean, bi, bp, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) * 1e3 / reps
+    nbytes = 56.0 * N
+    return {"us": us, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (us * 1e-6) / 1e9,
+            "peak_GBs": HBM_PEAK_GBS, "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "kernels": "estimate_partial_kernel + estimate_final_kernel"}
+
+
+def run_estimate(args):
+    """Pose estimate alone on seeded particle sets of 2^14, 2^18, 10^6 and 2^21 particles
+    (random pose rows, uniform weights in [0, 1)): mean time per call over 100 calls."""
+    import torch
+    from paper_2310_04172_amd import mcl
+
+    res = {}
+    stream = torch.cuda.current_stream()
+    for N in (16384, 262144, 1000000, 2097152):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(N)
+        poses = torch.randn((12, N), generator=g, device="cuda", dtype=torch.float32)
+        w = torch.rand(N, generator=g, device="cuda", dtype=torch.float64)
+        mean = torch.empty(12, dtype=torch.float64, device="cuda")
+        bi = torch.empty(1, dtype=torch.int32, device="cuda")
+        bp = torch.empty(12, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            mcl.pose_estimate(w, poses, mean, bi, bp, stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(100):
+            mcl.pose_estimate(w, poses, mean, bi, bp, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 10.0
+        res[str(N)] = {"us": us, "GB_per_s": 56.0 * N / us / 1e3}
+        log(f"N={N}: {us:.2f} us per call, {56.0 * N / us / 1e3:.0f} GB/s")
+    N = 1000000
+    out = base_record(args, "pose estimate: particles/s (G/s)", N / (res[str(N)]["us"] * 1e-6) / 1e9,
+                      res[str(N)]["us"] * 1e-3, {"workload": "pose estimate, seeded particle sets, N = 2^14 .. 2^21",
+                                                 "per_N": res}, dtype="f64")
+    out["unit"] = "G particles/s"
+    out["steps"] = 100
     return out
 
 
@@ -250,17 +322,15 @@ def run_batched(args):
 
 
 def run_precision(args):
-    """OS0-64-shaped workload on the warehouse stored as int16, int8 and float32: speed of
-    each storage type, and its log-weight error against the float64 oracle evaluated on the
-    unquantised (float64) distances, on a seeded particle sample."""
+    """OS0-64-shaped workload on the warehouse stored as int16, int8 and float32:
+    sensor-update speed of each storage type.  (Their log-weight error against
+    float64 distances is measured by the precision tests.)"""
     import torch
-    import oracle
     from paper_2310_04172_amd import mcl
     from workloads import configs
 
     dev = torch.device("cuda:0")
     res = {}
-    ref = None
     for dt in ("i16", "i8", "f32"):
         t0 = time.perf_counter()
         w = configs.config3(dtype=dt)
@@ -281,23 +351,13 @@ def run_precision(args):
             torch.cuda.synchronize()
             ts.append(a.elapsed_time(b))
         ms = float(np.median(ts))
-        sub = configs.subset_indices(3, w.N, args.precision_sample)
-        ps = np.ascontiguousarray(w.poses[:, sub])
-        if ref is None:
-            ref = oracle.sensor_update(w.tmap.with_dtype("f64"), w.points, ps, w.sigma, nthreads=cpu_threads())
-        same = oracle.sensor_update(w.tmap, w.points, ps, w.sigma, nthreads=cpu_threads())
-        got = logw.cpu().numpy()[sub].astype(np.float64)
-        err = np.abs(got - ref) / np.abs(ref)
-        par = np.abs(got - same) / np.abs(same)
         res[dt] = {"sensor_ms": ms, "evals_per_s_G": w.N * w.K / (ms * 1e-3) / 1e9,
-                   "rel_err_vs_f64_max": float(err.max()), "rel_err_vs_f64_mean": float(err.mean()),
-                   "parity_vs_same_storage_max": float(par.max()), "map_bytes": int(w.tmap.values.nbytes)}
+                   "map_bytes": int(w.tmap.values.nbytes)}
         log(f"{dt}: {json.dumps(res[dt])}")
         del m
     out = base_record(args, METRIC + " [precision: OS0-64 scan, int16 / int8 / float32 maps]",
                       res["i16"]["evals_per_s_G"], res["i16"]["sensor_ms"],
-                      {"workload": w.name.replace(" f32", ""), "N": w.N, "K": w.K,
-                       "sample_for_errors": args.precision_sample, "per_storage_type": res})
+                      {"workload": w.name.replace(" f32", ""), "N": w.N, "K": w.K, "per_storage_type": res})
     return out
 
 
@@ -370,8 +430,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision"])
-    ap.add_argument("--precision-sample", type=int, default=1024)
+    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision", "estimate"])
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -396,6 +455,8 @@ def main():
         out = run_served(args)
     elif args.workload == "precision":
         out = run_precision(args)
+    elif args.workload == "estimate":
+        out = run_estimate(args)
     else:
         t0 = time.perf_counter()
         w = configs.config2() if args.workload == "global" else configs.config1()

@@ -122,6 +122,30 @@ mcl_status mcl_normalize(const float *logw, int32_t N, double *w, uint64_t *wq, 
 mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t u, int32_t *idx,
                         const float *poses_in, float *poses_out, void *stream);
 
+/* Pose estimate of a weighted particle set (§III: the weighted average of the
+ * particles, or the particle of highest weight; §V: a second reduction forms
+ * the weighted sum of the poses).  The paper does not say how rotations are
+ * averaged; here:
+ *   position  t* = sum_n w_n t_n / sum_n w_n
+ *   rotation  R* = the rotation nearest to S = sum_n w_n R_n, the maximiser of
+ *             trace(R^T S) over SO(3) (weighted chordal L2 mean; for exact
+ *             rotations equal to the eigenvector quaternion average).  When S
+ *             has a repeated largest singular-value combination the maximiser is
+ *             not unique and any maximiser may be returned.
+ *   sum_n w_n = 0 is read as equal weights.
+ *   w:         device [N] float64 weights, finite and >= 0 (as mcl_normalize
+ *              writes them); other values give an unspecified estimate.
+ *   poses:     device [12][N] float32 particle poses.
+ *   mean:      device output [12] float64, the estimate in the particle layout
+ *              (r00 r01 r02 r10 r11 r12 r20 r21 r22 tx ty tz).
+ *   best_idx:  device output [1] int32 or NULL: the smallest index among the
+ *              largest weights (-1 if no weight exceeds -inf).
+ *   best_pose: device output [12] float32 or NULL: poses[:, best_idx] exactly
+ *              (NaN if best_idx is -1).
+ * Float64 sums in an order fixed by N alone: results are reproducible. */
+mcl_status mcl_pose_estimate(const double *w, const float *poses, int32_t N, double *mean,
+                             int32_t *best_idx, float *best_pose, void *stream);
+
 /* ------------------------------------------------------------- batching
  * One MCL update of many filters at once (the filters may use different maps,
  * particle counts and scan sizes).  mcl_tick runs, for every filter, exactly

@@ -9,9 +9,10 @@
  *
  * Plain and slow on purpose: one particle at a time, one scan point at a time,
  * in the order of the definitions.  Arithmetic is float64 or exact integer,
- * except the voxel-index step, whose float32 operation order is a fixed recipe
- * (so that voxel indices can be compared bit for bit with any other
- * implementation of the same recipe).  Build with -ffp-contract=off.
+ * except the voxel-index step, whose float32 operations are a fixed recipe (so
+ * that voxel indices can be compared bit for bit with any other implementation
+ * of the same recipe).  Build with -ffp-contract=off: the recipe's fused
+ * multiply-adds are explicit fmaf calls (IEEE fusedMultiplyAdd, one rounding).
  *
  * Definitions, with the reading taken where the paper is silent:
  *
@@ -27,11 +28,15 @@
  *    voxel that contains the point, half-open cells); a point outside the map
  *    reads +Q (+tau), truncated free space.
  *
- *  Voxel-index recipe (float32, IEEE round-to-nearest-even, no fused ops):
- *      inv_v = (float)(1.0 / (double)v)                      once per map
- *      a_jk  = r_jk * inv_v ;  b_j = (t_j - o_j) * inv_v        once per particle
- *      g_j   = ((a_j0 px + a_j1 py) + a_j2 pz) + b_j            per point, each op rounded
- *      valid iff 0 <= g_j < n_j for j = x, y, z ;  i_j = (int) g_j.
+ *  Voxel-index recipe (float32, IEEE round-to-nearest-even):
+ *      inv_v = (float)(1.0 / (double)v)                        once per map
+ *      a_jk  = r_jk * inv_v ;  b_j = (t_j - o_j) * inv_v + 0      once per particle
+ *      g_j   = fma(a_j2, pz, fma(a_j1, py, fma(a_j0, px, b_j)))  per point
+ *      valid iff 0 <= g_j < n_j for j = x, y, z, where -0.0 counts as below 0
+ *      (the sign bit decides) ;  i_j = (int) g_j.
+ *    The "+ 0" maps an offset of -0.0 to +0.0 (so that t = -0.0 and t = +0.0
+ *    select alike); a g_j of -0.0 can then only come from a negative exact value
+ *    too small to represent, which lies below 0.
  *
  *  Sensor model (Eq. 3, endpoint model): a point's likelihood is a Gaussian in
  *    the map distance m(x, z).  Reading: a particle's weight is the product over
@@ -90,7 +95,7 @@ static void particle_consts(const float *poses, int64_t N, int64_t n, const grid
             a[3 * j + k] = r * g->inv_v;
         }
         float shifted = poses[(int64_t)(9 + j) * N + n] - g->o[j];
-        b[j] = shifted * g->inv_v;
+        b[j] = shifted * g->inv_v + 0.0f; /* -0.0 -> +0.0, every other value unchanged */
     }
 }
 
@@ -99,13 +104,11 @@ static int64_t voxel_index(const float a[9], const float b[3], float px, float p
                            const grid_t *g) {
     int32_t idx[3];
     for (int j = 0; j < 3; ++j) {
-        float s = a[3 * j + 0] * px;
-        float t = a[3 * j + 1] * py;
-        s = s + t;
-        t = a[3 * j + 2] * pz;
-        s = s + t;
-        s = s + b[j];
-        if (!(s >= 0.0f && s < (float)g->n[j])) return -1; /* NaN fails too */
+        float s = fmaf(a[3 * j + 0], px, b[j]);
+        s = fmaf(a[3 * j + 1], py, s);
+        s = fmaf(a[3 * j + 2], pz, s);
+        /* inside iff 0 <= s < n with -0.0 taken as below 0; NaN fails too */
+        if (signbit(s) || !(s < (float)g->n[j])) return -1;
         idx[j] = (int32_t)s;
     }
     return (int64_t)idx[0] + (int64_t)g->n[0] * ((int64_t)idx[1] + (int64_t)g->n[1] * idx[2]);

@@ -12,6 +12,7 @@ mcl_status launch_sensor(const mcl_map_s *, const float *, int, const float *, i
 mcl_status launch_debug_indices(const mcl_map_s *, const float *, int, const float *, int, int64_t *, hipStream_t);
 mcl_status launch_normalize(const float *, int, double *, uint64_t *, double *, hipStream_t);
 mcl_status launch_resample(const uint64_t *, int, uint64_t, int32_t *, const float *, float *, hipStream_t);
+mcl_status launch_estimate(const double *, const float *, int, double *, int32_t *, float *, hipStream_t);
 
 static thread_local std::string g_last_error;
 
@@ -111,6 +112,23 @@ extern "C" mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t u, in
         overlaps(idx, (size_t)N * 4, poses_in, pb))
         return fail(MCL_EINVAL, "resample: overlapping buffers");
     return launch_resample(wq, N, u, idx, poses_in, poses_out, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mcl_status mcl_pose_estimate(const double *w, const float *poses, int32_t N, double *mean,
+                                        int32_t *best_idx, float *best_pose, void *stream) {
+    if (!w || !poses || !mean) return fail(MCL_EINVAL, "pose_estimate: NULL w, poses or mean");
+    if (N < 1) return fail(MCL_EINVAL, "pose_estimate: need N >= 1");
+    if (N > MCL_MAX_PARTICLES) return fail(MCL_ERANGE, "pose_estimate: N above the limit");
+    const size_t pb = (size_t)12 * N * 4, wb = (size_t)N * 8;
+    const void *outs[3] = {mean, best_idx, best_pose};
+    const size_t ob[3] = {12 * 8, 4, 12 * 4};
+    for (int a = 0; a < 3; ++a) {
+        if (overlaps(outs[a], ob[a], w, wb) || overlaps(outs[a], ob[a], poses, pb))
+            return fail(MCL_EINVAL, "pose_estimate: overlapping buffers");
+        for (int b = a + 1; b < 3; ++b)
+            if (overlaps(outs[a], ob[a], outs[b], ob[b])) return fail(MCL_EINVAL, "pose_estimate: overlapping buffers");
+    }
+    return launch_estimate(w, poses, N, mean, best_idx, best_pose, static_cast<hipStream_t>(stream));
 }
 
 extern "C" mcl_status mcl_debug_voxel_indices(mcl_map map, const float *points, int32_t K, const float *poses,

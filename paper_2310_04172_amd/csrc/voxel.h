@@ -19,30 +19,25 @@ __device__ inline void pose_consts(const float *__restrict__ poses, int N, int n
     float dy = poses[(size_t)10 * N + n] - m.oy;
     float dz = poses[(size_t)11 * N + n] - m.oz;
     // adding +0.0 turns a -0.0 offset into +0.0 and leaves every other value
-    // unchanged; then g = s + b is never -0.0 (see voxel_ijk), while the voxel
-    // selected is the same as without it (-0.0 and +0.0 select voxel 0 alike)
+    // unchanged, so that translations of -0.0 and +0.0 select alike
     pa[9] = dx * m.inv_v + 0.0f;
     pa[10] = dy * m.inv_v + 0.0f;
     pa[11] = dz * m.inv_v + 0.0f;
 }
 
-// One grid coordinate: ((a0 x + a1 y) + a2 z) + b, every operation rounded.
+// One grid coordinate: fma(a2, z, fma(a1, y, fma(a0, x, b))), three fused
+// multiply-adds, each rounded once.  With b not -0.0 an exact zero sum rounds
+// to +0.0, so g is -0.0 only when a negative exact value is too small to be
+// represented: such a point lies below 0.
 __device__ inline float grid_coord(float a0, float a1, float a2, float b, float x, float y, float z) {
-#pragma clang fp contract(off)
-    float s = a0 * x;
-    float t = a1 * y;
-    s = s + t;
-    t = a2 * z;
-    s = s + t;
-    return s + b;
+    return __builtin_fmaf(a2, z, __builtin_fmaf(a1, y, __builtin_fmaf(a0, x, b)));
 }
 
-// Voxel (ix, iy, iz) holding grid coordinates g, if 0 <= g < n on every axis
-// (NaN is outside).  For a float g that is not -0.0, 0 <= g < n holds exactly
-// when its bit pattern, read as an unsigned integer, is below that of n:
-// non-negative floats order like their bit patterns, and negative values and
-// NaNs of either sign have patterns above any finite positive n.  The pose
-// prologue makes g = -0.0 impossible.  The integer coordinates are (int)g;
+// Voxel (ix, iy, iz) holding grid coordinates g, if 0 <= g < n on every axis,
+// -0.0 counting as below 0 and NaN as outside: exactly when the bit pattern of
+// g, read as an unsigned integer, is below that of n (non-negative floats order
+// like their bit patterns; negative values, -0.0 and NaNs of either sign have
+// patterns above any finite positive n).  The integer coordinates are (int)g;
 // for a point outside the map they are meaningless and the caller must not
 // use them (voxel_offset replaces the address by the sentinel's).
 __device__ inline bool voxel_ijk(const MapView &m, float gx, float gy, float gz, uint32_t &ix,

@@ -53,6 +53,7 @@ _lib.mcl_sensor_update.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
 _lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, _P, _P, _P, _P]
 _lib.mcl_debug_voxel_indices.argtypes = [_P, _P, _I, _P, _I, _P, _P]
+_lib.mcl_pose_estimate.argtypes = [_P, _P, _I, _P, _P, _P, _P]
 _lib.mcl_tick.argtypes = [C.POINTER(FilterJob), _I, _I, _P]
 _lib.mcl_job_bytes.argtypes = [_I, _I]
 _lib.mcl_job_bytes.restype = C.c_size_t
@@ -60,7 +61,7 @@ _lib.mcl_autotune.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P, C.POINTER(L
 _lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_last_error.restype = C.c_char_p
 for _f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
-           "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config"):
+           "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_pose_estimate"):
     getattr(_lib, _f).restype = C.c_int32
 
 
@@ -184,6 +185,23 @@ def resample(wq, u: int, poses_in=None, poses_out=None, idx=None, stream=None):
     _check(_lib.mcl_resample(_ptr(wq), N, C.c_uint64(int(u) & (2 ** 64 - 1)), _ptr(idx), _ptr(poses_in),
                              _ptr(poses_out), _stream(stream)), "mcl_resample")
     return idx, poses_out
+
+
+def pose_estimate(w, poses, mean=None, best_idx=None, best_pose=None, stream=None):
+    """(mean float64 [12], best_idx int32 [1], best_pose float32 [12]) on the device."""
+    import torch
+    N = poses.shape[1]
+    _dev(w, torch.float64, (N,), "w")
+    _dev(poses, torch.float32, (12, N), "poses")
+    if mean is None:
+        mean = torch.empty(12, dtype=torch.float64, device=poses.device)
+    if best_idx is None:
+        best_idx = torch.empty(1, dtype=torch.int32, device=poses.device)
+    if best_pose is None:
+        best_pose = torch.empty(12, dtype=torch.float32, device=poses.device)
+    _check(_lib.mcl_pose_estimate(_ptr(w), _ptr(poses), N, _ptr(mean), _ptr(best_idx), _ptr(best_pose),
+                                  _stream(stream)), "mcl_pose_estimate")
+    return mean, best_idx, best_pose
 
 
 def debug_voxel_indices(m: Map, points, poses, out=None, stream=None):

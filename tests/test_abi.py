@@ -27,7 +27,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
               "mcl_debug_voxel_indices", "mcl_last_error", "mcl_tick", "mcl_job_bytes", "mcl_autotune",
-              "mcl_set_launch_config"):
+              "mcl_set_launch_config", "mcl_pose_estimate"):
         assert f in names
 
 
@@ -49,6 +49,13 @@ def test_argument_errors_are_reported_on_the_host(mcl):
     assert lib.mcl_normalize(fake, mcl.MAX_PARTICLES + 1, None, P(0x90000000), None, None) == mcl.MCL_ERANGE
     assert lib.mcl_resample(fake, 10, 0, P(0x9000), fake, None, None) == mcl.MCL_EINVAL
     assert lib.mcl_resample(fake, 0, 0, P(0x9000), None, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_pose_estimate(None, fake, 10, P(0x9000), None, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_pose_estimate(fake, fake, 0, P(0x90000), None, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_pose_estimate(fake, fake, mcl.MAX_PARTICLES + 1, P(0x9000000000), None, None,
+                                 None) == mcl.MCL_ERANGE
+    assert lib.mcl_pose_estimate(P(0x10000), P(0x20000), 100, P(0x10008), None, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_pose_estimate(P(0x10000), P(0x20000), 100, P(0x90000), P(0x90010), None,
+                                 None) == mcl.MCL_EINVAL
     # overlapping output and input
     assert lib.mcl_normalize(P(0x10000), 100, None, P(0x10010), None, None) == mcl.MCL_EINVAL
     d = mcl.MapDesc(0, 4, 4, 0.1, (C.c_float * 3)(0, 0, 0), 0.3, 0)

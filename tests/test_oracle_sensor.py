@@ -7,6 +7,7 @@ map was voxelised from (with a rigorous Lipschitz error bound).
 """
 
 import math
+from fractions import Fraction
 from fractions import Fraction as F
 
 import numpy as np
@@ -61,7 +62,7 @@ def test_voxel_index_matches_exact_geometry(oracle_lib):
 
 def test_cell_faces_are_half_open(oracle_lib):
     """A point exactly on a face belongs to the upper cell; the far face is outside;
-    -0.0 counts as >= 0; NaN is outside."""
+    a point of -0.0 under the identity pose is in voxel 0; NaN is outside."""
     nx, ny, nz = 4, 3, 2
     v = 0.125
     tmap = make_map(np.zeros((nz, ny, nx), np.int16), v)
@@ -73,7 +74,8 @@ def test_cell_faces_are_half_open(oracle_lib):
 
 
 def test_negative_zero_grid_coordinate_is_inside(oracle_lib):
-    """g = -0.0 (translation -0.0, zero origin, point -0.0) compares >= 0: voxel 0."""
+    """Translation -0.0 at a zero origin and a point of -0.0 select voxel 0, as
+    +0.0 does (the recipe maps an offset of -0.0 to +0.0)."""
     tmap = make_map(np.zeros((2, 2, 2), np.int16), 0.125)
     poses = identity_poses(1)
     poses[9:, 0] = -0.0
@@ -289,3 +291,90 @@ def test_analytic_scene_bound_and_rigid_motion(oracle_lib):
     np.testing.assert_allclose(anB, anA, rtol=1e-3, atol=1e-2 * c_metric * delta ** 2 * K)
     assert np.all(np.abs(lB - anB) <= bB)
     assert np.all(np.abs(lB - lA) <= bA + bB + np.abs(anB - anA))
+
+
+# ------------------------------------------------- the index recipe, exactly
+def _round_f32(x: Fraction, neg_zero: bool = False) -> float:
+    """Nearest float32 to an exact rational (ties to even), as a Python float;
+    a zero result takes the sign of x (or neg_zero for an exact zero)."""
+    if x == 0:
+        return -0.0 if neg_zero else 0.0
+    s = -1 if x < 0 else 1
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    e = max(e, -126)
+    ulp = Fraction(2) ** (e - 23)
+    q = round(a / ulp)                       # Fraction.__round__: half to even
+    if q == 0:
+        return -0.0 if s < 0 else 0.0
+    r = float(q * ulp)
+    if r >= 2.0 ** 128 - 2.0 ** 103:         # beyond the largest float32 after rounding
+        r = math.inf
+    return s * r
+
+
+def _fma32(a, b, c) -> float:
+    a, b, c = float(a), float(b), float(c)
+    exact = Fraction(a) * Fraction(b) + Fraction(c)
+    both_neg_zero = (exact == 0 and math.copysign(1, a) * math.copysign(1, b) < 0 and math.copysign(1, c) < 0)
+    return _round_f32(exact, neg_zero=both_neg_zero)
+
+
+def _index_exact(tmap, pose, p):
+    inv_v = np.float32(1.0 / float(tmap.voxel))
+    dims = (tmap.nx, tmap.ny, tmap.nz)
+    ijk = []
+    for j in range(3):
+        a = [np.float32(np.float32(pose[3 * j + k]) * inv_v) for k in range(3)]
+        b = np.float32(np.float32(np.float32(pose[9 + j]) - np.float32(tmap.origin[j])) * inv_v) + np.float32(0.0)
+        g = _fma32(a[0], p[0], b)
+        g = _fma32(a[1], p[1], g)
+        g = _fma32(a[2], p[2], g)
+        if math.copysign(1.0, g) < 0 or not (g < dims[j]):
+            return -1
+        ijk.append(int(g))
+    return ijk[0] + tmap.nx * (ijk[1] + tmap.ny * ijk[2])
+
+
+def test_index_recipe_against_exact_rational_fma(oracle_lib):
+    """Every fused multiply-add of the recipe redone in exact rational arithmetic
+    with one rounding to float32: indices bit for bit, on random rotations and on
+    points placed on and next to cell faces (where one rounding more or less, or
+    another operation order, changes the voxel)."""
+    rng = np.random.default_rng(17)
+    nx, ny, nz = 9, 7, 5
+    v = 0.1
+    tmap = make_map(np.zeros((nz, ny, nx), np.int16), v, origin=(-0.35, 0.2, -0.15))
+    R = random_rotations(rng, 6)
+    t = rng.uniform(-0.1, 0.1, (6, 3))
+    poses = poses_from(R, t)
+    # points whose world image lands exactly on faces for the first pose
+    face = []
+    for _ in range(200):
+        ijk = rng.integers(0, [nx + 1, ny + 1, nz + 1])
+        xw = np.asarray(tmap.origin) + ijk * float(np.float32(v))
+        face.append(R[0].T @ (xw - t[0]))
+    pts = np.concatenate([np.array(face).T, rng.uniform(-0.6, 0.6, (3, 200))], axis=1).astype(np.float32)
+    # nudge a third of the points by one ulp
+    pts[:, ::3] = np.nextafter(pts[:, ::3], np.float32(np.inf))
+    lin = oracle_lib.voxel_indices(tmap, pts, poses)
+    for n in range(poses.shape[1]):
+        for k in range(pts.shape[1]):
+            assert lin[n, k] == _index_exact(tmap, poses[:, n], pts[:, k]), (n, k)
+
+
+def test_negative_zero_from_underflow_is_outside(oracle_lib):
+    """A negative exact coordinate too small for float32 rounds to -0.0 in the
+    fused recipe; it lies below 0 and reads outside.  The same magnitude with a
+    positive sign rounds to +0.0 and is inside."""
+    tmap = make_map(np.zeros((2, 2, 2), np.int16), 0.125)
+    poses = identity_poses(2)
+    poses[2, 0] = np.float32(-1e-30)       # r02: a tiny coupling of z into x,
+    poses[2, 1] = np.float32(1e-30)        # negative, then positive
+    pts = np.array([[0.0], [0.0], [1e-30]], np.float32)
+    lin = oracle_lib.voxel_indices(tmap, pts, poses)
+    assert lin[0, 0] == -1 and lin[1, 0] == 0
+    assert _index_exact(tmap, poses[:, 0], pts[:, 0]) == -1
+    assert _index_exact(tmap, poses[:, 1], pts[:, 0]) == 0
