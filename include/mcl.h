@@ -5,8 +5,9 @@
  *
  * One MCL iteration (§III) is motion update, sensor update, resampling; the
  * sensor update is the costly step the paper moves to the GPU (§IV, §V-B).
- * This library runs the sensor update, the weight normalisation and the
- * resampling on the GPU, so particle state never leaves device memory.
+ * This library runs the sensor update, the weight normalisation, the pose
+ * estimate and the resampling on the GPU, so particle state never leaves device
+ * memory.
  *
  * Conventions shared by every call:
  *  - Device pointers are plain HIP device addresses (for example a torch
@@ -84,11 +85,13 @@ mcl_status mcl_map_free(mcl_map map);
  * transformed by particle pose x_n (R p + t), and +tau for points outside the
  * map.  This is the log of the product of Eq. (3) over the scan without its
  * constant factor, which cancels in normalisation.
- * The voxel of a point follows a fixed float32 recipe (round-to-nearest-even,
- * no fused multiply-add): with inv_v = (float)(1.0 / (double)voxel),
- *     a_jk = r_jk * inv_v,  b_j = (t_j - origin_j) * inv_v,
- *     g_j  = ((a_j0*x + a_j1*y) + a_j2*z) + b_j,
- * valid iff 0 <= g_j < n_j on every axis, voxel index (int)g_j.
+ * The voxel of a point follows a fixed float32 recipe (round-to-nearest-even;
+ * fma is the IEEE fused multiply-add, one rounding): with
+ * inv_v = (float)(1.0 / (double)voxel),
+ *     a_jk = r_jk * inv_v,  b_j = (t_j - origin_j) * inv_v + 0,
+ *     g_j  = fma(a_j2, z, fma(a_j1, y, fma(a_j0, x, b_j))),
+ * valid iff 0 <= g_j < n_j on every axis with -0.0 counted below 0 (NaN is
+ * outside), voxel index (int)g_j.
  * Sums of squares are accumulated in float32 in an order that depends only on
  * K (not on N or on how the work is split), with a relative error below 3e-6.
  *   points: device, [3][K] float32; K in [0, MCL_MAX_POINTS]; may be NULL if K = 0.
@@ -149,9 +152,10 @@ mcl_status mcl_pose_estimate(const double *w, const float *poses, int32_t N, dou
 /* ------------------------------------------------------------- batching
  * One MCL update of many filters at once (the filters may use different maps,
  * particle counts and scan sizes).  mcl_tick runs, for every filter, exactly
- * mcl_sensor_update, then mcl_normalize, then mcl_resample: each stage is one
- * launch over all filters together, and every filter's results are bit for
- * bit those of the three single-filter calls.  Buffers follow the rules of the
+ * mcl_sensor_update, then mcl_normalize, then (for filters that ask for it)
+ * mcl_pose_estimate on the normalised weights and the input poses, then
+ * mcl_resample: each stage is one launch over all filters together, and every
+ * filter's results are bit for bit those of the single-filter calls.  Buffers follow the rules of the
  * single-filter calls; all buffers of all jobs must be distinct. */
 #define MCL_MAX_JOBS 4096
 
@@ -169,6 +173,10 @@ typedef struct {
     uint64_t u;             /* uniform 64-bit draw for the resampling offset      */
     int32_t *idx;           /* device out [N] ancestor indices                    */
     float *poses_out;       /* device out [12][N] resampled poses, or NULL        */
+    double *est_mean;       /* device out [12], or NULL: the pose estimate of the
+                               weighted set (as mcl_pose_estimate); needs w       */
+    int32_t *est_idx;       /* device out [1] best particle, or NULL              */
+    float *est_pose;        /* device out [12] best particle's pose, or NULL      */
 } mcl_filter_job;
 
 /* Flag for mcl_tick: the launch chain is captured into a HIP graph the first

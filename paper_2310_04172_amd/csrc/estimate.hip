@@ -74,18 +74,24 @@ __device__ inline void block_reduce(double acc[kEAcc], Best &b, double (*red)[kE
     b = rb[0];
 }
 
-__global__ __launch_bounds__(kEThreads) void estimate_partial_kernel(const double *__restrict__ w,
-                                                                    const float *__restrict__ poses, int N,
-                                                                    double *__restrict__ part,
-                                                                    Best *__restrict__ pbest) {
+// Block b of the launch works for the job whose blocks [blk0, blk0 + nblk) hold
+// b; its particles are those of index local + k nblk (in blocks of kEBlock).
+template <typename Src>
+__global__ __launch_bounds__(kEThreads) void estimate_partial_kernel(Src src) {
     __shared__ double red[kEWaves][kEAcc];
     __shared__ Best rb[kEWaves];
     __shared__ double tot[kEAcc];
+    const int blk = blockIdx.x;
+    if (blk >= src.blocks()) return;  // surplus blocks of a replayed launch
+    const EstJob J = src.load(find_job_uniform(src, blk, [](const EstJob &e) { return (int64_t)e.blk0; }));
+    const int local = blk - J.blk0, N = J.N;
+    const double *__restrict__ w = J.w;
+    const float *__restrict__ poses = J.poses;
     double acc[kEAcc];
 #pragma unroll
     for (int a = 0; a < kEAcc; ++a) acc[a] = 0.0;
     Best b{-INFINITY, 0x7fffffff};
-    for (int base = blockIdx.x * kEBlock + threadIdx.x; base < N; base += gridDim.x * kEBlock) {
+    for (int base = local * kEBlock + threadIdx.x; base < N; base += J.nblk * kEBlock) {
         double wv[kEPer];
         float pv[kEPer][12];
 #pragma unroll
@@ -119,8 +125,8 @@ __global__ __launch_bounds__(kEThreads) void estimate_partial_kernel(const doubl
         }
     }
     block_reduce(acc, b, red, rb, tot);
-    if (threadIdx.x < kEAcc) part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = tot[threadIdx.x];
-    if (threadIdx.x == 0) pbest[blockIdx.x] = b;
+    if (threadIdx.x < kEAcc) J.part[(size_t)threadIdx.x * J.nblk + local] = tot[threadIdx.x];
+    if (threadIdx.x == 0) static_cast<Best *>(J.pbest)[local] = b;
 }
 
 // 1/x and 1/sqrt(x) for x > 0 normal: the hardware estimates refined by two
@@ -248,15 +254,21 @@ __device__ inline Quat sym4_top_eigvec(double (&A)[4][4]) {
     return Quat{col[0] / nrm, col[1] / nrm, col[2] / nrm, col[3] / nrm};
 }
 
-__global__ __launch_bounds__(kEThreads) void estimate_final_kernel(const double *__restrict__ part,
-                                                                  const Best *__restrict__ pbest, int nb, int N,
-                                                                  const float *__restrict__ poses,
-                                                                  double *__restrict__ mean,
-                                                                  int32_t *__restrict__ best_idx,
-                                                                  float *__restrict__ best_pose) {
+// One block per job: the job's block partials, then the estimate.
+template <typename Src>
+__global__ __launch_bounds__(kEThreads) void estimate_final_kernel(Src src) {
     __shared__ double red[kEWaves][kEAcc];
     __shared__ Best rb[kEWaves];
     __shared__ double tot[kEAcc];
+    if ((int)blockIdx.x >= src.count()) return;
+    const EstJob J = src.load(blockIdx.x);
+    const int nb = J.nblk, N = J.N;
+    const double *__restrict__ part = J.part;
+    const Best *__restrict__ pbest = static_cast<const Best *>(J.pbest);
+    const float *__restrict__ poses = J.poses;
+    double *__restrict__ mean = J.mean;
+    int32_t *__restrict__ best_idx = J.best_idx;
+    float *__restrict__ best_pose = J.best_pose;
     double acc[kEAcc];
 #pragma unroll
     for (int a = 0; a < kEAcc; ++a) acc[a] = 0.0;
@@ -302,25 +314,44 @@ __global__ __launch_bounds__(kEThreads) void estimate_final_kernel(const double 
     for (int j = 0; j < 3; ++j) mean[9 + j] = ts[j] / den;
 }
 
-static int estimate_blocks(int N) { return std::min((N + kEBlock - 1) / kEBlock, kEMaxBlocks); }
+int estimate_blocks(int N) { return std::min((N + kEBlock - 1) / kEBlock, kEMaxBlocks); }
 
 size_t estimate_ws_bytes(int N) {
     const size_t nb = estimate_blocks(N);
     return nb * kEAcc * sizeof(double) + nb * sizeof(Best);
 }
 
-mcl_status launch_estimate(const double *w, const float *poses, int N, double *mean, int32_t *best_idx,
-                           float *best_pose, hipStream_t stream) {
-    const int nb = estimate_blocks(N);
-    char *ws = static_cast<char *>(workspace(stream, estimate_ws_bytes(N)));
-    if (!ws) return fail(MCL_ENOMEM, "pose_estimate: workspace allocation failed");
-    double *part = reinterpret_cast<double *>(ws);
-    Best *pbest = reinterpret_cast<Best *>(part + (size_t)nb * kEAcc);
-    estimate_partial_kernel<<<nb, kEThreads, 0, stream>>>(w, poses, N, part, pbest);
+void bind_estimate_ws(EstJob &J, void *ws) {
+    J.nblk = estimate_blocks(J.N);
+    J.part = static_cast<double *>(ws);
+    J.pbest = J.part + (size_t)J.nblk * kEAcc;
+}
+
+template <typename Src>
+mcl_status launch_estimate_src(const Src &src, int64_t blocks, int64_t jobs, hipStream_t stream) {
+    estimate_partial_kernel<Src><<<(unsigned)blocks, kEThreads, 0, stream>>>(src);
     mcl_status st = check_launch("estimate_partial_kernel");
     if (st != MCL_OK) return st;
-    estimate_final_kernel<<<1, kEThreads, 0, stream>>>(part, pbest, nb, N, poses, mean, best_idx, best_pose);
+    estimate_final_kernel<Src><<<(unsigned)jobs, kEThreads, 0, stream>>>(src);
     return check_launch("estimate_final_kernel");
+}
+
+template mcl_status launch_estimate_src<JobTable<EstJob>>(const JobTable<EstJob> &, int64_t, int64_t, hipStream_t);
+
+mcl_status launch_estimate(const double *w, const float *poses, int N, double *mean, int32_t *best_idx,
+                           float *best_pose, hipStream_t stream) {
+    char *ws = static_cast<char *>(workspace(stream, estimate_ws_bytes(N)));
+    if (!ws) return fail(MCL_ENOMEM, "pose_estimate: workspace allocation failed");
+    EstJob J{};
+    J.w = w;
+    J.poses = poses;
+    J.mean = mean;
+    J.best_idx = best_idx;
+    J.best_pose = best_pose;
+    J.N = N;
+    bind_estimate_ws(J, ws);
+    OneJob<EstJob> one{J, Counts{1, 0, N, J.nblk}};
+    return launch_estimate_src(one, J.nblk, 1, stream);
 }
 
 }  // namespace mcl

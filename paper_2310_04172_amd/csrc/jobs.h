@@ -56,6 +56,25 @@ struct WeightJob {
     int32_t nblk, N, pad_;
 };
 
+// Pose estimate of one filter (weighted mean and best particle).
+struct EstJob {
+    const double *w;      // [N] normalised weights
+    const float *poses;   // [12][N]
+    double *mean;         // [12] output
+    int32_t *best_idx;    // [1] output or null
+    float *best_pose;     // [12] output or null
+    double *part;         // workspace [accumulators][nblk]
+    void *pbest;          // workspace [nblk] (weight, index) pairs
+    int32_t N;
+    int32_t nblk;         // blocks of this job (a function of N alone)
+    int32_t blk0;         // first block of this job in the launch
+    int32_t pad_;
+};
+
+int estimate_blocks(int N);
+size_t estimate_ws_bytes(int N);
+void bind_estimate_ws(EstJob &J, void *ws);
+
 // ------------------------------------------------------------ job sources
 // Copy a wave-uniform descriptor out of memory into scalar registers: every
 // lane reads the same words, readfirstlane makes the copy provably uniform.

@@ -1,5 +1,5 @@
-// Batched tick: sensor update, normalisation and resampling of many filters in
-// one launch per stage.  Job tables and totals live in device memory, so the
+// Batched tick: sensor update, normalisation, pose estimate and resampling of
+// many filters in one launch per stage.  Job tables and totals live in device memory, so the
 // launch chain does not depend on the job set: it is captured once into a HIP
 // graph (per stream, per storage-type mix and launch shape) and replayed every
 // tick after the tables are copied in.
@@ -22,6 +22,8 @@ template <typename Src>
 mcl_status launch_normalize_src(const Src &, int, int64_t, int64_t, hipStream_t);
 template <typename Src>
 mcl_status launch_resample_src(const Src &, int64_t, int64_t, hipStream_t);
+template <typename Src>
+mcl_status launch_estimate_src(const Src &, int64_t, int64_t, hipStream_t);
 size_t weight_ws_bytes(int N);
 void bind_weight_ws(WeightJob &J, void *ws);
 
@@ -30,14 +32,18 @@ constexpr int kGroups = 3;  // storage types
 
 static constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Device/staging layout: Counts[kGroups + 1] | SensorJob[kGroups][kMaxJobs] | WeightJob[kMaxJobs].
-// Each storage type has its own sensor table at a fixed place, so a captured
-// chain stays valid however the jobs of a tick split among the types.
-static constexpr size_t kCountsBytes = align256(sizeof(Counts) * (kGroups + 1));
+// Device/staging layout: Counts[kGroups + 2] | SensorJob[kGroups][kMaxJobs] |
+// WeightJob[kMaxJobs] | EstJob[kMaxJobs].  Each storage type has its own sensor
+// table at a fixed place, so a captured chain stays valid however the jobs of a
+// tick split among the types.  Counts: one per storage type, the weights', the
+// estimates'.
+static constexpr int kWeightCnt = kGroups, kEstCnt = kGroups + 1;
+static constexpr size_t kCountsBytes = align256(sizeof(Counts) * (kGroups + 2));
 static constexpr size_t kSensorTblOff = kCountsBytes;
 static constexpr size_t kSensorTblBytes = align256(sizeof(SensorJob) * kMaxJobs);
 static constexpr size_t kWeightTblOff = kSensorTblOff + kGroups * kSensorTblBytes;
-static constexpr size_t kTablesBytes = kWeightTblOff + align256(sizeof(WeightJob) * kMaxJobs);
+static constexpr size_t kEstTblOff = kWeightTblOff + align256(sizeof(WeightJob) * kMaxJobs);
+static constexpr size_t kTablesBytes = kEstTblOff + align256(sizeof(EstJob) * kMaxJobs);
 
 namespace {
 
@@ -45,10 +51,11 @@ namespace {
 struct GraphKey {
     int mask;
     int wpb, bpc;
-    int64_t items[3], elems, blocks;
+    int64_t items[3], elems, blocks, eblocks, ejobs;
     bool operator<(const GraphKey &o) const {
-        return std::tie(mask, wpb, bpc, items[0], items[1], items[2], elems, blocks) <
-               std::tie(o.mask, o.wpb, o.bpc, o.items[0], o.items[1], o.items[2], o.elems, o.blocks);
+        return std::tie(mask, wpb, bpc, items[0], items[1], items[2], elems, blocks, eblocks, ejobs) <
+               std::tie(o.mask, o.wpb, o.bpc, o.items[0], o.items[1], o.items[2], o.elems, o.blocks, o.eblocks,
+                        o.ejobs);
     }
 };
 
@@ -78,16 +85,17 @@ void drop_graphs(TickState &S) {
     S.graph_defs.clear();
 }
 
-size_t job_ws_bytes(int N, int K) {
+size_t job_ws_bytes(int N, int K, bool est) {
     const int np = sensor_pieces(K);
     size_t b = align256(weight_ws_bytes(N));
     if (np > 1) b += align256((size_t)np * N * sizeof(float));
+    if (est) b += align256(estimate_ws_bytes(N));
     return b;
 }
 
 }  // namespace
 
-size_t tick_job_bytes(int N, int K) { return job_ws_bytes(N, K); }
+size_t tick_job_bytes(int N, int K) { return job_ws_bytes(N, K, true); }
 
 mcl_status check_job(const mcl_filter_job &J, int j) {
     std::string at = "tick: job " + std::to_string(j) + ": ";
@@ -97,6 +105,9 @@ mcl_status check_job(const mcl_filter_job &J, int j) {
     if (J.K > MCL_MAX_POINTS || J.N > MCL_MAX_PARTICLES) return fail(MCL_ERANGE, at + "K or N above the limit");
     if (J.K > 0 && !J.points) return fail(MCL_EINVAL, at + "NULL points with K > 0");
     if (!(std::isfinite(J.sigma) && J.sigma > 0.0f)) return fail(MCL_EINVAL, at + "sigma must be finite and > 0");
+    if (!J.est_mean && (J.est_idx || J.est_pose))
+        return fail(MCL_EINVAL, at + "est_idx or est_pose without est_mean");
+    if (J.est_mean && !J.w) return fail(MCL_EINVAL, at + "a pose estimate needs the weights w");
     return MCL_OK;
 }
 
@@ -106,9 +117,9 @@ using namespace mcl;
 
 extern "C" size_t mcl_job_bytes(int32_t N, int32_t K) {
     if (N < 1 || K < 0) return 0;
-    // caller buffers: poses in + out, logw, w, wq, idx, scan; then library workspace
-    size_t caller = (size_t)N * (48 + 48 + 4 + 8 + 8 + 4) + (size_t)K * 12;
-    return caller + tick_job_bytes(N, K) + sizeof(SensorJob) + sizeof(WeightJob);
+    // caller buffers: poses in + out, logw, w, wq, idx, scan, estimate; then library workspace
+    size_t caller = (size_t)N * (48 + 48 + 4 + 8 + 8 + 4) + (size_t)K * 12 + 12 * 8 + 4 + 12 * 4;
+    return caller + tick_job_bytes(N, K) + sizeof(SensorJob) + sizeof(WeightJob) + sizeof(EstJob);
 }
 
 extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32_t flags, void *stream_) {
@@ -136,7 +147,12 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     for (int g = 0; g < kGroups; ++g) mask |= (g_begin[g + 1] > g_begin[g]) << g;
 
     size_t need = kTablesBytes;
-    for (int j = 0; j < n_jobs; ++j) need += job_ws_bytes(jobs[j].N, jobs[j].K);
+    int n_est = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        need += job_ws_bytes(jobs[j].N, jobs[j].K, jobs[j].est_mean != nullptr);
+        n_est += jobs[j].est_mean != nullptr;
+    }
+    if (n_est) mask |= 1 << kGroups;
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(MCL_EDEVICE, "tick: no device");
@@ -163,7 +179,10 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
 
     Counts *cnt = reinterpret_cast<Counts *>(S.host);
     WeightJob *wtbl = reinterpret_cast<WeightJob *>(S.host + kWeightTblOff);
+    EstJob *etbl = reinterpret_cast<EstJob *>(S.host + kEstTblOff);
     std::memset(cnt, 0, kCountsBytes);
+    int64_t eblk = 0, eelem = 0;
+    int ne = 0;
     char *ws = S.dev + kTablesBytes;
     bool combine[kGroups] = {false, false, false};
     int64_t wblk = 0, welem = 0;
@@ -205,10 +224,26 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             W.blk0 = (int32_t)wblk;
             welem += F.N;
             wblk += W.nblk;
+            if (F.est_mean) {
+                EstJob &E = etbl[ne++];
+                std::memset(&E, 0, sizeof E);
+                E.w = F.w;
+                E.poses = F.poses;
+                E.mean = F.est_mean;
+                E.best_idx = F.est_idx;
+                E.best_pose = F.est_pose;
+                E.N = F.N;
+                bind_estimate_ws(E, ws);
+                ws += align256(estimate_ws_bytes(F.N));
+                E.blk0 = (int32_t)eblk;
+                eblk += E.nblk;
+                eelem += F.N;
+            }
         }
         cnt[g] = Counts{g_begin[g + 1] - g_begin[g], items, elems, 0};
     }
-    cnt[kGroups] = Counts{n_jobs, 0, welem, wblk};
+    cnt[kWeightCnt] = Counts{n_jobs, 0, welem, wblk};
+    cnt[kEstCnt] = Counts{ne, 0, eelem, eblk};
 
     bool ok = hipMemcpyAsync(S.dev, S.host, kCountsBytes, hipMemcpyHostToDevice, stream) == hipSuccess;
     for (int g = 0; g < kGroups && ok; ++g) {
@@ -218,6 +253,9 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     }
     ok = ok && hipMemcpyAsync(S.dev + kWeightTblOff, S.host + kWeightTblOff, (size_t)n_jobs * sizeof(WeightJob),
                               hipMemcpyHostToDevice, stream) == hipSuccess;
+    if (ne)
+        ok = ok && hipMemcpyAsync(S.dev + kEstTblOff, S.host + kEstTblOff, (size_t)ne * sizeof(EstJob),
+                                  hipMemcpyHostToDevice, stream) == hipSuccess;
     if (!ok || hipEventRecord(S.copied, stream) != hipSuccess) return fail(MCL_EDEVICE, "tick: table copy failed");
     S.pending = true;
 
@@ -230,10 +268,12 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     LaunchCfg cfg = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
     const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
     const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
-    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu, {0, 0, 0}, 0, 0};
+    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu, {0, 0, 0}, 0, 0, 0, 0};
     for (int g = 0; g < kGroups; ++g) key.items[g] = use_graph ? bucket(cnt[g].items) : cnt[g].items;
     key.elems = use_graph ? bucket(welem) : welem;
     key.blocks = use_graph ? bucket(wblk) : wblk;
+    key.eblocks = use_graph ? bucket(eblk) : eblk;
+    key.ejobs = use_graph ? bucket(ne) : ne;
     auto chain = [&]() -> mcl_status {
         for (int g = 0; g < kGroups; ++g) {
             if (!(mask >> g & 1)) continue;
@@ -243,9 +283,14 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             mcl_status st = launch_sensor_src(g, src, key.items[g], key.elems, use_graph || combine[g], cfg, stream);
             if (st != MCL_OK) return st;
         }
-        JobTable<WeightJob> wsrc{dwt, dcnt + kGroups};
+        JobTable<WeightJob> wsrc{dwt, dcnt + kWeightCnt};
         mcl_status st = launch_normalize_src(wsrc, use_graph ? kMaxJobs : n_jobs, key.blocks, key.elems, stream);
         if (st != MCL_OK) return st;
+        if (key.ejobs) {
+            JobTable<EstJob> esrc{reinterpret_cast<const EstJob *>(S.dev + kEstTblOff), dcnt + kEstCnt};
+            st = launch_estimate_src(esrc, key.eblocks, key.ejobs, stream);
+            if (st != MCL_OK) return st;
+        }
         return launch_resample_src(wsrc, key.blocks, key.elems, stream);
     };
     if (!use_graph) return chain();

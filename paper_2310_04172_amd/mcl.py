@@ -40,7 +40,7 @@ class MapDesc(C.Structure):
 class FilterJob(C.Structure):
     _fields_ = [("map", _P), ("points", _P), ("K", C.c_int32), ("poses", _P), ("N", C.c_int32),
                 ("sigma", C.c_float), ("logw", _P), ("w", _P), ("wq", _P), ("log_z", _P), ("u", C.c_uint64),
-                ("idx", _P), ("poses_out", _P)]
+                ("idx", _P), ("poses_out", _P), ("est_mean", _P), ("est_idx", _P), ("est_pose", _P)]
 
 
 class LaunchConfig(C.Structure):
@@ -229,7 +229,8 @@ class Filter:
     buffers are allocated here unless given.
     """
 
-    def __init__(self, m: Map, points, poses, sigma: float, u: int, want_w: bool = True, resample_poses: bool = True):
+    def __init__(self, m: Map, points, poses, sigma: float, u: int, want_w: bool = True, resample_poses: bool = True,
+                 want_estimate: bool = False):
         import torch
         self.map = m
         self.points = points
@@ -244,6 +245,11 @@ class Filter:
         self.log_z = torch.empty(1, dtype=torch.float64, device=dev)
         self.idx = torch.empty(N, dtype=torch.int32, device=dev)
         self.poses_out = torch.empty_like(poses) if resample_poses else None
+        if want_estimate and self.w is None:
+            raise ValueError("a pose estimate needs the weights (want_w=True)")
+        self.est_mean = torch.empty(12, dtype=torch.float64, device=dev) if want_estimate else None
+        self.est_idx = torch.empty(1, dtype=torch.int32, device=dev) if want_estimate else None
+        self.est_pose = torch.empty(12, dtype=torch.float32, device=dev) if want_estimate else None
 
     @property
     def N(self):
@@ -260,11 +266,12 @@ class Filter:
             _dev(self.points, torch.float32, (3, self.K), "points")
         return FilterJob(self.map.handle, _ptr(self.points) if self.K else None, self.K, _ptr(self.poses), self.N,
                          self.sigma, _ptr(self.logw), _ptr(self.w), _ptr(self.wq), _ptr(self.log_z),
-                         self.u & (2 ** 64 - 1), _ptr(self.idx), _ptr(self.poses_out))
+                         self.u & (2 ** 64 - 1), _ptr(self.idx), _ptr(self.poses_out), _ptr(self.est_mean),
+                         _ptr(self.est_idx), _ptr(self.est_pose))
 
 
 def tick(filters, graph: bool = False, stream=None):
-    """One batched update (sensor, normalise, resample) of every filter."""
+    """One batched update (sensor, normalise, pose estimate if asked, resample) of every filter."""
     arr = (FilterJob * len(filters))(*[f.job() for f in filters])
     _check(_lib.mcl_tick(arr, len(filters), TICK_GRAPH if graph else 0, _stream(stream)), "mcl_tick")
 

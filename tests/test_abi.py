@@ -81,6 +81,13 @@ def test_tick_and_tuning_argument_errors(mcl):
     assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL
     assert b"job 1" in lib.mcl_last_error()
     assert lib.mcl_tick(jobs, mcl.MAX_JOBS + 1, 0, None) == mcl.MCL_ERANGE
+    # a pose estimate needs the weights; its optional outputs need est_mean
+    jobs[1].sigma = 0.1
+    jobs[1].est_mean = P(0x7000)
+    assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL and b"needs the weights" in lib.mcl_last_error()
+    jobs[1].est_mean = None
+    jobs[1].est_idx = P(0x7100)
+    assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL and b"without est_mean" in lib.mcl_last_error()
     assert lib.mcl_job_bytes(0, 5) == 0
     assert lib.mcl_job_bytes(1000, 28800) > 1000 * 120
     bad = mcl.LaunchConfig(3, 0)

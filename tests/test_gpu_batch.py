@@ -1,8 +1,9 @@
 """Batched tick (mcl_tick), graph replay and launch-shape tuning, through the C ABI.
 
-The contract: every filter in a tick gets bit for bit the results of the three
-single-filter calls, eagerly or replayed from a captured graph, and no launch
-shape changes any result.
+The contract: every filter in a tick gets bit for bit the results of the
+single-filter calls (sensor update, normalisation, pose estimate for the
+filters that ask for one, resampling), eagerly or replayed from a captured
+graph, and no launch shape changes any result.
 """
 
 import sys
@@ -59,7 +60,7 @@ def job_set(torch, mcl, seed, maps, specs):
         poses = poses_from(random_rotations(rng, N), rng.uniform(0, 1, (N, 3)) * ext)
         pts = rng.normal(0, 0.3 * ext.mean(), size=(3, K)).astype(np.float32) if K else None
         f = mcl.Filter(m, dev(torch, pts) if K else None, dev(torch, poses), f32(0.1 + 0.05 * mi),
-                       int(rng.integers(0, 2 ** 63)))
+                       int(rng.integers(0, 2 ** 63)), want_estimate=len(filters) % 2 == 0)
         filters.append(f)
     return filters
 
@@ -68,17 +69,20 @@ def single(torch, mcl, f):
     lw = mcl.sensor_update(f.map, f.points, f.poses, f.sigma)
     w, wq, lz = mcl.normalize(lw)
     idx, pout = mcl.resample(wq, f.u, f.poses)
+    est = mcl.pose_estimate(w, f.poses) if f.est_mean is not None else ()
     torch.cuda.synchronize()
-    return [x.cpu().numpy() for x in (lw, w, wq, lz, idx, pout)]
+    return [x.cpu().numpy() for x in (lw, w, wq, lz, idx, pout, *est)]
 
 
 def outputs(torch, f):
     torch.cuda.synchronize()
-    return [x.cpu().numpy() for x in (f.logw, f.w, f.wq, f.log_z, f.idx, f.poses_out)]
+    est = (f.est_mean, f.est_idx, f.est_pose) if f.est_mean is not None else ()
+    return [x.cpu().numpy() for x in (f.logw, f.w, f.wq, f.log_z, f.idx, f.poses_out, *est)]
 
 
 def assert_same(a, b, what):
-    names = ("logw", "w", "wq", "log_z", "idx", "poses_out")
+    assert len(a) == len(b), what
+    names = ("logw", "w", "wq", "log_z", "idx", "poses_out", "est_mean", "est_idx", "est_pose")
     for n, x, y in zip(names, a, b):
         assert x.dtype == y.dtype and np.array_equal(x.view(np.uint8), y.view(np.uint8)), f"{what}: {n} differs"
 
@@ -113,6 +117,9 @@ def test_tick_graph_replay(torch, mcl, maps):
     s = torch.cuda.Stream()
     for rep, (seed, specs) in enumerate([(10, SPECS), (11, SPECS[::-1]), (12, SPECS[2:7]), (13, SPECS)]):
         filters = job_set(torch, mcl, seed, maps, specs)
+        if rep == 2:  # a tick without any pose estimate between ticks with them
+            for f in filters:
+                f.est_mean = f.est_idx = f.est_pose = None
         torch.cuda.synchronize()
         with torch.cuda.stream(s):
             mcl.tick(filters, graph=True, stream=s)
