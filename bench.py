@@ -12,7 +12,8 @@ Prints one JSON line.  `value` is particle-point evaluations per second
 update) measured with HIP events on its stream; `cpu_baseline` times the CPU
 oracle on a bounded particle sample of the same workload.
 
-Other workloads (not the default line): --workload estimate (the pose estimate alone,
+Other workloads (not the default line): --workload trilinear (the default workload with
+the trilinear map lookup), --workload estimate (the pose estimate alone,
 2^14 to 2^21 particles), --workload small (1,000 particles in a
 small office map), --workload batched (64 filters: sequential single-filter
 calls vs one batched tick, eager and graph-replayed), --workload served (256
@@ -120,8 +121,9 @@ def base_record(args, metric, value, ms_step, config, dtype="f32"):
             "config": config}
 
 
-def run_single(args, w, workload_key, with_roofline=True):
-    """A plain single-filter update: sensor update + normalise + resample, timed."""
+def run_single(args, w, workload_key, with_roofline=True, trilinear=False):
+    """A plain single-filter update: sensor update + normalise + resample, timed.
+    trilinear: the sensor update reads the map by trilinear interpolation."""
     import torch
     from paper_2310_04172_amd import mcl
 
@@ -144,7 +146,10 @@ def run_single(args, w, workload_key, with_roofline=True):
         if timed:
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-        mcl.sensor_update(m, pts, poses, w.sigma, logw, stream)
+        if trilinear:
+            mcl.sensor_update_trilinear(m, pts, poses, w.sigma, logw, stream)
+        else:
+            mcl.sensor_update(m, pts, poses, w.sigma, logw, stream)
         if timed:
             b.record(stream)
             ev.append((a, b))
@@ -181,11 +186,12 @@ def run_single(args, w, workload_key, with_roofline=True):
     out = base_record(args, METRIC,
                       evals / (ms_step * 1e-3) / 1e9, ms_step,
                       {"workload": w.name, "N": N, "K": K, "map_dtype": w.tmap.dtype,
-                       "step": "sensor update + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
+                       "step": ("sensor update (trilinear lookup)" if trilinear else "sensor update") +
+                               " + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
                        "workload_key": workload_key, "sensor_update_ms": sensor_ms})
     out["latency_ms"] = {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}
     out["pose_estimate"] = est
-    if with_roofline:
+    if with_roofline and not trilinear:
         flops = 20.0 * evals   # 9 fused multiply-adds (transform) + 1 (score), 2 flops each, per evaluation
         achieved = flops / (sensor_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -430,7 +436,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision", "estimate"])
+    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision", "estimate", "trilinear"])
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -459,10 +465,12 @@ def main():
         out = run_estimate(args)
     else:
         t0 = time.perf_counter()
-        w = configs.config2() if args.workload == "global" else configs.config1()
+        w = configs.config1() if args.workload == "small" else configs.config2()
         log(f"workload built in {time.perf_counter() - t0:.1f} s: N={w.N} K={w.K}")
-        out = run_single(args, w, args.workload)
-        if not args.no_cpu_baseline:
+        out = run_single(args, w, args.workload, trilinear=args.workload == "trilinear")
+        if args.workload == "trilinear":
+            out["metric"] = METRIC + " [trilinear lookup]"
+        if not args.no_cpu_baseline and args.workload != "trilinear":
             out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

@@ -101,6 +101,24 @@ mcl_status mcl_map_free(mcl_map map);
 mcl_status mcl_sensor_update(mcl_map map, const float *points, int32_t K, const float *poses,
                              int32_t N, float sigma, float *logw, void *stream);
 
+/* Sensor update with a trilinear lookup (§III: a pseudo-continuous map value by
+ * interpolation).  As mcl_sensor_update, except that m(x_n, z_k) is the
+ * trilinear interpolation of the 8 voxel centres around the transformed point
+ * (the stored values sit at the centres; a centre outside the map reads +tau).
+ * With g_j from the recipe above, in float32:
+ *     h_j = min(max(g_j - 0.5, -2), n_j + 1),  i_j = floor(h_j),  f_j = h_j - i_j,
+ * and m = sum over the 8 corners (i_x + a, i_y + b, i_z + c), a, b, c in {0, 1},
+ * of (a ? f_x : 1 - f_x)(b ? f_y : 1 - f_y)(c ? f_z : 1 - f_z) * value, computed
+ * as lerps along x, then y, then z, lerp(p, q, t) = fma(t, q - p, p).
+ * Each interpolated value is within 10 eps M of the exact one (M the largest
+ * stored magnitude, eps = 2^-24: three levels of lerps, each adding at most one
+ * rounding of its fma and one of its difference), so the relative error of logw
+ * is at most the float32 sum bound above plus
+ * (20 eps M sum|m| + 100 K eps^2 M^2) / sum m^2.  Arguments and errors as for
+ * mcl_sensor_update. */
+mcl_status mcl_sensor_update_trilinear(mcl_map map, const float *points, int32_t K, const float *poses,
+                                       int32_t N, float sigma, float *logw, void *stream);
+
 /* Weight normalisation (§V-A: the particle weights are summed for
  * normalisation), float64 log-sum-exp:
  *     log_z = max_n l_n + log sum_n exp(l_n - max l),  w_n = exp(l_n - log_z),

@@ -45,9 +45,12 @@ def lib():
         L.oracle_voxel_indices.argtypes = [P, C.c_float, P, P, C.c_int32, P, C.c_int32, P]
         L.oracle_sensor_update.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, P, P, C.c_int32,
                                            P, C.c_int32, C.c_float, P, P, C.c_int32]
+        L.oracle_sensor_update_trilinear.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, P, P, C.c_int32,
+                                                     P, C.c_int32, C.c_float, P, P, P, C.c_int32]
         L.oracle_normalize.argtypes = [P, C.c_int32, P, P, P]
         L.oracle_resample.argtypes = [P, C.c_int32, C.c_uint64, P]
-        for f in (L.oracle_voxel_indices, L.oracle_sensor_update, L.oracle_normalize, L.oracle_resample):
+        for f in (L.oracle_voxel_indices, L.oracle_sensor_update, L.oracle_sensor_update_trilinear,
+                  L.oracle_normalize, L.oracle_resample):
             f.restype = C.c_int
         _lib = L
     return _lib
@@ -91,6 +94,23 @@ def sensor_update(tmap, points: np.ndarray, poses: np.ndarray, sigma: float, nth
                                     _p(vals), _p(pts), K, _p(ps), N, sigma, _p(logw), _p(ssum), nthreads)
     assert rc == 0
     return (logw, ssum) if return_sum else logw
+
+
+def sensor_update_trilinear(tmap, points: np.ndarray, poses: np.ndarray, sigma: float, nthreads: int = 1,
+                            return_sums: bool = False):
+    """float64 log-weights with the trilinear lookup (and optionally sum m^2, sum |m|)."""
+    dims, origin, vals = _map_args(tmap)
+    pts = np.ascontiguousarray(points, np.float32)
+    ps = np.ascontiguousarray(poses, np.float32)
+    K, N = pts.shape[1], ps.shape[1]
+    logw = np.empty(N, np.float64)
+    ssum = np.empty(N, np.float64)
+    sabs = np.empty(N, np.float64)
+    rc = lib().oracle_sensor_update_trilinear(_p(dims), tmap.voxel, _p(origin), tmap.tau, DTYPE_CODE[tmap.dtype],
+                                              _p(vals), _p(pts), K, _p(ps), N, sigma, _p(logw), _p(ssum),
+                                              _p(sabs), nthreads)
+    assert rc == 0
+    return (logw, ssum, sabs) if return_sums else logw
 
 
 def normalize(logw: np.ndarray):

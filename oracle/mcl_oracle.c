@@ -48,6 +48,20 @@
  *    unquantised distances) serves as the precision reference of the storage
  *    types.
  *
+ *  Trilinear lookup (§III: a pseudo-continuous state by interpolation).
+ *    Reading: the stored values sit at the voxel centres, grid coordinate
+ *    i + 1/2; a point's map value is the trilinear interpolation of the 8
+ *    centres around it, a centre outside the map reading +Q (+tau).  Recipe:
+ *    g_j as above (float32), then in float32
+ *        h_j = g_j - 0.5 ;  h_j = min(max(h_j, -2), n_j + 1) ;
+ *        i_j = (int) floor(h_j) ;  f_j = h_j - floor(h_j)   (exact),
+ *    (the clamp only moves points whose 8 centres are all outside, and sends
+ *    NaN there), then in float64
+ *        m = sum over a, b, c in {0, 1} of
+ *            (a ? f_x : 1 - f_x)(b ? f_y : 1 - f_y)(c ? f_z : 1 - f_z) d(i_x + a, i_y + b, i_z + c)
+ *    with d the stored value (int16 / int8 in units of Q, or metres), and
+ *        l_n = -(s^2 / (2 sigma^2)) * sum_k m_k^2.
+ *
  *  Normalisation (§V-A sums the weights for normalisation), float64:
  *        m = max_n l_n ;  S = sum_n exp(l_n - m) in index order ;
  *        log Z = m + log S ;  w_n = exp(l_n - log Z) ;
@@ -243,6 +257,125 @@ int oracle_sensor_update(const int32_t dims[3], float voxel, const float origin[
         jobs[t].n0 = (int64_t)N * t / nthreads;
         jobs[t].n1 = (int64_t)N * (t + 1) / nthreads;
         pthread_create(&th[t], NULL, su_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(jobs);
+    free(th);
+    return 0;
+}
+
+/* ------------------------------------------------------- trilinear lookup */
+
+/* Stored value at voxel (i, j, k), or the out-of-map value. */
+static double stored_value(const su_job_t *J, int64_t i, int64_t j, int64_t k) {
+    const grid_t *g = &J->g;
+    if (i < 0 || j < 0 || k < 0 || i >= g->n[0] || j >= g->n[1] || k >= g->n[2])
+        return J->dtype >= ORACLE_F32 ? (double)(float)J->tau : (double)J->Q;
+    int64_t v = i + (int64_t)g->n[0] * (j + (int64_t)g->n[1] * k);
+    switch (J->dtype) {
+    case ORACLE_I16: return ((const int16_t *)J->values)[v];
+    case ORACLE_I8: return ((const int8_t *)J->values)[v];
+    case ORACLE_F32: return ((const float *)J->values)[v];
+    default: return ((const double *)J->values)[v];
+    }
+}
+
+/* Interpolated map value of one point for particle constants a, b. */
+static double trilinear_value(const su_job_t *J, const float a[9], const float b[3], float px, float py,
+                              float pz) {
+    int64_t i0[3];
+    double f[3];
+    for (int j = 0; j < 3; ++j) {
+        float s = fmaf(a[3 * j + 0], px, b[j]);
+        s = fmaf(a[3 * j + 1], py, s);
+        s = fmaf(a[3 * j + 2], pz, s);
+        float h = s - 0.5f;
+        h = fminf(fmaxf(h, -2.0f), (float)J->g.n[j] + 1.0f);
+        float fl = floorf(h);
+        i0[j] = (int64_t)fl;
+        f[j] = (double)(h - fl);
+    }
+    double m = 0.0;
+    for (int c = 0; c < 2; ++c)
+        for (int bb = 0; bb < 2; ++bb)
+            for (int aa = 0; aa < 2; ++aa) {
+                double wgt = (aa ? f[0] : 1.0 - f[0]) * (bb ? f[1] : 1.0 - f[1]) * (c ? f[2] : 1.0 - f[2]);
+                m += wgt * stored_value(J, i0[0] + aa, i0[1] + bb, i0[2] + c);
+            }
+    return m;
+}
+
+typedef struct {
+    su_job_t base;
+    double *sabs;
+} tri_job_t;
+
+static void *tri_worker(void *arg) {
+    tri_job_t *T = (tri_job_t *)arg;
+    const su_job_t *J = &T->base;
+    const float *px = J->points, *py = J->points + J->K, *pz = J->points + 2 * J->K;
+    for (int64_t n = J->n0; n < J->n1; ++n) {
+        float a[9], b[3];
+        particle_consts(J->poses, J->N, n, &J->g, a, b);
+        double S = 0.0, A = 0.0;
+        for (int64_t k = 0; k < J->K; ++k) {
+            double m = trilinear_value(J, a, b, px[k], py[k], pz[k]);
+            S += m * m;
+            A += fabs(m);
+        }
+        if (J->ssum) J->ssum[n] = S;
+        if (T->sabs) T->sabs[n] = A;
+        J->logw[n] = -(S * J->c);
+    }
+    return NULL;
+}
+
+/*
+ * l_n with the trilinear lookup (see the header comment).  ssum / sabs may be
+ * NULL; else they receive sum m^2 and sum |m| per particle (stored units).
+ */
+int oracle_sensor_update_trilinear(const int32_t dims[3], float voxel, const float origin[3], float tau,
+                                   int32_t dtype, const void *values, const float *points, int32_t K,
+                                   const float *poses, int32_t N, float sigma, double *logw, double *ssum,
+                                   double *sabs, int32_t nthreads) {
+    if (K < 0 || N < 0 || dtype < 0 || dtype > 3 || !(sigma > 0.0f)) return -1;
+    tri_job_t base;
+    memset(&base, 0, sizeof base);
+    su_job_t *B = &base.base;
+    B->g = make_grid(dims, voxel, origin);
+    B->dtype = dtype;
+    B->values = values;
+    B->tau = (double)tau;
+    B->Q = dtype == ORACLE_I16 ? 32767 : dtype == ORACLE_I8 ? 127 : 1;
+    B->points = points;
+    B->K = K;
+    B->poses = poses;
+    B->N = N;
+    double s = dtype >= ORACLE_F32 ? 1.0 : (double)tau / (double)B->Q;
+    double sg = (double)sigma;
+    B->c = (s * s) / (2.0 * sg * sg);
+    B->logw = logw;
+    B->ssum = ssum;
+    base.sabs = sabs;
+    if (nthreads <= 1 || N < 2) {
+        B->n0 = 0;
+        B->n1 = N;
+        tri_worker(&base);
+        return 0;
+    }
+    if (nthreads > N) nthreads = N;
+    tri_job_t *jobs = (tri_job_t *)malloc(sizeof(tri_job_t) * (size_t)nthreads);
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    if (!jobs || !th) {
+        free(jobs);
+        free(th);
+        return -2;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = base;
+        jobs[t].base.n0 = (int64_t)N * t / nthreads;
+        jobs[t].base.n1 = (int64_t)N * (t + 1) / nthreads;
+        pthread_create(&th[t], NULL, tri_worker, &jobs[t]);
     }
     for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
     free(jobs);

@@ -9,6 +9,8 @@
 namespace mcl {
 
 mcl_status launch_sensor(const mcl_map_s *, const float *, int, const float *, int, float, float *, hipStream_t);
+mcl_status launch_sensor_trilinear(mcl_map_s *, const float *, int, const float *, int, float, float *,
+                                   hipStream_t);
 mcl_status launch_debug_indices(const mcl_map_s *, const float *, int, const float *, int, int64_t *, hipStream_t);
 mcl_status launch_normalize(const float *, int, double *, uint64_t *, double *, hipStream_t);
 mcl_status launch_resample(const uint64_t *, int, uint64_t, int32_t *, const float *, float *, hipStream_t);
@@ -73,19 +75,36 @@ using namespace mcl;
 
 extern "C" const char *mcl_last_error(void) { return g_last_error.c_str(); }
 
+static mcl_status sensor_args(const char *what, mcl_map map, const float *points, int32_t K, const float *poses,
+                              int32_t N, float sigma, float *logw, float *c) {
+    const std::string w(what);
+    if (!map) return fail(MCL_EINVAL, w + ": NULL map");
+    if (!poses || !logw) return fail(MCL_EINVAL, w + ": NULL poses or logw");
+    if (K < 0 || N < 1) return fail(MCL_EINVAL, w + ": need K >= 0 and N >= 1");
+    if (K > MCL_MAX_POINTS || N > MCL_MAX_PARTICLES) return fail(MCL_ERANGE, w + ": K or N above the limit");
+    if (K > 0 && !points) return fail(MCL_EINVAL, w + ": NULL points with K > 0");
+    if (!(std::isfinite(sigma) && sigma > 0.0f)) return fail(MCL_EINVAL, w + ": sigma must be finite and > 0");
+    if (overlaps(logw, (size_t)N * 4, poses, (size_t)12 * N * 4) || overlaps(logw, (size_t)N * 4, points, (size_t)3 * K * 4))
+        return fail(MCL_EINVAL, w + ": logw overlaps an input");
+    const double s = map->scale, sg = (double)sigma;
+    *c = (float)((s * s) / (2.0 * sg * sg));
+    return MCL_OK;
+}
+
 extern "C" mcl_status mcl_sensor_update(mcl_map map, const float *points, int32_t K, const float *poses, int32_t N,
                                         float sigma, float *logw, void *stream) {
-    if (!map) return fail(MCL_EINVAL, "sensor_update: NULL map");
-    if (!poses || !logw) return fail(MCL_EINVAL, "sensor_update: NULL poses or logw");
-    if (K < 0 || N < 1) return fail(MCL_EINVAL, "sensor_update: need K >= 0 and N >= 1");
-    if (K > MCL_MAX_POINTS || N > MCL_MAX_PARTICLES) return fail(MCL_ERANGE, "sensor_update: K or N above the limit");
-    if (K > 0 && !points) return fail(MCL_EINVAL, "sensor_update: NULL points with K > 0");
-    if (!(std::isfinite(sigma) && sigma > 0.0f)) return fail(MCL_EINVAL, "sensor_update: sigma must be finite and > 0");
-    if (overlaps(logw, (size_t)N * 4, poses, (size_t)12 * N * 4) || overlaps(logw, (size_t)N * 4, points, (size_t)3 * K * 4))
-        return fail(MCL_EINVAL, "sensor_update: logw overlaps an input");
-    const double s = map->scale, sg = (double)sigma;
-    const float c = (float)((s * s) / (2.0 * sg * sg));
+    float c = 0.0f;
+    mcl_status st = sensor_args("sensor_update", map, points, K, poses, N, sigma, logw, &c);
+    if (st != MCL_OK) return st;
     return launch_sensor(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mcl_status mcl_sensor_update_trilinear(mcl_map map, const float *points, int32_t K, const float *poses,
+                                                  int32_t N, float sigma, float *logw, void *stream) {
+    float c = 0.0f;
+    mcl_status st = sensor_args("sensor_update_trilinear", map, points, K, poses, N, sigma, logw, &c);
+    if (st != MCL_OK) return st;
+    return launch_sensor_trilinear(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream));
 }
 
 extern "C" mcl_status mcl_normalize(const float *logw, int32_t N, double *w, uint64_t *wq, double *log_z,

@@ -1,9 +1,11 @@
 // TSDF map upload: dense x-fastest host array -> device brick layout + sentinels.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "mcl_internal.h"
+#include "voxel.h"
 
 namespace mcl {
 
@@ -54,6 +56,121 @@ static void fill_sentinels(char *host, T outside, int es) {
         reinterpret_cast<T *>(host)[w] = outside;          // +Q sentinel brick at out_off
         reinterpret_cast<T *>(host + 64 * es)[w] = T(0);  // zero sentinel brick at zero_off
     }
+}
+
+// Cell e of the corner-cell layout (see TriView): cell (i, j, k) of the cell
+// grid holds map voxels (i - 1 + a, j - 1 + b, k - 1 + c), a, b, c in {0, 1},
+// as value a + 2 b + 4 c, read from the main brick layout, or +Q outside.
+template <typename T>
+__global__ __launch_bounds__(256) void tri_build_kernel(MapView src, T *__restrict__ dst, int nbx, int nbz,
+                                                        int64_t ncells, T outside) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ncells) return;
+    int64_t bi = e >> 6;
+    int w = (int)(e & 63);
+    int bz = (int)(bi % nbz);
+    int64_t r = bi / nbz;
+    int bx = (int)(r % nbx);
+    int by = (int)(r / nbx);
+    int ix = bx * 4 + (w & 3) - 1, iy = by * 4 + ((w >> 2) & 3) - 1, iz = bz * 4 + (w >> 4) - 1;
+    for (int c = 0; c < 8; ++c) {
+        int x = ix + (c & 1), y = iy + ((c >> 1) & 1), z = iz + (c >> 2);
+        T v = outside;
+        if (x >= 0 && y >= 0 && z >= 0 && x < src.nx && y < src.ny && z < src.nz)
+            v = *reinterpret_cast<const T *>(src.base + brick_offset<sizeof(T)>(src, (uint32_t)x, (uint32_t)y, (uint32_t)z));
+        dst[e * 8 + c] = v;
+    }
+}
+
+// Class byte of every brick of cells: kCellPos if all 8 corners of all its 64
+// cells are +Q, kCellNeg if all are -Q, else kCellMixed.
+template <typename T>
+__global__ __launch_bounds__(256) void tri_class_kernel(const T *__restrict__ cells, uint8_t *__restrict__ cls,
+                                                        int64_t nbricks, T qpos, T qneg) {
+    int64_t bi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= nbricks) return;
+    const T *b = cells + bi * 64 * 8;
+    bool pos = true, neg = true;
+    for (int w = 0; w < 64 * 8; ++w) {
+        pos &= b[w] == qpos;
+        neg &= b[w] == qneg;
+    }
+    cls[bi] = pos ? kCellPos : neg ? kCellNeg : kCellMixed;
+}
+
+static std::mutex g_tri_mu;
+
+mcl_status ensure_trilinear(mcl_map_s *m, hipStream_t stream) {
+    std::lock_guard<std::mutex> lk(g_tri_mu);
+    if (m->tri_dev) return MCL_OK;
+    const MapView &v = m->view;
+    const int es = 8 * elem_size(m->dtype);  // bytes per cell
+    const int px = v.nx + 2, py = v.ny + 2, pz = v.nz + 2;
+    const int nbx = (px + 3) / 4, nby = (py + 3) / 4, nbz = (pz + 3) / 4;
+    const int64_t nvals = (int64_t)nbx * nby * nbz * kBrickVals;  // cells
+    const int64_t data_bytes = nvals * es;
+    const int64_t nbricks = nvals / kBrickVals;
+    const int64_t cls_off = (data_bytes + 2 * es + 255) / 256 * 256;  // two sentinel cells, then the classes
+    const int64_t bytes = cls_off + (nbricks + 255) / 256 * 256;
+    const int64_t cy = (int64_t)es * (16 * (int64_t)nbz * nbx - 4);
+    if (bytes >= ((int64_t)1 << 32) || cy >= ((int64_t)1 << 24))
+        return fail(MCL_ERANGE, "trilinear: the corner-cell map exceeds the brick addressing limits");
+    void *dev = nullptr;
+    if (hipMalloc(&dev, (size_t)bytes) != hipSuccess) return fail(MCL_ENOMEM, "trilinear: device allocation failed");
+    char *base = static_cast<char *>(dev);
+    uint8_t *cls = reinterpret_cast<uint8_t *>(base + cls_off);
+    char sent[64];
+    for (int c = 0; c < 8; ++c) {
+        if (m->dtype == MCL_TSDF_I16) {
+            reinterpret_cast<int16_t *>(sent)[c] = 32767;
+            reinterpret_cast<int16_t *>(sent + es)[c] = -32767;
+        } else if (m->dtype == MCL_TSDF_I8) {
+            reinterpret_cast<int8_t *>(sent)[c] = 127;
+            reinterpret_cast<int8_t *>(sent + es)[c] = -127;
+        } else {
+            reinterpret_cast<float *>(sent)[c] = m->tau;
+            reinterpret_cast<float *>(sent + es)[c] = -m->tau;
+        }
+    }
+    mcl_status st = MCL_OK;
+    if (hipMemcpyAsync(base + data_bytes, sent, (size_t)(2 * es), hipMemcpyHostToDevice, stream) != hipSuccess)
+        st = fail(MCL_EDEVICE, "trilinear: sentinel copy failed");
+    const unsigned blocks = (unsigned)((nvals + 255) / 256);
+    const unsigned cblocks = (unsigned)((nbricks + 255) / 256);
+    if (st == MCL_OK) {
+        if (m->dtype == MCL_TSDF_I16) {
+            tri_build_kernel<int16_t><<<blocks, 256, 0, stream>>>(v, (int16_t *)dev, nbx, nbz, nvals, (int16_t)32767);
+            tri_class_kernel<int16_t><<<cblocks, 256, 0, stream>>>((const int16_t *)dev, cls, nbricks, (int16_t)32767,
+                                                                   (int16_t)-32767);
+        } else if (m->dtype == MCL_TSDF_I8) {
+            tri_build_kernel<int8_t><<<blocks, 256, 0, stream>>>(v, (int8_t *)dev, nbx, nbz, nvals, (int8_t)127);
+            tri_class_kernel<int8_t><<<cblocks, 256, 0, stream>>>((const int8_t *)dev, cls, nbricks, (int8_t)127,
+                                                                  (int8_t)-127);
+        } else {
+            tri_build_kernel<float><<<blocks, 256, 0, stream>>>(v, (float *)dev, nbx, nbz, nvals, m->tau);
+            tri_class_kernel<float><<<cblocks, 256, 0, stream>>>((const float *)dev, cls, nbricks, m->tau, -m->tau);
+        }
+        st = check_launch("tri_build_kernel / tri_class_kernel");
+    }
+    if (st == MCL_OK && hipStreamSynchronize(stream) != hipSuccess)
+        st = fail(MCL_EDEVICE, "trilinear: synchronisation failed");
+    if (st != MCL_OK) {
+        (void)hipFree(dev);
+        return st;
+    }
+    TriView t{};
+    t.base = static_cast<const char *>(dev);
+    t.cx = (uint32_t)(es * (16 * nbz - 1));
+    t.cy = (uint32_t)cy;
+    t.hx = (float)v.nx;
+    t.hy = (float)v.ny;
+    t.hz = (float)v.nz;
+    t.pos_off = (uint32_t)data_bytes;
+    t.cls = cls;
+    m->tri = t;
+    m->tri_bytes = (size_t)bytes;
+    m->tri_dev = dev;
+    return MCL_OK;
 }
 
 }  // namespace mcl
@@ -170,6 +287,7 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
 extern "C" mcl_status mcl_map_free(mcl_map map) {
     if (!map) return fail(MCL_EINVAL, "map_free: NULL map");
     hipError_t e = hipFree(map->dev);
+    if (map->tri_dev && hipFree(map->tri_dev) != hipSuccess) e = hipErrorInvalidValue;
     delete map;
     return e == hipSuccess ? MCL_OK : fail(MCL_EDEVICE, "map_free: hipFree failed");
 }

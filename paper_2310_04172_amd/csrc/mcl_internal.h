@@ -43,6 +43,25 @@ struct MapView {
     const uint8_t *cls;      // device: class byte per brick, indexed by byte offset >> (6 + log2 esize)
 };
 
+// The map for the trilinear lookup, one gather per point: cell (i, j, k) holds
+// the 8 voxel values at its corners (i..i+1, j..j+1, k..k+1), x fastest, so an
+// interpolation reads one 16-byte run (int16; 8 bytes int8, 32 bytes float32).
+// Cells span i in [-1, n] per axis (corners outside the map hold +Q) and are
+// stored at index i + 1 in the same brick order as the values, 64 cells per
+// brick.  Eight times the map's memory (HBM is plentiful, gathers are not).
+// As for the values, a class byte per brick of cells says whether every corner
+// of its 64 cells is +Q (class 1) or every one is -Q (class 3); such points
+// read one of two sentinel cells (all +Q, all -Q) after the data instead of
+// their own.  Built on first use of the trilinear lookup.
+struct TriView {
+    const char *base;        // device: bricked corner cells
+    uint32_t cx, cy;         // brick address coefficients of the cell grid (bytes)
+    float hx, hy, hz;        // (float)n per axis: upper clamp of h
+    uint32_t pos_off;        // byte offset of the all +Q sentinel cell (the -Q one follows)
+    const uint8_t *cls;      // class byte per brick of cells, indexed by byte offset >> (6 + log2 cell bytes)
+};
+constexpr uint8_t kCellMixed = 0, kCellPos = 1, kCellNeg = 3;
+
 }  // namespace mcl
 
 struct mcl_map_s {
@@ -55,7 +74,16 @@ struct mcl_map_s {
     float tau;
     float voxel;
     double scale;       // metres per stored unit: tau / Q, or 1 for float32
+    void *tri_dev;      // corner cells for the trilinear lookup, or null
+    size_t tri_bytes;
+    mcl::TriView tri;
 };
+
+namespace mcl {
+// Builds map->tri on first use (allocation + one kernel, then a synchronisation
+// of `stream`); later calls return at once.
+mcl_status ensure_trilinear(mcl_map_s *map, hipStream_t stream);
+}  // namespace mcl
 
 namespace mcl {
 

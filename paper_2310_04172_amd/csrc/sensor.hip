@@ -111,22 +111,141 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum(const MapV
     return s;
 }
 
+// Trilinear lookup (§III: a pseudo-continuous map value by interpolation): one
+// gather of the point's corner cell (the 8 voxel values around it; corners
+// outside the map hold +Q; cells of uniform +Q / -Q bricks read a shared
+// sentinel cell after a class-byte lookup), interpolated along x, then y, then z by
+// lerp(a, b, t) = fma(t, b - a, a) in float32.  A point clamped to h = -1 has
+// weight 0 on its inside corner and a point clamped to h = n reads two +Q
+// corners, so both give exactly Q.  Padding slots contribute 0.  Points go in
+// batches of kTriU, whose gathers are all in flight together.
+constexpr int kTriU = 8;
+
+__device__ inline float lerp(float a, float b, float t) { return __builtin_fmaf(t, b - a, a); }
+
+template <typename T>
+struct CellRaw;
+template <>
+struct CellRaw<int16_t> {
+    uint4 q;
+};
+template <>
+struct CellRaw<int8_t> {
+    uint2 q;
+};
+template <>
+struct CellRaw<float> {
+    float4 a, b;
+};
+
+template <typename T>
+__device__ inline CellRaw<T> load_cell(const char *base, uint32_t off) {
+    CellRaw<T> r;
+    if constexpr (sizeof(T) == 2) {
+        r.q = *reinterpret_cast<const uint4 *>(base + off);
+    } else if constexpr (sizeof(T) == 1) {
+        r.q = *reinterpret_cast<const uint2 *>(base + off);
+    } else {
+        r.a = *reinterpret_cast<const float4 *>(base + off);
+        r.b = *reinterpret_cast<const float4 *>(base + off + 16);
+    }
+    return r;
+}
+
+// The 8 corner values as floats, corner a + 2 b + 4 c (sign-extended fields).
+template <typename T>
+__device__ inline void unpack_cell(const CellRaw<T> &r, float (&d)[8]) {
+    if constexpr (sizeof(T) == 2) {
+        const uint32_t w[4] = {r.q.x, r.q.y, r.q.z, r.q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            d[2 * i] = (float)((int32_t)(w[i] << 16) >> 16);
+            d[2 * i + 1] = (float)((int32_t)w[i] >> 16);
+        }
+    } else if constexpr (sizeof(T) == 1) {
+        const uint32_t w[2] = {r.q.x, r.q.y};
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[4 * i + k] = (float)((int32_t)(w[i] << (24 - 8 * k)) >> 24);
+    } else {
+        d[0] = r.a.x, d[1] = r.a.y, d[2] = r.a.z, d[3] = r.a.w;
+        d[4] = r.b.x, d[5] = r.b.y, d[6] = r.b.z, d[7] = r.b.w;
+    }
+}
+
 template <typename T, bool TAIL>
-__device__ __attribute__((always_inline)) inline void chunk_group(const MapView &m, const float (&pa)[12], const float (&px)[kU],
+__device__ __attribute__((always_inline)) inline float lane_chunk_sum_tri(const TriView &tv, const float (&A)[12],
+                                                                          const float (&px)[kU], const float (&py)[kU],
+                                                                          const float (&pz)[kU], int lane, int nvalid) {
+    constexpr int E = 8 * sizeof(T);  // bytes per cell
+    constexpr int kShift = 6 + (E == 8 ? 3 : E == 16 ? 4 : 5);
+    float s = 0.0f;
+#pragma unroll
+    for (int u0 = 0; u0 < kU; u0 += kTriU) {
+        CellRaw<T> raw[kTriU];
+        uint32_t off[kTriU];
+        float fx[kTriU], fy[kTriU], fz[kTriU];
+#pragma unroll
+        for (int v = 0; v < kTriU; ++v) {
+            const int u = u0 + v;
+            const float gx = grid_coord(A[0], A[1], A[2], A[9], px[u], py[u], pz[u]);
+            const float gy = grid_coord(A[3], A[4], A[5], A[10], px[u], py[u], pz[u]);
+            const float gz = grid_coord(A[6], A[7], A[8], A[11], px[u], py[u], pz[u]);
+            const uint32_t ix = tri_axis(gx, tv.hx, fx[v]);
+            const uint32_t iy = tri_axis(gy, tv.hy, fy[v]);
+            const uint32_t iz = tri_axis(gz, tv.hz, fz[v]);
+            off[v] = brick_x<E>(tv.cx, ix) + brick_y<E>(tv.cy, iy) + brick_z<E>(iz);
+        }
+        uint32_t cls[kTriU];
+#pragma unroll
+        for (int v = 0; v < kTriU; ++v) cls[v] = tv.cls[off[v] >> kShift];
+        __builtin_amdgcn_sched_barrier(0);
+        // cells of uniform bricks read the shared sentinel cell of their sign
+        // (class 1: +Q at pos_off, class 3: -Q right after it)
+#pragma unroll
+        for (int v = 0; v < kTriU; ++v)
+            raw[v] = load_cell<T>(tv.base, cls[v] == kCellMixed ? off[v] : tv.pos_off + ((cls[v] >> 1) & 1u) * E);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < kTriU; ++v) {
+            float d[8];
+            unpack_cell<T>(raw[v], d);
+            const float c00 = lerp(d[0], d[1], fx[v]), c10 = lerp(d[2], d[3], fx[v]);
+            const float c01 = lerp(d[4], d[5], fx[v]), c11 = lerp(d[6], d[7], fx[v]);
+            const float c0 = lerp(c00, c10, fy[v]), c1 = lerp(c01, c11, fy[v]);
+            float mv = lerp(c0, c1, fz[v]);
+            if (TAIL) mv = (u0 + v) * kWave + lane < nvalid ? mv : 0.0f;
+            s = __builtin_fmaf(mv, mv, s);
+        }
+        // Keep batches apart so that only one batch's cells are live: the
+        // empty statement takes s as an operand, so this batch's arithmetic must
+        // be done here, not sunk below the next batch's gathers.
+        asm volatile("" : "+v"(s));
+    }
+    return s;
+}
+
+template <typename T, bool TAIL, bool TRI>
+__device__ __attribute__((always_inline)) inline void chunk_group(const MapView &m, const TriView &tv, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
                                    int gcount, float &acc) {
     for (int p = 0; p < gcount; ++p) {
         float A[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) A[j] = bcast(pa[j], p);
-        float t = wave_sum(lane_chunk_sum<T, TAIL>(m, A, px, py, pz, lane, nvalid));
+        float t;
+        if constexpr (TRI)
+            t = wave_sum(lane_chunk_sum_tri<T, TAIL>(tv, A, px, py, pz, lane, nvalid));
+        else
+            t = wave_sum(lane_chunk_sum<T, TAIL>(m, A, px, py, pz, lane, nvalid));
         if (lane == p) acc += t;
     }
 }
 
 // One work item: particles [64 g, 64 g + 64) of a job against points
 // [4096 piece, 4096 piece + 4096).  Returns lane p's sum for particle 64 g + p.
-template <typename T>
+template <typename T, bool TRI>
 __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJob &J, int local, int lane) {
     const int group = local / J.npiece;
     const int piece = local - group * J.npiece;
@@ -152,9 +271,9 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
             pz[u] = J.pts[(size_t)2 * K + k];
         }
         if (nvalid == kChunk)
-            chunk_group<T, false>(m, pa, px, py, pz, lane, nvalid, gcount, acc);
+            chunk_group<T, false, TRI>(m, J.tri, pa, px, py, pz, lane, nvalid, gcount, acc);
         else
-            chunk_group<T, true>(m, pa, px, py, pz, lane, nvalid, gcount, acc);
+            chunk_group<T, true, TRI>(m, J.tri, pa, px, py, pz, lane, nvalid, gcount, acc);
     }
     return acc;
 }
@@ -177,8 +296,8 @@ __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJ
 // wave for a full grid, several for a persistent one).  The job descriptor is
 // read into scalar registers per item and read again for the store, so it need
 // not stay live across the item.
-template <typename T, int WPB, typename Src>
-__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4))) void sensor_kernel(Src src) {
+template <typename T, int WPB, typename Src, bool TRI = false>
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(TRI ? 2 : 4))) void sensor_kernel(Src src) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nitems = src.items();
     const int64_t stride = (int64_t)gridDim.x * WPB;
@@ -190,7 +309,7 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         {
             const SensorJob J = src.load(j);
             local = (int)(item - J.item0);
-            acc = sensor_item<T>(J, local, lane);
+            acc = sensor_item<T, TRI>(J, local, lane);
         }
         const SensorJob J = src.load(j);
         sensor_store(J, local, lane, acc);
@@ -320,6 +439,38 @@ mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, cons
     const int64_t nitems = (int64_t)src.job.ngroups * npiece;
     src.n = Counts{1, nitems, N, 0};
     return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream);
+}
+
+// Trilinear lookup: the same decomposition and summation order, one wave per
+// work item, four waves per workgroup.
+mcl_status launch_sensor_trilinear(mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
+                                   float *logw, hipStream_t stream) {
+    mcl_status est = ensure_trilinear(map, stream);
+    if (est != MCL_OK) return est;
+    if (K == 0) {
+        fill_kernel<<<(N + 255) / 256, 256, 0, stream>>>(logw, N, -(0.0f * c));
+        return check_launch("fill_kernel");
+    }
+    const int npiece = sensor_pieces(K);
+    float *part = nullptr;
+    if (npiece > 1) {
+        part = static_cast<float *>(workspace(stream, (size_t)npiece * N * sizeof(float)));
+        if (!part) return fail(MCL_ENOMEM, "sensor_update_trilinear: workspace allocation failed");
+    }
+    using Src = OneJob<SensorJob>;
+    Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
+    src.job.tri = map->tri;
+    const int64_t nitems = (int64_t)src.job.ngroups * npiece;
+    src.n = Counts{1, nitems, N, 0};
+    const unsigned blocks = (unsigned)((nitems + 3) / 4);
+    if (map->dtype == MCL_TSDF_I16) sensor_kernel<int16_t, 4, Src, true><<<blocks, 256, 0, stream>>>(src);
+    else if (map->dtype == MCL_TSDF_I8) sensor_kernel<int8_t, 4, Src, true><<<blocks, 256, 0, stream>>>(src);
+    else sensor_kernel<float, 4, Src, true><<<blocks, 256, 0, stream>>>(src);
+    mcl_status st = check_launch("sensor_kernel (trilinear)");
+    if (st != MCL_OK || npiece == 1) return st;
+    int64_t cb = std::min<int64_t>((N + 255) / 256, (int64_t)device_cus() * 16);
+    combine_kernel<<<(unsigned)std::max<int64_t>(cb, 1), 256, 0, stream>>>(src);
+    return check_launch("combine_kernel");
 }
 
 mcl_status launch_sensor(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,

@@ -70,4 +70,27 @@ __device__ inline uint32_t voxel_offset(const MapView &m, float gx, float gy, fl
     return ok ? off : m.out_off;
 }
 
+// Trilinear lookup, one axis: the stored values sit at the voxel centres (grid
+// coordinate i + 1/2), so the interpolation coordinate is h = g - 1/2, clamped
+// to [-1, n] (this only moves points whose two centres are both outside, and
+// sends NaN there: such points read +Q exactly, see the kernel); the lower
+// centre is i = floor(h), the weight of the upper one f = h - floor(h) (exact).
+// Returns i + 1, the index of the cell with lower corner i in the cell grid.
+__device__ inline uint32_t tri_axis(float g, float hmax, float &f) {
+    float h = g - 0.5f;
+    h = fminf(fmaxf(h, -1.0f), hmax);
+    const float fl = floorf(h);
+    f = h - fl;
+    return (uint32_t)((int32_t)fl + 1);
+}
+
+// Byte offset of element (i, j, k) of a bricked grid with ESIZE bytes per
+// element is X(i) + Y(j) + Z(k) (brick_offset, separated per axis).
+template <int ESIZE>
+__device__ inline uint32_t brick_x(uint32_t cx, uint32_t ix) { return __umul24(ix & ~3u, cx) + ix * ESIZE; }
+template <int ESIZE>
+__device__ inline uint32_t brick_y(uint32_t cy, uint32_t iy) { return __umul24(iy & ~3u, cy) + (iy << 2) * ESIZE; }
+template <int ESIZE>
+__device__ inline uint32_t brick_z(uint32_t iz) { return (iz << 4) * ESIZE; }
+
 }  // namespace mcl

@@ -50,6 +50,7 @@ class LaunchConfig(C.Structure):
 _lib.mcl_map_upload.argtypes = [C.POINTER(MapDesc), _P, _P, C.POINTER(_P)]
 _lib.mcl_map_free.argtypes = [_P]
 _lib.mcl_sensor_update.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
+_lib.mcl_sensor_update_trilinear.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
 _lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, _P, _P, _P, _P]
 _lib.mcl_debug_voxel_indices.argtypes = [_P, _P, _I, _P, _I, _P, _P]
@@ -60,7 +61,8 @@ _lib.mcl_job_bytes.restype = C.c_size_t
 _lib.mcl_autotune.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P, C.POINTER(LaunchConfig)]
 _lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_last_error.restype = C.c_char_p
-for _f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
+for _f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear", "mcl_normalize",
+           "mcl_resample",
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_pose_estimate"):
     getattr(_lib, _f).restype = C.c_int32
 
@@ -154,6 +156,22 @@ def sensor_update(m: Map, points, poses, sigma: float, logw=None, stream=None):
     _dev(logw, torch.float32, (N,), "logw")
     _check(_lib.mcl_sensor_update(m.handle, _ptr(points) if K else None, K, _ptr(poses), N,
                                   float(sigma), _ptr(logw), _stream(stream)), "mcl_sensor_update")
+    return logw
+
+
+def sensor_update_trilinear(m: Map, points, poses, sigma: float, logw=None, stream=None):
+    """logw [N] float32 with the trilinear lookup (see include/mcl.h)."""
+    import torch
+    K = points.shape[1] if points is not None else 0
+    N = poses.shape[1]
+    _dev(poses, torch.float32, (12, N), "poses")
+    if K:
+        _dev(points, torch.float32, (3, K), "points")
+    if logw is None:
+        logw = torch.empty(N, dtype=torch.float32, device=poses.device)
+    _dev(logw, torch.float32, (N,), "logw")
+    _check(_lib.mcl_sensor_update_trilinear(m.handle, _ptr(points) if K else None, K, _ptr(poses), N,
+                                            float(sigma), _ptr(logw), _stream(stream)), "mcl_sensor_update_trilinear")
     return logw
 
 

@@ -27,7 +27,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
               "mcl_debug_voxel_indices", "mcl_last_error", "mcl_tick", "mcl_job_bytes", "mcl_autotune",
-              "mcl_set_launch_config", "mcl_pose_estimate"):
+              "mcl_set_launch_config", "mcl_pose_estimate", "mcl_sensor_update_trilinear"):
         assert f in names
 
 
@@ -44,6 +44,8 @@ def test_argument_errors_are_reported_on_the_host(mcl):
     # NULL map / pointers, bad sizes, bad sigma: rejected before any device work
     assert lib.mcl_sensor_update(None, fake, 10, fake, 10, 0.1, P(0x2000), None) == mcl.MCL_EINVAL
     assert b"NULL map" in lib.mcl_last_error()
+    assert lib.mcl_sensor_update_trilinear(None, fake, 10, fake, 10, 0.1, P(0x2000), None) == mcl.MCL_EINVAL
+    assert lib.mcl_sensor_update_trilinear(fake, fake, 10, fake, 10, float("nan"), P(0x2000), None) == mcl.MCL_EINVAL
     assert lib.mcl_normalize(None, 10, None, fake, None, None) == mcl.MCL_EINVAL
     assert lib.mcl_normalize(fake, 0, None, P(0x9000), None, None) == mcl.MCL_EINVAL
     assert lib.mcl_normalize(fake, mcl.MAX_PARTICLES + 1, None, P(0x90000000), None, None) == mcl.MCL_ERANGE
