@@ -12,7 +12,9 @@ Prints one JSON line.  `value` is particle-point evaluations per second
 update) measured with HIP events on its stream; `cpu_baseline` times the CPU
 oracle on a bounded particle sample of the same workload.
 
-Other workloads (not the default line): --workload trilinear (the default workload with
+Other workloads (not the default line): --workload loop (the whole MCL loop on the
+device: uniform initialisation, then motion, sensor, normalise, estimate, resample per
+iteration, with per-stage times), --workload trilinear (the default workload with
 the trilinear map lookup), --workload estimate (the pose estimate alone,
 2^14 to 2^21 particles), --workload small (1,000 particles in a
 small office map), --workload batched (64 filters: sequential single-filter
@@ -264,6 +266,79 @@ def run_estimate(args):
     return out
 
 
+def run_loop(args):
+    """The whole MCL loop on the device for the global-localisation workload:
+    particles initialised uniformly in free space once, then per iteration
+    motion update (a static robot: identity odometry with noise), sensor update,
+    normalisation, pose estimate and resampling, each stage timed with HIP
+    events; the estimate's error against the true pose is reported after the
+    last iteration."""
+    import torch
+    from paper_2310_04172_amd import mcl
+    from workloads import configs
+
+    w = configs.config2()
+    dev = torch.device("cuda:0")
+    m = mcl.Map.from_tsdf(w.tmap)
+    pts = torch.from_numpy(w.points).to(dev)
+    N, K = w.N, w.K
+    stream = torch.cuda.current_stream()
+    poses = torch.empty((12, N), dtype=torch.float32, device=dev)
+    spare = torch.empty_like(poses)
+    logw = torch.empty(N, dtype=torch.float32, device=dev)
+    wt = torch.empty(N, dtype=torch.float64, device=dev)
+    wq = torch.empty(N, dtype=torch.uint64, device=dev)
+    idx = torch.empty(N, dtype=torch.int32, device=dev)
+    mean = torch.empty(12, dtype=torch.float64, device=dev)
+    bi = torch.empty(1, dtype=torch.int32, device=dev)
+    bp = torch.empty(12, dtype=torch.float32, device=dev)
+    tilt = 5.0 * np.pi / 180.0
+    mcl.init_uniform(m, N, tilt, 1, poses, stream=stream)   # builds the free-voxel index once
+    torch.cuda.synchronize()
+    ev = {k: [] for k in ("init", "motion", "sensor", "normalize", "estimate", "resample")}
+
+    def timed(name, fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        ev[name].append((a, b))
+
+    timed("init", lambda: mcl.init_uniform(m, N, tilt, 2, poses, stream=stream))
+    identity = np.r_[np.eye(3).ravel(), 0.0, 0.0, 0.0]
+    total = args.warmup + args.steps
+    for it in range(total):
+        timed("motion", lambda: mcl.motion_update(poses, identity, 0.02, 0.01, 3, it, poses_out=poses, stream=stream))
+        timed("sensor", lambda: mcl.sensor_update(m, pts, poses, w.sigma, logw, stream))
+        timed("normalize", lambda: mcl.normalize(logw, wt, wq, None, want_w=True, stream=stream))
+        timed("estimate", lambda: mcl.pose_estimate(wt, poses, mean, bi, bp, stream))
+        timed("resample", lambda: mcl.resample(wq, int(it) * 0x9E3779B97F4A7C15, poses, spare, idx, stream))
+        poses, spare = spare, poses
+    torch.cuda.synchronize()
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v[-args.steps:] if True])) for k, v in ev.items()}
+    ms["init"] = ev["init"][0][0].elapsed_time(ev["init"][0][1])
+    step_ms = sum(ms[k] for k in ("motion", "sensor", "normalize", "estimate", "resample"))
+    gxyz, grpy = w.gt
+    est = mean.cpu().numpy()
+    R_est = est[:9].reshape(3, 3)
+    R_gt, t_gt = configs.pose_matrix(gxyz, grpy)
+    pos_err = float(np.linalg.norm(est[9:] - np.asarray(t_gt)))
+    c = (np.trace(R_gt.T @ R_est) - 1.0) / 2.0
+    rot_err = float(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))
+    best = bp.cpu().numpy().astype(np.float64)
+    best_err = float(np.linalg.norm(best[9:] - np.asarray(t_gt)))
+    log(f"stages (ms): {json.dumps(ms)}; estimate error {pos_err:.3f} m / {rot_err:.2f} deg, "
+        f"best particle {best_err:.3f} m after {total} iterations")
+    out = base_record(args, METRIC + " [full MCL loop on the device]", N * K / (step_ms * 1e-3) / 1e9, step_ms,
+                      {"workload": w.name + ", full loop: init once, then motion + sensor + normalise + estimate "
+                                   "+ resample", "N": N, "K": K, "iterations": total,
+                       "stage_ms": ms,
+                       "motion_GB_per_s": 96.0 * N / (ms["motion"] * 1e-3) / 1e9,
+                       "estimate_error_m": pos_err, "estimate_error_deg": rot_err,
+                       "best_particle_error_m": best_err})
+    return out
+
+
 def run_batched(args):
     """64 filters on one map: sequential plain calls vs one tick (eager, and graph-replayed)."""
     import torch
@@ -436,7 +511,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision", "estimate", "trilinear"])
+    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision", "estimate", "trilinear", "loop"])
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -463,6 +538,8 @@ def main():
         out = run_precision(args)
     elif args.workload == "estimate":
         out = run_estimate(args)
+    elif args.workload == "loop":
+        out = run_loop(args)
     else:
         t0 = time.perf_counter()
         w = configs.config1() if args.workload == "small" else configs.config2()

@@ -167,6 +167,46 @@ mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t u, int32_t *idx,
 mcl_status mcl_pose_estimate(const double *w, const float *poses, int32_t N, double *mean,
                              int32_t *best_idx, float *best_pose, void *stream);
 
+/* ---------------------------------------------------- motion and initialisation
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011), counter (n, lo32(step),
+ * hi32(step), c), key (lo32(seed), hi32(seed)): particle n's draws depend only on
+ * (seed, step, n), never on the launch.  Uniforms from a 32-bit word x:
+ * ((x >> 8) + 1) 2^-24 in (0, 1] and (x >> 8) 2^-24 in [0, 1). */
+
+/* Motion update (§III: every iteration first moves each particle by the motion
+ * model; §VI: odometry from dead reckoning or an IMU, with noise on velocity
+ * and angular velocity).  The paper gives no formula; here the odometry
+ * increment is a rigid motion (dR, dt) in the robot frame and each particle
+ * moves by its own noisy copy:
+ *     n0..n5 = six standard normals (Box-Muller on Philox words 0..5 of
+ *              counters (n, step, 0) and (n, step, 1)),
+ *     dt' = dt + sigma_t (n0, n1, n2),   dR' = dR Exp(sigma_r (n3, n4, n5)),
+ *     R <- R dR',   t <- R dt' + t        (float32).
+ *   poses_in:  device [12][N] float32; poses_out: device [12][N], may equal
+ *              poses_in (in place) but must not overlap it otherwise.
+ *   delta:     HOST [12] float32, the increment (dR row-major, dt), finite.
+ *   sigma_t, sigma_r: standard deviations of the increment's translation (m)
+ *              and rotation (rad) noise, >= 0 (velocity noise times the step).
+ *   seed, step: select the random numbers (use a new step every update). */
+mcl_status mcl_motion_update(const float *poses_in, float *poses_out, int32_t N, const float *delta,
+                             float sigma_t, float sigma_r, uint64_t seed, uint64_t step, void *stream);
+
+/* Uniform initialisation in free space (§III: without an initial pose estimate
+ * the particles are distributed uniformly in free space).  Free voxels are
+ * those with a stored value > 0, counted in x-fastest order; with F of them,
+ * particle n takes the free voxel of rank floor(U F / 2^64), U = w0 + 2^32 w1
+ * from counter (n, 0, 0, 2), a position uniform inside it,
+ *     p_j = origin_j + ((float) i_j + u) * voxel   (float32, each step rounded),
+ * u from w2, w3, w4 in [0, 1), and the orientation Rz(yaw) Ry(pitch) Rx(roll)
+ * with yaw = pi (2 u5 - 1) and pitch, roll = max_tilt (2 u - 1) from w6, w7
+ * (counter (n, 0, 0, 3)).  The first call on a map counts its free voxels
+ * (one kernel and a host prefix sum; synchronises `stream`).
+ *   poses:    device output [12][N] float32.
+ *   max_tilt: largest |roll| and |pitch| in radians, >= 0.
+ * Returns MCL_EINVAL if the map has no free voxel. */
+mcl_status mcl_init_uniform(mcl_map map, float *poses, int32_t N, float max_tilt, uint64_t seed,
+                            void *stream);
+
 /* ------------------------------------------------------------- batching
  * One MCL update of many filters at once (the filters may use different maps,
  * particle counts and scan sizes).  mcl_tick runs, for every filter, exactly
@@ -239,6 +279,12 @@ mcl_status mcl_set_launch_config(int32_t dtype, int32_t K, int32_t N, const mcl_
 mcl_status mcl_debug_voxel_indices(mcl_map map, const float *points, int32_t K,
                                    const float *poses, int32_t N, int64_t *lin_idx,
                                    void *stream);
+
+/* Test support: Philox4x32-10 of one counter and key on the device, by the same
+ * device code as the motion update and the initialisation.  counter_key: HOST
+ * [6] (counter words 0..3, key words 0..1); out: HOST [4].  Synchronous, on the
+ * default stream. */
+mcl_status mcl_debug_philox(const uint32_t *counter_key, uint32_t *out);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *mcl_last_error(void);

@@ -3,8 +3,9 @@
 Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product path never routes through it.
 
-Thin ctypes wrapper over ``mcl_oracle.c`` (the definitions and readings are in
-that file's header comment) plus its build step.
+Thin ctypes wrapper over ``mcl_oracle.c`` and ``mcl_oracle_motion.c`` (the
+definitions and readings are in their header comments) plus their build step;
+``estimate.py`` holds the pose-estimate oracle.
 """
 
 from __future__ import annotations
@@ -16,7 +17,7 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "mcl_oracle.c")
+SRCS = [os.path.join(HERE, "mcl_oracle.c"), os.path.join(HERE, "mcl_oracle_motion.c")]
 LIB = os.path.join(HERE, "libmcl_oracle.so")
 
 DTYPE_CODE = {"i16": 0, "i8": 1, "f32": 2, "f64": 3}
@@ -26,8 +27,8 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc: -O2, no contraction, no fast-math."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-pthread", "-Wall", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-pthread", "-Wall", "-o", tmp, *SRCS, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -48,6 +49,12 @@ def lib():
         L.oracle_sensor_update_trilinear.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, P, P, C.c_int32,
                                                      P, C.c_int32, C.c_float, P, P, P, C.c_int32]
         L.oracle_normalize.argtypes = [P, C.c_int32, P, P, P]
+        L.oracle_philox4x32.argtypes = [P, P, P]
+        L.oracle_philox4x32.restype = None
+        L.oracle_motion_update.argtypes = [P, P, C.c_int32, P, C.c_float, C.c_float, C.c_uint64, C.c_uint64, P]
+        L.oracle_motion_update.restype = C.c_int
+        L.oracle_init_uniform.argtypes = [P, C.c_float, P, C.c_int32, P, C.c_int32, C.c_float, C.c_uint64, P, P]
+        L.oracle_init_uniform.restype = C.c_int
         L.oracle_resample.argtypes = [P, C.c_int32, C.c_uint64, P]
         for f in (L.oracle_voxel_indices, L.oracle_sensor_update, L.oracle_sensor_update_trilinear,
                   L.oracle_normalize, L.oracle_resample):
@@ -111,6 +118,42 @@ def sensor_update_trilinear(tmap, points: np.ndarray, poses: np.ndarray, sigma: 
                                               _p(sabs), nthreads)
     assert rc == 0
     return (logw, ssum, sabs) if return_sums else logw
+
+
+def philox4x32(counter, key) -> np.ndarray:
+    """Philox4x32-10 of a 4-word counter and a 2-word key: 4 uint32 words."""
+    c = np.ascontiguousarray(counter, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().oracle_philox4x32(_p(c), _p(k), _p(out))
+    return out
+
+
+def motion_update(poses: np.ndarray, delta: np.ndarray, sigma_t: float, sigma_r: float, seed: int, step: int,
+                  return_normals: bool = False):
+    """float64 [12, N] poses after the motion update (and the [6, N] normals drawn)."""
+    ps = np.ascontiguousarray(poses, np.float32)
+    N = ps.shape[1]
+    d = np.ascontiguousarray(delta, np.float32).reshape(12)
+    out = np.empty((12, N), np.float64)
+    nrm = np.empty((6, N), np.float64)
+    rc = lib().oracle_motion_update(_p(ps), _p(out), N, _p(d), sigma_t, sigma_r, C.c_uint64(seed & (2**64 - 1)),
+                                    C.c_uint64(step & (2**64 - 1)), _p(nrm))
+    assert rc == 0
+    return (out, nrm) if return_normals else out
+
+
+def init_uniform(tmap, N: int, max_tilt: float, seed: int):
+    """(float64 [12, N] poses, int64 [N] chosen voxels) uniform over free voxels."""
+    dims, origin, vals = _map_args(tmap)
+    out = np.empty((12, N), np.float64)
+    vox = np.empty(N, np.int64)
+    rc = lib().oracle_init_uniform(_p(dims), tmap.voxel, _p(origin), DTYPE_CODE[tmap.dtype], _p(vals), N, max_tilt,
+                                   C.c_uint64(seed & (2**64 - 1)), _p(out), _p(vox))
+    if rc == -3:
+        raise ValueError("the map has no free voxel")
+    assert rc == 0
+    return out, vox
 
 
 def normalize(logw: np.ndarray):

@@ -288,6 +288,7 @@ extern "C" mcl_status mcl_map_free(mcl_map map) {
     if (!map) return fail(MCL_EINVAL, "map_free: NULL map");
     hipError_t e = hipFree(map->dev);
     if (map->tri_dev && hipFree(map->tri_dev) != hipSuccess) e = hipErrorInvalidValue;
+    if (map->free_prefix && hipFree(map->free_prefix) != hipSuccess) e = hipErrorInvalidValue;
     delete map;
     return e == hipSuccess ? MCL_OK : fail(MCL_EDEVICE, "map_free: hipFree failed");
 }

@@ -77,6 +77,8 @@ struct mcl_map_s {
     void *tri_dev;      // corner cells for the trilinear lookup, or null
     size_t tri_bytes;
     mcl::TriView tri;
+    void *free_prefix;  // free voxels before each 64-voxel row chunk (uniform initialisation), or null
+    uint64_t free_total;
 };
 
 namespace mcl {

@@ -1,9 +1,9 @@
 """Python binding of libmcl.so: argument marshalling only.
 
-Every step of the sensor update, normalisation and resampling runs in the HIP
-kernels behind the C ABI (include/mcl.h).  torch supplies device memory and
-streams.  If the built library is missing this module raises at import: there
-is no fallback.
+Every step of the sensor update, normalisation, pose estimate, resampling,
+motion update and initialisation runs in the HIP kernels behind the C ABI
+(include/mcl.h).  torch supplies device memory and streams.  If the built
+library is missing this module raises at import: there is no fallback.
 """
 
 from __future__ import annotations
@@ -12,6 +12,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch before the library: the library then binds to the HIP runtime torch has
+# loaded, so one runtime serves both (loading the library first would make torch
+# share a runtime it was not built against)
+import torch  # noqa: F401
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MCL_LIBRARY") or os.path.join(PKG, "libmcl.so")
@@ -55,6 +59,9 @@ _lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
 _lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, _P, _P, _P, _P]
 _lib.mcl_debug_voxel_indices.argtypes = [_P, _P, _I, _P, _I, _P, _P]
 _lib.mcl_pose_estimate.argtypes = [_P, _P, _I, _P, _P, _P, _P]
+_lib.mcl_motion_update.argtypes = [_P, _P, _I, _P, C.c_float, C.c_float, C.c_uint64, C.c_uint64, _P]
+_lib.mcl_init_uniform.argtypes = [_P, _P, _I, C.c_float, C.c_uint64, _P]
+_lib.mcl_debug_philox.argtypes = [_P, _P]
 _lib.mcl_tick.argtypes = [C.POINTER(FilterJob), _I, _I, _P]
 _lib.mcl_job_bytes.argtypes = [_I, _I]
 _lib.mcl_job_bytes.restype = C.c_size_t
@@ -63,7 +70,8 @@ _lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_last_error.restype = C.c_char_p
 for _f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear", "mcl_normalize",
            "mcl_resample",
-           "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_pose_estimate"):
+           "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_pose_estimate", "mcl_motion_update",
+           "mcl_init_uniform", "mcl_debug_philox"):
     getattr(_lib, _f).restype = C.c_int32
 
 
@@ -220,6 +228,41 @@ def pose_estimate(w, poses, mean=None, best_idx=None, best_pose=None, stream=Non
     _check(_lib.mcl_pose_estimate(_ptr(w), _ptr(poses), N, _ptr(mean), _ptr(best_idx), _ptr(best_pose),
                                   _stream(stream)), "mcl_pose_estimate")
     return mean, best_idx, best_pose
+
+
+def motion_update(poses_in, delta, sigma_t: float, sigma_r: float, seed: int, step: int, poses_out=None,
+                  stream=None):
+    """Poses [12, N] after the motion update (in place if poses_out is poses_in)."""
+    import torch
+    N = poses_in.shape[1]
+    _dev(poses_in, torch.float32, (12, N), "poses_in")
+    if poses_out is None:
+        poses_out = torch.empty_like(poses_in)
+    _dev(poses_out, torch.float32, (12, N), "poses_out")
+    d = np.ascontiguousarray(np.asarray(delta, np.float32).reshape(12))
+    _check(_lib.mcl_motion_update(_ptr(poses_in), _ptr(poses_out), N, d.ctypes.data_as(C.c_void_p), float(sigma_t),
+                                  float(sigma_r), C.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                  C.c_uint64(int(step) & (2 ** 64 - 1)), _stream(stream)), "mcl_motion_update")
+    return poses_out
+
+
+def init_uniform(m: Map, N: int, max_tilt: float, seed: int, poses=None, device=None, stream=None):
+    """[12, N] poses uniform over the map's free voxels (see include/mcl.h)."""
+    import torch
+    if poses is None:
+        poses = torch.empty((12, N), dtype=torch.float32, device=device or "cuda")
+    _dev(poses, torch.float32, (12, N), "poses")
+    _check(_lib.mcl_init_uniform(m.handle, _ptr(poses), N, float(max_tilt), C.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                 _stream(stream)), "mcl_init_uniform")
+    return poses
+
+
+def debug_philox(counter, key) -> np.ndarray:
+    """Philox4x32-10 on the device (test support): 4 uint32 words."""
+    ck = np.ascontiguousarray(list(counter) + list(key), np.uint32)
+    out = np.empty(4, np.uint32)
+    _check(_lib.mcl_debug_philox(ck.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)), "mcl_debug_philox")
+    return out
 
 
 def debug_voxel_indices(m: Map, points, poses, out=None, stream=None):

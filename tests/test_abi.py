@@ -27,7 +27,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
               "mcl_debug_voxel_indices", "mcl_last_error", "mcl_tick", "mcl_job_bytes", "mcl_autotune",
-              "mcl_set_launch_config", "mcl_pose_estimate", "mcl_sensor_update_trilinear"):
+              "mcl_set_launch_config", "mcl_pose_estimate", "mcl_sensor_update_trilinear", "mcl_motion_update",
+              "mcl_init_uniform"):
         assert f in names
 
 
@@ -58,6 +59,16 @@ def test_argument_errors_are_reported_on_the_host(mcl):
     assert lib.mcl_pose_estimate(P(0x10000), P(0x20000), 100, P(0x10008), None, None, None) == mcl.MCL_EINVAL
     assert lib.mcl_pose_estimate(P(0x10000), P(0x20000), 100, P(0x90000), P(0x90010), None,
                                  None) == mcl.MCL_EINVAL
+    d12 = (C.c_float * 12)(*([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0]))
+    assert lib.mcl_motion_update(None, fake, 10, d12, 0.1, 0.1, 1, 1, None) == mcl.MCL_EINVAL
+    assert lib.mcl_motion_update(fake, fake, 0, d12, 0.1, 0.1, 1, 1, None) == mcl.MCL_EINVAL
+    assert lib.mcl_motion_update(fake, fake, 10, d12, -0.1, 0.1, 1, 1, None) == mcl.MCL_EINVAL
+    assert lib.mcl_motion_update(P(0x10000), P(0x10004), 10, d12, 0.1, 0.1, 1, 1, None) == mcl.MCL_EINVAL
+    bad = (C.c_float * 12)(*([float("nan")] + [0.0] * 11))
+    assert lib.mcl_motion_update(fake, fake, 10, bad, 0.1, 0.1, 1, 1, None) == mcl.MCL_EINVAL
+    assert lib.mcl_init_uniform(None, fake, 10, 0.1, 1, None) == mcl.MCL_EINVAL
+    assert lib.mcl_init_uniform(fake, fake, 10, -1.0, 1, None) == mcl.MCL_EINVAL
+    assert lib.mcl_init_uniform(fake, fake, mcl.MAX_PARTICLES + 1, 0.1, 1, None) == mcl.MCL_ERANGE
     # overlapping output and input
     assert lib.mcl_normalize(P(0x10000), 100, None, P(0x10010), None, None) == mcl.MCL_EINVAL
     d = mcl.MapDesc(0, 4, 4, 0.1, (C.c_float * 3)(0, 0, 0), 0.3, 0)
