@@ -12,7 +12,8 @@ Prints one JSON line.  `value` is particle-point evaluations per second
 update) measured with HIP events on its stream; `cpu_baseline` times the CPU
 oracle on a bounded particle sample of the same workload.
 
-Other workloads (not the default line): --workload loop (the whole MCL loop on the
+Other workloads (not the default line): --workload sparse (the default workload with the
+map held as a sparse coarse/fine brick pool), --workload loop (the whole MCL loop on the
 device: uniform initialisation, then motion, sensor, normalise, estimate, resample per
 iteration, with per-stage times), --workload trilinear (the default workload with
 the trilinear map lookup), --workload estimate (the pose estimate alone,
@@ -123,14 +124,26 @@ def base_record(args, metric, value, ms_step, config, dtype="f32"):
             "config": config}
 
 
-def run_single(args, w, workload_key, with_roofline=True, trilinear=False):
+def run_single(args, w, workload_key, with_roofline=True, trilinear=False, sparse=False):
     """A plain single-filter update: sensor update + normalise + resample, timed.
-    trilinear: the sensor update reads the map by trilinear interpolation."""
+    trilinear: the sensor update reads the map by trilinear interpolation;
+    sparse: the map is held as a coarse table + pool of band bricks."""
     import torch
     from paper_2310_04172_amd import mcl
 
     dev = torch.device("cuda:0")
-    m = mcl.Map.from_tsdf(w.tmap)
+    sparse_info = None
+    if sparse:
+        from workloads.tsdf import to_bricks
+        co, va = to_bricks(w.tmap)
+        m = mcl.Map.from_bricks(w.tmap.dims, w.tmap.voxel, w.tmap.origin, w.tmap.tau, w.tmap.dtype, co, va)
+        nb = ((w.tmap.nx + 3) // 4) * ((w.tmap.ny + 3) // 4) * ((w.tmap.nz + 3) // 4)
+        sparse_info = {"stored_bricks": int(co.shape[0]), "bricks": nb,
+                       "device_bytes": int((nb + 31) // 32 * 8 + (co.shape[0] + 2) * va.itemsize * 64),
+                       "dense_device_bytes": int(nb * 64 * va.itemsize + nb)}
+        log(f"sparse map: {json.dumps(sparse_info)}")
+    else:
+        m = mcl.Map.from_tsdf(w.tmap)
     pts = torch.from_numpy(w.points).to(dev)
     poses = torch.from_numpy(w.poses).to(dev)
     N, K = w.N, w.K
@@ -193,7 +206,9 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False):
                        "workload_key": workload_key, "sensor_update_ms": sensor_ms})
     out["latency_ms"] = {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}
     out["pose_estimate"] = est
-    if with_roofline and not trilinear:
+    if sparse_info:
+        out["config"]["sparse_map"] = sparse_info
+    if with_roofline and not trilinear and not sparse:
         flops = 20.0 * evals   # 9 fused multiply-adds (transform) + 1 (score), 2 flops each, per evaluation
         achieved = flops / (sensor_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -511,7 +526,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision", "estimate", "trilinear", "loop"])
+    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision", "estimate", "trilinear", "loop",
+                                                    "sparse"])
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -544,10 +560,11 @@ def main():
         t0 = time.perf_counter()
         w = configs.config1() if args.workload == "small" else configs.config2()
         log(f"workload built in {time.perf_counter() - t0:.1f} s: N={w.N} K={w.K}")
-        out = run_single(args, w, args.workload, trilinear=args.workload == "trilinear")
-        if args.workload == "trilinear":
-            out["metric"] = METRIC + " [trilinear lookup]"
-        if not args.no_cpu_baseline and args.workload != "trilinear":
+        out = run_single(args, w, args.workload, trilinear=args.workload == "trilinear",
+                         sparse=args.workload == "sparse")
+        if args.workload in ("trilinear", "sparse"):
+            out["metric"] = METRIC + (" [trilinear lookup]" if args.workload == "trilinear" else " [sparse map]")
+        if not args.no_cpu_baseline and args.workload not in ("trilinear", "sparse"):
             out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

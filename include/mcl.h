@@ -76,6 +76,23 @@ typedef struct mcl_map_s *mcl_map; /* opaque; device-resident, immutable */
 mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_values, void *stream,
                           mcl_map *out);
 
+/* Upload a sparse coarse/fine map (§III: the map holds fine data only for the
+ * parts of the coarse grid with distances inside the truncation band, after
+ * Akai et al.).  The grid is cut into 4x4x4 bricks (brick (bx, by, bz) holds
+ * voxels 4bx..4bx+3 etc.); only the listed bricks are stored, every other
+ * voxel reads +Q (+tau): free or unobserved space.  Memory grows with the
+ * number of stored bricks, and the map may exceed the 4 GiB limit of the dense
+ * layout (limits: nbx*nby*nbz < 2^31 bricks, nbz*nbx < 2^24).  The sensor
+ * update gives exactly the results of the dense map with the same values; the
+ * trilinear lookup, the uniform initialisation and mcl_tick reject sparse maps.
+ *   nstored:      number of listed bricks, >= 0.
+ *   brick_coords: HOST [nstored][3] int32 (bx, by, bz), each brick at most once.
+ *   brick_values: HOST [nstored][64] values of the storage type, in-brick index
+ *                 x + 4 y + 16 z (voxels beyond the map edge are never read).
+ * The call copies everything and synchronises `stream`. */
+mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t nstored, const int32_t *brick_coords,
+                                 const void *brick_values, void *stream, mcl_map *out);
+
 /* Release a map.  The caller must ensure no enqueued work still reads it. */
 mcl_status mcl_map_free(mcl_map map);
 

@@ -49,6 +49,9 @@ def lib():
         L.oracle_sensor_update_trilinear.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, P, P, C.c_int32,
                                                      P, C.c_int32, C.c_float, P, P, P, C.c_int32]
         L.oracle_normalize.argtypes = [P, C.c_int32, P, P, P]
+        L.oracle_sensor_update_bricks.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, C.c_int64, P, P, P, C.c_int32,
+                                                  P, C.c_int32, C.c_float, P, P, C.c_int32]
+        L.oracle_sensor_update_bricks.restype = C.c_int
         L.oracle_philox4x32.argtypes = [P, P, P]
         L.oracle_philox4x32.restype = None
         L.oracle_motion_update.argtypes = [P, P, C.c_int32, P, C.c_float, C.c_float, C.c_uint64, C.c_uint64, P]
@@ -101,6 +104,23 @@ def sensor_update(tmap, points: np.ndarray, poses: np.ndarray, sigma: float, nth
                                     _p(vals), _p(pts), K, _p(ps), N, sigma, _p(logw), _p(ssum), nthreads)
     assert rc == 0
     return (logw, ssum) if return_sum else logw
+
+
+def sensor_update_bricks(dims, voxel: float, origin, tau: float, dtype: str, coords: np.ndarray, values: np.ndarray,
+                         points: np.ndarray, poses: np.ndarray, sigma: float, nthreads: int = 1):
+    """float64 log-weights on a sparse map given as bricks (unlisted bricks read +Q)."""
+    d = np.asarray(dims, np.int32)
+    o = np.asarray(origin, np.float32)
+    co = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)
+    va = np.ascontiguousarray(values, {"i16": np.int16, "i8": np.int8, "f32": np.float32}[dtype]).reshape(-1, 64)
+    pts = np.ascontiguousarray(points, np.float32)
+    ps = np.ascontiguousarray(poses, np.float32)
+    K, N = pts.shape[1], ps.shape[1]
+    logw = np.empty(N, np.float64)
+    rc = lib().oracle_sensor_update_bricks(_p(d), voxel, _p(o), tau, DTYPE_CODE[dtype], co.shape[0], _p(co), _p(va),
+                                           _p(pts), K, _p(ps), N, sigma, _p(logw), None, nthreads)
+    assert rc == 0
+    return logw
 
 
 def sensor_update_trilinear(tmap, points: np.ndarray, poses: np.ndarray, sigma: float, nthreads: int = 1,

@@ -48,6 +48,12 @@
  *    unquantised distances) serves as the precision reference of the storage
  *    types.
  *
+ *  Sparse coarse/fine map (§III, after Akai et al.: fine data only where the
+ *    coarse grid holds distances inside the truncation band).  A storage form
+ *    only: 4x4x4 bricks of the voxel grid are listed with their values and
+ *    every voxel of an unlisted brick reads +Q (+tau); the score is the dense
+ *    definition on those values.
+ *
  *  Trilinear lookup (§III: a pseudo-continuous state by interpolation).
  *    Reading: the stored values sit at the voxel centres, grid coordinate
  *    i + 1/2; a point's map value is the trilinear interpolation of the 8
@@ -158,13 +164,42 @@ typedef struct {
     double *logw;
     double *ssum;
     int64_t n0, n1;    /* this worker's particle range */
+    /* sparse coarse/fine map: slot per 4x4x4 brick (-1: not stored), bricks of 64 values */
+    const int32_t *table;
+    const void *bricks;
+    int64_t nbx, nby, nbz;
 } su_job_t;
+
+/* Stored value of voxel v (linear index) of a sparse map as an exact double:
+ * the listed brick's value, or Q (tau) for bricks that are not listed. */
+static double sparse_value(const su_job_t *J, int64_t v) {
+    const int64_t nx = J->g.n[0], ny = J->g.n[1];
+    const int64_t i = v % nx, j = (v / nx) % ny, k = v / (nx * ny);
+    const int64_t b = (k >> 2) + J->nbz * ((i >> 2) + J->nbx * (j >> 2));
+    const int32_t slot = J->table[b];
+    if (slot < 0) return J->dtype == ORACLE_F32 ? (double)(float)J->tau : (double)J->Q;
+    const int64_t e = (int64_t)slot * 64 + (i & 3) + 4 * (j & 3) + 16 * (k & 3);
+    switch (J->dtype) {
+    case ORACLE_I16: return ((const int16_t *)J->bricks)[e];
+    case ORACLE_I8: return ((const int8_t *)J->bricks)[e];
+    default: return ((const float *)J->bricks)[e];
+    }
+}
 
 /* Sum of squared map values over the scan for particle n: exact for fixed point. */
 static double particle_sum_sq(const su_job_t *J, int64_t n) {
     float a[9], b[3];
     particle_consts(J->poses, J->N, n, &J->g, a, b);
     const float *px = J->points, *py = J->points + J->K, *pz = J->points + 2 * J->K;
+    if (J->table) { /* sparse map; exact for fixed point (integers < 2^53 in total) */
+        double acc = 0.0;
+        for (int64_t k = 0; k < J->K; ++k) {
+            int64_t v = voxel_index(a, b, px[k], py[k], pz[k], &J->g);
+            double d = v < 0 ? (J->dtype == ORACLE_F32 ? (double)(float)J->tau : (double)J->Q) : sparse_value(J, v);
+            acc += d * d;
+        }
+        return acc;
+    }
     if (J->dtype == ORACLE_F32) {
         const float *vals = (const float *)J->values;
         double acc = 0.0;
@@ -262,6 +297,76 @@ int oracle_sensor_update(const int32_t dims[3], float voxel, const float origin[
     free(jobs);
     free(th);
     return 0;
+}
+
+/*
+ * l_n for a sparse coarse/fine map given as a list of bricks (the definition is
+ * the dense one; only the storage differs): nstored bricks, coords [nstored][3]
+ * (bx, by, bz), values [nstored][64] (index x + 4 y + 16 z within the brick);
+ * every voxel of an unlisted brick reads Q (tau).
+ */
+int oracle_sensor_update_bricks(const int32_t dims[3], float voxel, const float origin[3], float tau, int32_t dtype,
+                                int64_t nstored, const int32_t *coords, const void *values, const float *points,
+                                int32_t K, const float *poses, int32_t N, float sigma, double *logw, double *ssum,
+                                int32_t nthreads) {
+    if (K < 0 || N < 0 || dtype < 0 || dtype > 2 || !(sigma > 0.0f) || nstored < 0) return -1;
+    const int64_t nbx = (dims[0] + 3) / 4, nby = (dims[1] + 3) / 4, nbz = (dims[2] + 3) / 4;
+    int32_t *table = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nbx * nby * nbz));
+    if (!table) return -2;
+    for (int64_t b = 0; b < nbx * nby * nbz; ++b) table[b] = -1;
+    for (int64_t s = 0; s < nstored; ++s) {
+        int64_t bx = coords[3 * s], by = coords[3 * s + 1], bz = coords[3 * s + 2];
+        if (bx < 0 || by < 0 || bz < 0 || bx >= nbx || by >= nby || bz >= nbz) {
+            free(table);
+            return -1;
+        }
+        table[bz + nbz * (bx + nbx * by)] = (int32_t)s;
+    }
+    su_job_t base;
+    memset(&base, 0, sizeof base);
+    base.g = make_grid(dims, voxel, origin);
+    base.dtype = dtype;
+    base.tau = (double)tau;
+    base.Q = dtype == ORACLE_I16 ? 32767 : dtype == ORACLE_I8 ? 127 : 1;
+    base.points = points;
+    base.K = K;
+    base.poses = poses;
+    base.N = N;
+    double s = dtype == ORACLE_F32 ? 1.0 : (double)tau / (double)base.Q;
+    double sg = (double)sigma;
+    base.c = (s * s) / (2.0 * sg * sg);
+    base.logw = logw;
+    base.ssum = ssum;
+    base.table = table;
+    base.bricks = values;
+    base.nbx = nbx;
+    base.nby = nby;
+    base.nbz = nbz;
+    int rc = 0;
+    if (nthreads <= 1 || N < 2) {
+        base.n0 = 0;
+        base.n1 = N;
+        su_worker(&base);
+    } else {
+        if (nthreads > N) nthreads = N;
+        su_job_t *jobs = (su_job_t *)malloc(sizeof(su_job_t) * (size_t)nthreads);
+        pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+        if (!jobs || !th) {
+            rc = -2;
+        } else {
+            for (int t = 0; t < nthreads; ++t) {
+                jobs[t] = base;
+                jobs[t].n0 = (int64_t)N * t / nthreads;
+                jobs[t].n1 = (int64_t)N * (t + 1) / nthreads;
+                pthread_create(&th[t], NULL, su_worker, &jobs[t]);
+            }
+            for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+        }
+        free(jobs);
+        free(th);
+    }
+    free(table);
+    return rc;
 }
 
 /* ------------------------------------------------------- trilinear lookup */

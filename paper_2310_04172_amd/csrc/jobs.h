@@ -20,7 +20,8 @@ inline int sensor_pieces(int K) { return K <= 0 ? 1 : (K + kPiece - 1) / kPiece;
 
 struct SensorJob {
     MapView map;
-    TriView tri;          // bordered map (trilinear lookup only)
+    TriView tri;          // corner cells (trilinear lookup only)
+    SparseView sp;        // coarse table + pool (sparse maps only)
     const float *pts;     // [3][K]
     const float *poses;   // [12][N]
     float *logw;          // [N] output

@@ -3,6 +3,8 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "mcl_internal.h"
 #include "voxel.h"
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(256) void tri_class_kernel(const T *__restrict__ ce
 static std::mutex g_tri_mu;
 
 mcl_status ensure_trilinear(mcl_map_s *m, hipStream_t stream) {
+    if (m->sparse) return fail(MCL_EINVAL, "trilinear: not available for sparse maps (mcl_map_upload_bricks)");
     std::lock_guard<std::mutex> lk(g_tri_mu);
     if (m->tri_dev) return MCL_OK;
     const MapView &v = m->view;
@@ -173,21 +176,135 @@ mcl_status ensure_trilinear(mcl_map_s *m, hipStream_t stream) {
     return MCL_OK;
 }
 
+static mcl_status check_desc(const mcl_map_desc &d, const char *what) {
+    const std::string w(what);
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(MCL_EINVAL, w + ": dimensions must be >= 1");
+    if (d.nx >= (1 << 24) || d.ny >= (1 << 24) || d.nz >= (1 << 24))
+        return fail(MCL_ERANGE, w + ": dimensions must be below 2^24");
+    if (!(std::isfinite(d.voxel) && d.voxel > 0.0f)) return fail(MCL_EINVAL, w + ": voxel must be finite and > 0");
+    if (!(std::isfinite(d.tau) && d.tau > 0.0f)) return fail(MCL_EINVAL, w + ": tau must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d.origin[a])) return fail(MCL_EINVAL, w + ": origin must be finite");
+    if (d.dtype < MCL_TSDF_I16 || d.dtype > MCL_TSDF_F32) return fail(MCL_EINVAL, w + ": unknown dtype");
+    return MCL_OK;
+}
+
+// The fields of a map handle that both layouts share: grid, index recipe, scale.
+static void fill_common(mcl_map_s *m, const mcl_map_desc &d) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    m->device = dev;
+    m->dtype = d.dtype;
+    m->Q = d.dtype == MCL_TSDF_I16 ? 32767 : d.dtype == MCL_TSDF_I8 ? 127 : 1;
+    m->tau = d.tau;
+    m->voxel = d.voxel;
+    m->scale = d.dtype == MCL_TSDF_F32 ? 1.0 : (double)d.tau / (double)m->Q;
+    MapView &v = m->view;
+    v.nx = d.nx; v.ny = d.ny; v.nz = d.nz;
+    v.nbx = (d.nx + 3) / 4; v.nby = (d.ny + 3) / 4; v.nbz = (d.nz + 3) / 4;
+    float fx = (float)d.nx, fy = (float)d.ny, fz = (float)d.nz;
+    std::memcpy(&v.bx, &fx, 4);
+    std::memcpy(&v.by, &fy, 4);
+    std::memcpy(&v.bz, &fz, 4);
+    v.inv_v = (float)(1.0 / (double)d.voxel);
+    v.ox = d.origin[0]; v.oy = d.origin[1]; v.oz = d.origin[2];
+}
+
 }  // namespace mcl
 
 using namespace mcl;
+
+extern "C" mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t nstored, const int32_t *brick_coords,
+                                            const void *brick_values, void *stream_, mcl_map *out) {
+    if (!desc || !out || (nstored > 0 && (!brick_coords || !brick_values)))
+        return fail(MCL_EINVAL, "map_upload_bricks: NULL argument");
+    *out = nullptr;
+    const mcl_map_desc &d = *desc;
+    mcl_status st = check_desc(d, "map_upload_bricks");
+    if (st != MCL_OK) return st;
+    if (nstored < 0) return fail(MCL_EINVAL, "map_upload_bricks: nstored must be >= 0");
+    const int64_t nbx = (d.nx + 3) / 4, nby = (d.ny + 3) / 4, nbz = (d.nz + 3) / 4;
+    const int64_t nbricks = nbx * nby * nbz;
+    if (nbricks >= ((int64_t)1 << 31) || nbz * nbx >= ((int64_t)1 << 24) || nstored + 2 >= ((int64_t)1 << 31))
+        return fail(MCL_ERANGE, "map_upload_bricks: too many bricks (need nbx*nby*nbz < 2^31, nbz*nbx < 2^24)");
+    const int es = elem_size(d.dtype);
+    // which input brick sits at each brick index (-1: not stored)
+    std::vector<int32_t> at((size_t)nbricks, -1);
+    for (int64_t i = 0; i < nstored; ++i) {
+        const int32_t bx = brick_coords[3 * i], by = brick_coords[3 * i + 1], bz = brick_coords[3 * i + 2];
+        if (bx < 0 || by < 0 || bz < 0 || bx >= nbx || by >= nby || bz >= nbz)
+            return fail(MCL_EINVAL, "map_upload_bricks: brick " + std::to_string(i) + " outside the grid");
+        int32_t &slot = at[(size_t)(bz + nbz * (bx + nbx * (int64_t)by))];
+        if (slot >= 0) return fail(MCL_EINVAL, "map_upload_bricks: brick " + std::to_string(i) + " listed twice");
+        slot = (int32_t)i;
+    }
+    // rank table {mask, stored before} per 32 bricks, and the pool in brick-index order
+    const int64_t ngroups = (nbricks + 31) / 32;
+    std::vector<uint32_t> coarse((size_t)ngroups * 2, 0u);
+    const size_t brick_bytes = (size_t)64 * es;
+    const size_t pool_bytes = (size_t)(nstored + 2) * brick_bytes;
+    std::vector<char> pool_h(pool_bytes, 0);
+    for (int w = 0; w < 64; ++w) {  // slot 0: +Q; slot 1 stays zero
+        if (d.dtype == MCL_TSDF_I16) reinterpret_cast<int16_t *>(pool_h.data())[w] = 32767;
+        else if (d.dtype == MCL_TSDF_I8) reinterpret_cast<int8_t *>(pool_h.data())[w] = 127;
+        else reinterpret_cast<float *>(pool_h.data())[w] = d.tau;
+    }
+    const char *src = static_cast<const char *>(brick_values);
+    uint32_t rank = 0;
+    for (int64_t g = 0; g < ngroups; ++g) {
+        uint32_t mask = 0;
+        coarse[(size_t)g * 2 + 1] = rank;
+        for (int k = 0; k < 32 && g * 32 + k < nbricks; ++k) {
+            const int32_t i = at[(size_t)(g * 32 + k)];
+            if (i < 0) continue;
+            mask |= 1u << k;
+            std::memcpy(pool_h.data() + (size_t)(2 + rank) * brick_bytes, src + (size_t)i * brick_bytes, brick_bytes);
+            ++rank;
+        }
+        coarse[(size_t)g * 2] = mask;
+    }
+    mcl_map_s *m = new (std::nothrow) mcl_map_s();
+    if (!m) return fail(MCL_ENOMEM, "map_upload_bricks: host allocation failed");
+    if (hipMalloc(&m->sp_coarse, coarse.size() * 4) != hipSuccess) {
+        delete m;
+        return fail(MCL_ENOMEM, "map_upload_bricks: device allocation failed");
+    }
+    if (hipMalloc(&m->sp_pool, pool_bytes) != hipSuccess) {
+        (void)hipFree(m->sp_coarse);
+        delete m;
+        return fail(MCL_ENOMEM, "map_upload_bricks: device allocation failed");
+    }
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    bool ok = hipMemcpyAsync(m->sp_coarse, coarse.data(), coarse.size() * 4, hipMemcpyHostToDevice, stream) == hipSuccess &&
+              hipMemcpyAsync(m->sp_pool, pool_h.data(), pool_bytes, hipMemcpyHostToDevice, stream) == hipSuccess &&
+              hipStreamSynchronize(stream) == hipSuccess;
+    if (!ok) {
+        (void)hipFree(m->sp_coarse);
+        (void)hipFree(m->sp_pool);
+        delete m;
+        return fail(MCL_EDEVICE, "map_upload_bricks: copy to device failed");
+    }
+    fill_common(m, d);
+    m->sparse = true;
+    m->bytes = coarse.size() * 4 + pool_bytes;
+    m->sp.coarse = static_cast<const uint2 *>(m->sp_coarse);
+    m->sp.pool = static_cast<const char *>(m->sp_pool);
+    m->sp.nbz = (uint32_t)nbz;
+    m->sp.nbzx = (uint32_t)(nbz * nbx);
+    m->sp.small = (nstored + 2 < ((int64_t)1 << 24) && pool_bytes < ((size_t)1 << 32)) ? 1u : 0u;
+    *out = m;
+    return MCL_OK;
+}
 
 extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_values, void *stream_,
                                      mcl_map *out) {
     if (!desc || !host_values || !out) return fail(MCL_EINVAL, "map_upload: NULL argument");
     *out = nullptr;
     const mcl_map_desc &d = *desc;
-    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(MCL_EINVAL, "map_upload: dimensions must be >= 1");
-    if (!(std::isfinite(d.voxel) && d.voxel > 0.0f)) return fail(MCL_EINVAL, "map_upload: voxel must be finite and > 0");
-    if (!(std::isfinite(d.tau) && d.tau > 0.0f)) return fail(MCL_EINVAL, "map_upload: tau must be finite and > 0");
-    for (int a = 0; a < 3; ++a)
-        if (!std::isfinite(d.origin[a])) return fail(MCL_EINVAL, "map_upload: origin must be finite");
-    if (d.dtype < MCL_TSDF_I16 || d.dtype > MCL_TSDF_F32) return fail(MCL_EINVAL, "map_upload: unknown dtype");
+    {
+        mcl_status cst = check_desc(d, "map_upload");
+        if (cst != MCL_OK) return cst;
+    }
     const int es = elem_size(d.dtype);
     const int nbx = (d.nx + 3) / 4, nby = (d.ny + 3) / 4, nbz = (d.nz + 3) / 4;
     const int64_t nvals = (int64_t)nbx * nby * nbz * kBrickVals;
@@ -254,27 +371,10 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
         delete m;
         return st;
     }
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    m->device = dev;
+    fill_common(m, d);
     m->bytes = (size_t)total;
-    m->dtype = d.dtype;
-    m->Q = d.dtype == MCL_TSDF_I16 ? 32767 : d.dtype == MCL_TSDF_I8 ? 127 : 1;
-    m->tau = d.tau;
-    m->voxel = d.voxel;
-    m->scale = d.dtype == MCL_TSDF_F32 ? 1.0 : (double)d.tau / (double)m->Q;
     MapView &v = m->view;
     v.base = static_cast<const char *>(m->dev);
-    v.nx = d.nx; v.ny = d.ny; v.nz = d.nz;
-    v.nbx = nbx; v.nby = nby; v.nbz = nbz;
-    {
-        float fx = (float)d.nx, fy = (float)d.ny, fz = (float)d.nz;
-        std::memcpy(&v.bx, &fx, 4);
-        std::memcpy(&v.by, &fy, 4);
-        std::memcpy(&v.bz, &fz, 4);
-    }
-    v.inv_v = (float)(1.0 / (double)d.voxel);
-    v.ox = d.origin[0]; v.oy = d.origin[1]; v.oz = d.origin[2];
     v.cx = (uint32_t)(es * (16 * nbz - 1));
     v.cy = (uint32_t)cy;
     v.out_off = (uint32_t)data_bytes;
@@ -286,7 +386,10 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
 
 extern "C" mcl_status mcl_map_free(mcl_map map) {
     if (!map) return fail(MCL_EINVAL, "map_free: NULL map");
-    hipError_t e = hipFree(map->dev);
+    hipError_t e = hipSuccess;
+    if (map->dev) e = hipFree(map->dev);
+    if (map->sp_coarse && hipFree(map->sp_coarse) != hipSuccess) e = hipErrorInvalidValue;
+    if (map->sp_pool && hipFree(map->sp_pool) != hipSuccess) e = hipErrorInvalidValue;
     if (map->tri_dev && hipFree(map->tri_dev) != hipSuccess) e = hipErrorInvalidValue;
     if (map->free_prefix && hipFree(map->free_prefix) != hipSuccess) e = hipErrorInvalidValue;
     delete map;

@@ -62,6 +62,22 @@ struct TriView {
 };
 constexpr uint8_t kCellMixed = 0, kCellPos = 1, kCellNeg = 3;
 
+// Sparse coarse/fine map (§III: the map holds fine data only for the coarse
+// cells with distances inside the truncation band, after Akai et al.): a pool
+// of the stored 4x4x4 bricks (64 values each, in brick-index order) and a
+// coarse rank table: per 32 consecutive brick indices a 32-bit mask of the
+// stored ones and the number stored before them, 8 bytes per 32 bricks, so the
+// table of a 2-million-brick map is 0.5 MB and stays in L2.  A stored brick's
+// slot is 2 + base + popcount(mask below it); slot 0 is a brick of +Q
+// (unstored bricks, points outside the map), slot 1 a brick of zeros (padding
+// lanes).  A lookup is two dependent gathers (rank entry, then value).
+struct SparseView {
+    const uint2 *coarse;     // device [2 ngroups]: {mask, stored before} per 32 bricks
+    const char *pool;        // device [nslots][64] values
+    uint32_t nbz, nbzx;      // brick index = bz + nbz bx + nbz nbx by (both < 2^24)
+    uint32_t small;          // pool below 2^24 slots and 4 GiB: 32-bit offsets
+};
+
 }  // namespace mcl
 
 struct mcl_map_s {
@@ -79,6 +95,9 @@ struct mcl_map_s {
     mcl::TriView tri;
     void *free_prefix;  // free voxels before each 64-voxel row chunk (uniform initialisation), or null
     uint64_t free_total;
+    bool sparse;        // coarse table + brick pool (view.base and view.cls unused)
+    mcl::SparseView sp;
+    void *sp_coarse, *sp_pool;
 };
 
 namespace mcl {

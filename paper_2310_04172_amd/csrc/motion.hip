@@ -283,6 +283,7 @@ extern "C" mcl_status mcl_init_uniform(mcl_map map, float *poses, int32_t N, flo
     if (N < 1) return fail(MCL_EINVAL, "init_uniform: need N >= 1");
     if (N > MCL_MAX_PARTICLES) return fail(MCL_ERANGE, "init_uniform: N above the limit");
     if (!(std::isfinite(max_tilt) && max_tilt >= 0.0f)) return fail(MCL_EINVAL, "init_uniform: max_tilt must be >= 0");
+    if (map->sparse) return fail(MCL_EINVAL, "init_uniform: not available for sparse maps (mcl_map_upload_bricks)");
     hipStream_t s = static_cast<hipStream_t>(stream);
     FreeIndex fi;
     mcl_status st = ensure_free_index(map, s, fi);

@@ -226,8 +226,76 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_tri(const 
     return s;
 }
 
-template <typename T, bool TAIL, bool TRI>
-__device__ __attribute__((always_inline)) inline void chunk_group(const MapView &m, const TriView &tv, const float (&pa)[12], const float (&px)[kU],
+// Sparse map (rank table + brick pool): the brick's rank entry first, then the
+// value in the pool; points outside the map read slot 0 (the +Q brick) and
+// padding slots slot 1 (zeros).  Same index recipe, values and summation order
+// as the dense layout, so a map gives the same bits in either form.
+template <typename T>
+__device__ inline int load_raw64(const char *p) {
+    if constexpr (sizeof(T) == 4)
+        return __float_as_int(*reinterpret_cast<const float *>(p));
+    else
+        return (int)*reinterpret_cast<const T *>(p);
+}
+
+template <typename T, bool TAIL, bool WIDE>
+__device__ __attribute__((always_inline)) inline float lane_chunk_sum_sparse(const MapView &m, const SparseView &sp,
+                                                                             const float (&A)[12], const float (&px)[kU],
+                                                                             const float (&py)[kU], const float (&pz)[kU],
+                                                                             int lane, int nvalid) {
+    uint32_t bidx[kU], wv[kU], sel[kU];  // sel: 0 inside, 1 outside (+Q), 2 padding (0)
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const float gx = grid_coord(A[0], A[1], A[2], A[9], px[u], py[u], pz[u]);
+        const float gy = grid_coord(A[3], A[4], A[5], A[10], px[u], py[u], pz[u]);
+        const float gz = grid_coord(A[6], A[7], A[8], A[11], px[u], py[u], pz[u]);
+        uint32_t ix, iy, iz;
+        const bool ok = voxel_ijk(m, gx, gy, gz, ix, iy, iz);
+        const uint32_t b = __umul24(ix >> 2, sp.nbz) + __umul24(iy >> 2, sp.nbzx) + (iz >> 2);
+        bidx[u] = ok ? b : 0u;  // any entry in range; outside lanes ignore it
+        sel[u] = ok ? 0u : 1u;
+        if (TAIL) sel[u] = (u * kWave + lane < nvalid) ? sel[u] : 2u;
+        wv[u] = (ix & 3u) + ((iy & 3u) << 2) + ((iz & 3u) << 4);
+    }
+    // each group of 64 bricks is two half-entries {mask of 32 bricks, stored before them}
+    uint2 ent[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) ent[u] = sp.coarse[bidx[u] >> 5];
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t slot[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const uint32_t k = bidx[u] & 31u;
+        const uint32_t below = (uint32_t)__popc(ent[u].x & ((1u << k) - 1u));
+        const uint32_t s0 = (ent[u].x >> k) & 1u ? 2u + ent[u].y + below : 0u;
+        slot[u] = sel[u] == 0u ? s0 : sel[u] - 1u;
+    }
+    int raw[kU];
+    if constexpr (!WIDE) {
+        // pool below 2^24 slots and 4 GiB: 24-bit multiplies and 32-bit offsets
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            raw[u] = load_raw<T>(sp.pool, __umul24(slot[u], 64u * sizeof(T)) + wv[u] * (uint32_t)sizeof(T));
+    } else {
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            raw[u] = load_raw64<T>(sp.pool + ((uint64_t)slot[u] * (64u * sizeof(T)) + wv[u] * (uint32_t)sizeof(T)));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float s = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const float f = as_value<T>(raw[u]);
+        s = __builtin_fmaf(f, f, s);
+    }
+    return s;
+}
+
+// Lookup kinds of the sensor kernel (sparse: pools below / above 2^24 slots or 4 GiB).
+constexpr int kLookNearest = 0, kLookTrilinear = 1, kLookSparse = 2, kLookSparseWide = 3;
+
+template <typename T, bool TAIL, int LK>
+__device__ __attribute__((always_inline)) inline void chunk_group(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
                                    int gcount, float &acc) {
     for (int p = 0; p < gcount; ++p) {
@@ -235,17 +303,19 @@ __device__ __attribute__((always_inline)) inline void chunk_group(const MapView 
 #pragma unroll
         for (int j = 0; j < 12; ++j) A[j] = bcast(pa[j], p);
         float t;
-        if constexpr (TRI)
-            t = wave_sum(lane_chunk_sum_tri<T, TAIL>(tv, A, px, py, pz, lane, nvalid));
+        if constexpr (LK == kLookTrilinear)
+            t = wave_sum(lane_chunk_sum_tri<T, TAIL>(J.tri, A, px, py, pz, lane, nvalid));
+        else if constexpr (LK == kLookSparse || LK == kLookSparseWide)
+            t = wave_sum(lane_chunk_sum_sparse<T, TAIL, LK == kLookSparseWide>(J.map, J.sp, A, px, py, pz, lane, nvalid));
         else
-            t = wave_sum(lane_chunk_sum<T, TAIL>(m, A, px, py, pz, lane, nvalid));
+            t = wave_sum(lane_chunk_sum<T, TAIL>(J.map, A, px, py, pz, lane, nvalid));
         if (lane == p) acc += t;
     }
 }
 
 // One work item: particles [64 g, 64 g + 64) of a job against points
 // [4096 piece, 4096 piece + 4096).  Returns lane p's sum for particle 64 g + p.
-template <typename T, bool TRI>
+template <typename T, int LK>
 __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJob &J, int local, int lane) {
     const int group = local / J.npiece;
     const int piece = local - group * J.npiece;
@@ -271,9 +341,9 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
             pz[u] = J.pts[(size_t)2 * K + k];
         }
         if (nvalid == kChunk)
-            chunk_group<T, false, TRI>(m, J.tri, pa, px, py, pz, lane, nvalid, gcount, acc);
+            chunk_group<T, false, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc);
         else
-            chunk_group<T, true, TRI>(m, J.tri, pa, px, py, pz, lane, nvalid, gcount, acc);
+            chunk_group<T, true, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc);
     }
     return acc;
 }
@@ -296,8 +366,8 @@ __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJ
 // wave for a full grid, several for a persistent one).  The job descriptor is
 // read into scalar registers per item and read again for the store, so it need
 // not stay live across the item.
-template <typename T, int WPB, typename Src, bool TRI = false>
-__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(TRI ? 2 : 4))) void sensor_kernel(Src src) {
+template <typename T, int WPB, typename Src, int LK = kLookNearest>
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == kLookTrilinear ? 2 : LK == kLookNearest ? 4 : 3))) void sensor_kernel(Src src) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nitems = src.items();
     const int64_t stride = (int64_t)gridDim.x * WPB;
@@ -309,7 +379,7 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(TRI ? 
         {
             const SensorJob J = src.load(j);
             local = (int)(item - J.item0);
-            acc = sensor_item<T, TRI>(J, local, lane);
+            acc = sensor_item<T, LK>(J, local, lane);
         }
         const SensorJob J = src.load(j);
         sensor_store(J, local, lane, acc);
@@ -411,6 +481,7 @@ SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const f
                           float *logw, float *part) {
     SensorJob J{};
     J.map = map->view;
+    J.sp = map->sp;
     J.pts = pts;
     J.poses = poses;
     J.logw = logw;
@@ -435,10 +506,27 @@ mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, cons
         part = static_cast<float *>(workspace(stream, (size_t)npiece * N * sizeof(float)));
         if (!part) return fail(MCL_ENOMEM, "sensor_update: workspace allocation failed");
     }
-    OneJob<SensorJob> src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
+    using Src = OneJob<SensorJob>;
+    Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
     const int64_t nitems = (int64_t)src.job.ngroups * npiece;
     src.n = Counts{1, nitems, N, 0};
-    return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream);
+    if (!map->sparse) return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream);
+    // sparse map: one wave per work item, four waves per workgroup
+    const unsigned blocks = (unsigned)((nitems + 3) / 4);
+    if (map->sp.small) {
+        if (map->dtype == MCL_TSDF_I16) sensor_kernel<int16_t, 4, Src, kLookSparse><<<blocks, 256, 0, stream>>>(src);
+        else if (map->dtype == MCL_TSDF_I8) sensor_kernel<int8_t, 4, Src, kLookSparse><<<blocks, 256, 0, stream>>>(src);
+        else sensor_kernel<float, 4, Src, kLookSparse><<<blocks, 256, 0, stream>>>(src);
+    } else {
+        if (map->dtype == MCL_TSDF_I16) sensor_kernel<int16_t, 4, Src, kLookSparseWide><<<blocks, 256, 0, stream>>>(src);
+        else if (map->dtype == MCL_TSDF_I8) sensor_kernel<int8_t, 4, Src, kLookSparseWide><<<blocks, 256, 0, stream>>>(src);
+        else sensor_kernel<float, 4, Src, kLookSparseWide><<<blocks, 256, 0, stream>>>(src);
+    }
+    mcl_status st = check_launch("sensor_kernel (sparse map)");
+    if (st != MCL_OK || npiece == 1) return st;
+    int64_t cb = std::min<int64_t>((N + 255) / 256, (int64_t)device_cus() * 16);
+    combine_kernel<<<(unsigned)std::max<int64_t>(cb, 1), 256, 0, stream>>>(src);
+    return check_launch("combine_kernel");
 }
 
 // Trilinear lookup: the same decomposition and summation order, one wave per
@@ -463,9 +551,9 @@ mcl_status launch_sensor_trilinear(mcl_map_s *map, const float *pts, int K, cons
     const int64_t nitems = (int64_t)src.job.ngroups * npiece;
     src.n = Counts{1, nitems, N, 0};
     const unsigned blocks = (unsigned)((nitems + 3) / 4);
-    if (map->dtype == MCL_TSDF_I16) sensor_kernel<int16_t, 4, Src, true><<<blocks, 256, 0, stream>>>(src);
-    else if (map->dtype == MCL_TSDF_I8) sensor_kernel<int8_t, 4, Src, true><<<blocks, 256, 0, stream>>>(src);
-    else sensor_kernel<float, 4, Src, true><<<blocks, 256, 0, stream>>>(src);
+    if (map->dtype == MCL_TSDF_I16) sensor_kernel<int16_t, 4, Src, kLookTrilinear><<<blocks, 256, 0, stream>>>(src);
+    else if (map->dtype == MCL_TSDF_I8) sensor_kernel<int8_t, 4, Src, kLookTrilinear><<<blocks, 256, 0, stream>>>(src);
+    else sensor_kernel<float, 4, Src, kLookTrilinear><<<blocks, 256, 0, stream>>>(src);
     mcl_status st = check_launch("sensor_kernel (trilinear)");
     if (st != MCL_OK || npiece == 1) return st;
     int64_t cb = std::min<int64_t>((N + 255) / 256, (int64_t)device_cus() * 16);

@@ -129,6 +129,9 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         mcl_status st = check_job(jobs[j], j);
         if (st != MCL_OK) return st;
     }
+    for (int j = 0; j < n_jobs; ++j)
+        if (jobs[j].map->sparse)
+            return fail(MCL_EINVAL, "tick: job " + std::to_string(j) + ": sparse maps are not supported in a batched tick");
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const bool use_graph = (flags & MCL_TICK_GRAPH) != 0;
     if (use_graph && stream == nullptr) return fail(MCL_EINVAL, "tick: graph replay needs a non-default stream");

@@ -53,6 +53,7 @@ class LaunchConfig(C.Structure):
 
 _lib.mcl_map_upload.argtypes = [C.POINTER(MapDesc), _P, _P, C.POINTER(_P)]
 _lib.mcl_map_free.argtypes = [_P]
+_lib.mcl_map_upload_bricks.argtypes = [C.POINTER(MapDesc), C.c_int64, _P, _P, _P, C.POINTER(_P)]
 _lib.mcl_sensor_update.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_sensor_update_trilinear.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
@@ -68,7 +69,7 @@ _lib.mcl_job_bytes.restype = C.c_size_t
 _lib.mcl_autotune.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P, C.POINTER(LaunchConfig)]
 _lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_last_error.restype = C.c_char_p
-for _f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear", "mcl_normalize",
+for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear", "mcl_normalize",
            "mcl_resample",
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_pose_estimate", "mcl_motion_update",
            "mcl_init_uniform", "mcl_debug_philox"):
@@ -134,6 +135,29 @@ class Map:
     @classmethod
     def from_tsdf(cls, tmap, stream=None) -> "Map":
         return cls(tmap.values, tmap.voxel, tmap.origin, tmap.tau, tmap.dtype, stream)
+
+    @classmethod
+    def from_bricks(cls, dims, voxel: float, origin, tau: float, dtype: str, coords: np.ndarray,
+                    values: np.ndarray, stream=None) -> "Map":
+        """Sparse coarse/fine map: coords [M, 3] int32 (bx, by, bz), values [M, 64] of the
+        storage type (in-brick index x + 4 y + 16 z); unlisted bricks read +Q."""
+        nx, ny, nz = dims
+        d = MapDesc(nx, ny, nz, float(voxel), (C.c_float * 3)(*[float(o) for o in origin]), float(tau),
+                    DTYPE_CODE[dtype])
+        co = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)
+        want = {"i16": np.int16, "i8": np.int8, "f32": np.float32}[dtype]
+        va = np.ascontiguousarray(values, want).reshape(-1, 64)
+        if co.shape[0] != va.shape[0]:
+            raise ValueError("coords and values must list the same bricks")
+        h = _P()
+        _check(_lib.mcl_map_upload_bricks(C.byref(d), co.shape[0], co.ctypes.data_as(_P), va.ctypes.data_as(_P),
+                                          _stream(stream), C.byref(h)), "mcl_map_upload_bricks")
+        self = cls.__new__(cls)
+        self._h = h
+        self.dims = (nx, ny, nz)
+        self.dtype = dtype
+        self.voxel, self.tau = float(voxel), float(tau)
+        return self
 
     @property
     def handle(self):

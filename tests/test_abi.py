@@ -28,7 +28,7 @@ def test_header_declares_the_boundary():
     for f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
               "mcl_debug_voxel_indices", "mcl_last_error", "mcl_tick", "mcl_job_bytes", "mcl_autotune",
               "mcl_set_launch_config", "mcl_pose_estimate", "mcl_sensor_update_trilinear", "mcl_motion_update",
-              "mcl_init_uniform"):
+              "mcl_init_uniform", "mcl_map_upload_bricks"):
         assert f in names
 
 
@@ -69,6 +69,16 @@ def test_argument_errors_are_reported_on_the_host(mcl):
     assert lib.mcl_init_uniform(None, fake, 10, 0.1, 1, None) == mcl.MCL_EINVAL
     assert lib.mcl_init_uniform(fake, fake, 10, -1.0, 1, None) == mcl.MCL_EINVAL
     assert lib.mcl_init_uniform(fake, fake, mcl.MAX_PARTICLES + 1, 0.1, 1, None) == mcl.MCL_ERANGE
+    # sparse maps: bricks outside the grid or listed twice, before any allocation
+    d = mcl.MapDesc(8, 8, 8, 0.1, (C.c_float * 3)(0, 0, 0), 0.3, 0)
+    h = P()
+    vals = (C.c_int16 * 128)()
+    assert lib.mcl_map_upload_bricks(C.byref(d), 1, (C.c_int32 * 3)(2, 0, 0), vals, None, C.byref(h)) == mcl.MCL_EINVAL
+    assert b"outside the grid" in lib.mcl_last_error()
+    assert lib.mcl_map_upload_bricks(C.byref(d), 2, (C.c_int32 * 6)(1, 1, 1, 1, 1, 1), vals, None,
+                                     C.byref(h)) == mcl.MCL_EINVAL
+    assert b"listed twice" in lib.mcl_last_error()
+    assert lib.mcl_map_upload_bricks(C.byref(d), -1, None, None, None, C.byref(h)) == mcl.MCL_EINVAL
     # overlapping output and input
     assert lib.mcl_normalize(P(0x10000), 100, None, P(0x10010), None, None) == mcl.MCL_EINVAL
     d = mcl.MapDesc(0, 4, 4, 0.1, (C.c_float * 3)(0, 0, 0), 0.3, 0)

@@ -1,0 +1,141 @@
+"""Parity of the sparse coarse/fine map (mcl_map_upload_bricks + mcl_sensor_update,
+through the C ABI) with the CPU oracle, and bit-identity with the dense layout
+holding the same values (same index recipe, values and summation order)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from tests.helpers import make_map, poses_from, random_rotations
+from workloads import configs
+from workloads.tsdf import f32, to_bricks
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "a GPU is required"
+    return t
+
+
+@pytest.fixture(scope="module")
+def mcl():
+    from paper_2310_04172_amd import mcl as m
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def sparse_of(mcl, tmap, coords, values):
+    return mcl.Map.from_bricks(tmap.dims, tmap.voxel, tmap.origin, tmap.tau, tmap.dtype, coords, values)
+
+
+def case(seed, dims, dtype, N, K):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    Q = {"i16": 32767, "i8": 127, "f32": np.float32(0.3)}[dtype]
+    if dtype == "f32":
+        vals = rng.uniform(-0.3, 0.3, (nz, ny, nx)).astype(np.float32)
+    else:
+        vals = rng.integers(-Q, Q + 1, (nz, ny, nx)).astype(np.int16 if dtype == "i16" else np.int8)
+    m = rng.random(((nz + 3) // 4, (ny + 3) // 4, (nx + 3) // 4)) < 0.6
+    sgn = np.where(rng.random(m.shape) < 0.5, Q, -Q)
+    for bz, by, bx in zip(*np.nonzero(m)):
+        vals[4 * bz:4 * bz + 4, 4 * by:4 * by + 4, 4 * bx:4 * bx + 4] = sgn[bz, by, bx]
+    tmap = make_map(vals, 0.1, origin=(-0.3, 0.2, -0.1), tau=0.3, dtype=dtype)
+    ext = np.array(dims) * 0.1
+    poses = poses_from(random_rotations(rng, N), rng.uniform(0, 1, (N, 3)) * ext)
+    pts = rng.normal(0, 0.4 * ext.mean(), (3, K)).astype(np.float32)
+    return tmap, pts, poses
+
+
+@pytest.mark.parametrize("N,K", [(1, 1), (63, 1000), (65, 4097), (7, 9000)])
+@pytest.mark.parametrize("dtype", ["i16", "i8", "f32"])
+def test_sparse_matches_oracle_and_dense(torch, mcl, oracle_lib, N, K, dtype):
+    say(f"case: sparse N={N} K={K} {dtype}")
+    tmap, pts, poses = case(N + K, (23, 18, 13), dtype, N, K)
+    co, va = to_bricks(tmap)
+    sm = sparse_of(mcl, tmap, co, va)
+    dm = mcl.Map.from_tsdf(tmap)
+    X, P = dev(torch, pts), dev(torch, poses)
+    ls = mcl.sensor_update(sm, X, P, f32(0.15)).cpu().numpy()
+    ld = mcl.sensor_update(dm, X, P, f32(0.15)).cpu().numpy()
+    assert np.array_equal(ls.view(np.uint32), ld.view(np.uint32))
+    ref = oracle_lib.sensor_update_bricks(tmap.dims, tmap.voxel, tmap.origin, tmap.tau, dtype, co, va, pts, poses,
+                                          f32(0.15))
+    assert np.all(np.abs(ls - ref) <= RTOL * np.abs(ref))
+
+
+def test_empty_listing_reads_q(torch, mcl, oracle_lib):
+    say("case: sparse map without bricks")
+    tmap, pts, poses = case(5, (12, 12, 12), "i16", 40, 2000)
+    sm = sparse_of(mcl, tmap, np.zeros((0, 3), np.int32), np.zeros((0, 64), np.int16))
+    ls = mcl.sensor_update(sm, dev(torch, pts), dev(torch, poses), f32(0.2)).cpu().numpy()
+    ref = oracle_lib.sensor_update_bricks(tmap.dims, tmap.voxel, tmap.origin, tmap.tau, "i16",
+                                          np.zeros((0, 3), np.int32), np.zeros((0, 64), np.int16), pts, poses, f32(0.2))
+    assert np.all(np.abs(ls - ref) <= RTOL * np.abs(ref))
+
+
+def test_map_beyond_the_dense_limit(torch, mcl, oracle_lib):
+    """A 4096 x 4096 x 192 int16 grid (6.4 GB dense, past the 4 GiB dense layout
+    limit) with band bricks only in a region: parity on particles around it."""
+    say("case: sparse map beyond 4 GiB dense")
+    rng = np.random.default_rng(9)
+    dims = (4096, 4096, 192)
+    bx, by, bz = np.meshgrid(np.arange(600, 640), np.arange(900, 930), np.arange(8, 20), indexing="ij")
+    co = np.stack([bx.ravel(), by.ravel(), bz.ravel()], 1).astype(np.int32)
+    va = rng.integers(-32767, 32768, (co.shape[0], 64)).astype(np.int16)
+    v = 0.05
+    lo = np.array([600 * 4, 900 * 4, 8 * 4]) * v
+    hi = np.array([640 * 4, 930 * 4, 20 * 4]) * v
+    N, K = 200, 6000
+    poses = poses_from(random_rotations(rng, N), rng.uniform(lo, hi, (N, 3)))
+    pts = rng.normal(0, 1.5, (3, K)).astype(np.float32)
+    sm = mcl.Map.from_bricks(dims, f32(v), (0.0, 0.0, 0.0), f32(0.15), "i16", co, va)
+    ls = mcl.sensor_update(sm, dev(torch, pts), dev(torch, poses), f32(0.075)).cpu().numpy()
+    ref = oracle_lib.sensor_update_bricks(dims, f32(v), (0.0, 0.0, 0.0), f32(0.15), "i16", co, va, pts, poses,
+                                          f32(0.075), nthreads=8)
+    assert np.all(np.abs(ls - ref) <= RTOL * np.abs(ref))
+    assert np.unique(np.round(ref, 3)).size > N // 2     # the region is actually read
+
+
+def test_global_workload_sparse_equals_dense(torch, mcl):
+    w = configs.config2()
+    say("case: sparse warehouse map, N = 10^6")
+    co, va = to_bricks(w.tmap)
+    sm = sparse_of(mcl, w.tmap, co, va)
+    dm = mcl.Map.from_tsdf(w.tmap)
+    X, P = dev(torch, w.points), dev(torch, w.poses)
+    ls = mcl.sensor_update(sm, X, P, w.sigma).cpu().numpy()
+    ld = mcl.sensor_update(dm, X, P, w.sigma).cpu().numpy()
+    assert np.array_equal(ls.view(np.uint32), ld.view(np.uint32))
+    nb = ((w.tmap.nx + 3) // 4) * ((w.tmap.ny + 3) // 4) * ((w.tmap.nz + 3) // 4)
+    say(f"stored bricks {co.shape[0]} of {nb} ({co.shape[0] / nb:.1%})")
+
+
+def test_sparse_guards(torch, mcl):
+    tmap, pts, poses = case(6, (8, 8, 8), "i16", 4, 10)
+    co, va = to_bricks(tmap)
+    sm = sparse_of(mcl, tmap, co, va)
+    P = dev(torch, poses)
+    with pytest.raises(mcl.MclError):
+        mcl.sensor_update_trilinear(sm, dev(torch, pts), P, f32(0.1))
+    with pytest.raises(mcl.MclError):
+        mcl.init_uniform(sm, 10, 0.0, 1)
+    f = mcl.Filter(sm, dev(torch, pts), P, f32(0.1), 1)
+    with pytest.raises(mcl.MclError):
+        mcl.tick([f])
+    with pytest.raises(mcl.MclError):   # a brick listed twice
+        sparse_of(mcl, tmap, np.r_[co[:1], co[:1]], np.r_[va[:1], va[:1]])
+    with pytest.raises(mcl.MclError):   # outside the brick grid
+        sparse_of(mcl, tmap, np.array([[2, 0, 0]], np.int32), va[:1])

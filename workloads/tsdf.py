@@ -151,3 +151,28 @@ def build_map(scene: Scene, dims, voxel, origin, tau, dtype="i16", keep_d64=Fals
     o = tuple(f32(x) for x in origin)
     vals, d64 = voxelise(scene, dims, v, o, t, dtype, keep_d64)
     return TsdfMap(dims[0], dims[1], dims[2], v, o, t, dtype, vals, d64)
+
+
+def to_bricks(tmap: "TsdfMap", band_only: bool = True):
+    """A dense map as a sparse coarse/fine map: (coords int32 [M, 3] (bx, by, bz),
+    values [M, 64] of the storage type, in-brick index x + 4 y + 16 z).  With
+    band_only, only bricks with a value strictly inside the truncation band are
+    listed (the others are all +-Q and read +Q when unlisted, the same q^2);
+    voxels beyond the map edge are filled with Q."""
+    Qv = {"i16": 32767, "i8": 127}.get(tmap.dtype, None)
+    q = np.asarray(Qv if Qv is not None else np.float32(tmap.tau), tmap.values.dtype)
+    nz, ny, nx = tmap.values.shape
+    pz, py, px = -(-nz // 4) * 4, -(-ny // 4) * 4, -(-nx // 4) * 4
+    padded = np.full((pz, py, px), q, tmap.values.dtype)
+    padded[:nz, :ny, :nx] = tmap.values
+    # [bz, z, by, y, bx, x] -> [by, bx, bz, z, y, x]
+    b = padded.reshape(pz // 4, 4, py // 4, 4, px // 4, 4).transpose(2, 4, 0, 1, 3, 5)
+    flat = b.reshape(py // 4, px // 4, pz // 4, 64)
+    if band_only:
+        keep = (np.abs(flat.astype(np.float64)) < float(q)).any(axis=3)
+    else:
+        keep = np.ones(flat.shape[:3], bool)
+    by, bx, bz = np.nonzero(keep)
+    coords = np.stack([bx, by, bz], 1).astype(np.int32)
+    return coords, np.ascontiguousarray(flat[keep])
+
