@@ -84,7 +84,7 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
 SENSOR_SOURCES = ("paper_2310_04172_amd/csrc/sensor.hip", "paper_2310_04172_amd/csrc/voxel.h",
                   "paper_2310_04172_amd/csrc/jobs.h", "paper_2310_04172_amd/csrc/mcl_internal.h",
                   "paper_2310_04172_amd/csrc/map.hip", "paper_2310_04172_amd/csrc/tune.hip",
-                  "paper_2310_04172_amd/build.py", "include/mcl.h")
+                  "paper_2310_04172_amd/build.py")
 
 
 def kernel_source_hash() -> str:
