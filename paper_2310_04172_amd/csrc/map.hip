@@ -11,21 +11,27 @@
 
 namespace mcl {
 
-// Element e of the brick layout: brick e >> 6 = bz + nbz (bx + nbx by), value
-// e & 63 = 16 (iz & 3) + 4 (iy & 3) + (ix & 3).  Padding voxels get 0 (never read).
+// Element e of the brick layout: brick bi = e / V = bz + nbz (bx + nbx by),
+// value w = e % V = (ix % BX) + BX (iy % BY) + BX BY (iz % BZ), V = BX BY BZ.
+// Padding voxels get 0 (never read).
+__device__ inline void brick_voxel(int64_t bi, int w, int nbx, int nbz, int &ix, int &iy, int &iz) {
+    const int bz = (int)(bi % nbz);
+    const int64_t r = bi / nbz;
+    const int bx = (int)(r % nbx);
+    const int by = (int)(r / nbx);
+    ix = bx * kBX + (w & (kBX - 1));
+    iy = by * kBY + ((w >> kBLX) & (kBY - 1));
+    iz = bz * kBZ + (w >> (kBLX + kBLY));
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void brick_kernel(const T *__restrict__ dense, T *__restrict__ bricked,
                                                     int nx, int ny, int nz, int nbx, int nbz,
                                                     int64_t nvals) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nvals) return;
-    int64_t bi = e >> 6;
-    int w = (int)(e & 63);
-    int bz = (int)(bi % nbz);
-    int64_t r = bi / nbz;
-    int bx = (int)(r % nbx);
-    int by = (int)(r / nbx);
-    int ix = bx * 4 + (w & 3), iy = by * 4 + ((w >> 2) & 3), iz = bz * 4 + (w >> 4);
+    int ix, iy, iz;
+    brick_voxel(e >> kBrickLog2, (int)(e & (kBrickVals - 1)), nbx, nbz, ix, iy, iz);
     T v = T(0);
     if (ix < nx && iy < ny && iz < nz) v = dense[(int64_t)ix + (int64_t)nx * ((int64_t)iy + (int64_t)ny * iz)];
     bricked[e] = v;
@@ -39,14 +45,11 @@ __global__ __launch_bounds__(256) void brick_class_kernel(const T *__restrict__ 
                                                           T qpos, T qneg) {
     int64_t bi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (bi >= nbricks) return;
-    int bz = (int)(bi % nbz);
-    int64_t r = bi / nbz;
-    int bx = (int)(r % nbx);
-    int by = (int)(r / nbx);
-    const T *b = bricked + bi * 64;
+    const T *b = bricked + bi * kBrickVals;
     bool trunc = true;
-    for (int w = 0; w < 64; ++w) {
-        int ix = bx * 4 + (w & 3), iy = by * 4 + ((w >> 2) & 3), iz = bz * 4 + (w >> 4);
+    for (int w = 0; w < kBrickVals; ++w) {
+        int ix, iy, iz;
+        brick_voxel(bi, w, nbx, nbz, ix, iy, iz);
         if (ix < nx && iy < ny && iz < nz) trunc &= (b[w] == qpos) | (b[w] == qneg);
     }
     cls[bi] = trunc ? kClassTrunc : kClassMixed;
@@ -54,9 +57,9 @@ __global__ __launch_bounds__(256) void brick_class_kernel(const T *__restrict__ 
 
 template <typename T>
 static void fill_sentinels(char *host, T outside, int es) {
-    for (int w = 0; w < 64; ++w) {
-        reinterpret_cast<T *>(host)[w] = outside;          // +Q sentinel brick at out_off
-        reinterpret_cast<T *>(host + 64 * es)[w] = T(0);  // zero sentinel brick at zero_off
+    for (int w = 0; w < kBrickVals; ++w) {
+        reinterpret_cast<T *>(host)[w] = outside;                  // +Q sentinel brick at out_off
+        reinterpret_cast<T *>(host + kBrickVals * es)[w] = T(0);  // zero sentinel brick at zero_off
     }
 }
 
@@ -110,9 +113,9 @@ mcl_status ensure_trilinear(mcl_map_s *m, hipStream_t stream) {
     const int es = 8 * elem_size(m->dtype);  // bytes per cell
     const int px = v.nx + 2, py = v.ny + 2, pz = v.nz + 2;
     const int nbx = (px + 3) / 4, nby = (py + 3) / 4, nbz = (pz + 3) / 4;
-    const int64_t nvals = (int64_t)nbx * nby * nbz * kBrickVals;  // cells
+    const int64_t nvals = (int64_t)nbx * nby * nbz * kCellBrickVals;  // cells
     const int64_t data_bytes = nvals * es;
-    const int64_t nbricks = nvals / kBrickVals;
+    const int64_t nbricks = nvals / kCellBrickVals;
     const int64_t cls_off = (data_bytes + 2 * es + 255) / 256 * 256;  // two sentinel cells, then the classes
     const int64_t bytes = cls_off + (nbricks + 255) / 256 * 256;
     const int64_t cy = (int64_t)es * (16 * (int64_t)nbz * nbx - 4);
@@ -201,7 +204,7 @@ static void fill_common(mcl_map_s *m, const mcl_map_desc &d) {
     m->scale = d.dtype == MCL_TSDF_F32 ? 1.0 : (double)d.tau / (double)m->Q;
     MapView &v = m->view;
     v.nx = d.nx; v.ny = d.ny; v.nz = d.nz;
-    v.nbx = (d.nx + 3) / 4; v.nby = (d.ny + 3) / 4; v.nbz = (d.nz + 3) / 4;
+    v.nbx = (d.nx + kBX - 1) / kBX; v.nby = (d.ny + kBY - 1) / kBY; v.nbz = (d.nz + kBZ - 1) / kBZ;
     float fx = (float)d.nx, fy = (float)d.ny, fz = (float)d.nz;
     std::memcpy(&v.bx, &fx, 4);
     std::memcpy(&v.by, &fy, 4);
@@ -306,16 +309,17 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
         if (cst != MCL_OK) return cst;
     }
     const int es = elem_size(d.dtype);
-    const int nbx = (d.nx + 3) / 4, nby = (d.ny + 3) / 4, nbz = (d.nz + 3) / 4;
-    const int64_t nvals = (int64_t)nbx * nby * nbz * kBrickVals;
+    const int64_t nbx = (d.nx + kBX - 1) / kBX, nby = (d.ny + kBY - 1) / kBY, nbz = (d.nz + kBZ - 1) / kBZ;
+    const int64_t nvals = nbx * nby * nbz * kBrickVals;
     const int64_t data_bytes = nvals * es;
     const int64_t nbricks = nvals / kBrickVals;
-    const int64_t sent_bytes = 128 * es;                           // two sentinel bricks
+    const int64_t sent_bytes = 2 * kBrickVals * es;                // two sentinel bricks
     const int64_t cls_off = (data_bytes + sent_bytes + 255) / 256 * 256;
     const int64_t total = cls_off + (nbricks + 2 + 255) / 256 * 256;
     if (total >= ((int64_t)1 << 32)) return fail(MCL_ERANGE, "map_upload: map exceeds the 4 GiB device layout limit");
-    const int64_t cy = (int64_t)es * (16 * (int64_t)nbz * nbx - 4);
-    if (cy >= ((int64_t)1 << 24) || d.nx >= (1 << 24) || d.ny >= (1 << 24))
+    const int64_t cx = (int64_t)es * (kBrickVals / kBX * nbz - 1);
+    const int64_t cy = (int64_t)es * (kBrickVals / kBY * nbz * nbx - kBX);
+    if (cy >= ((int64_t)1 << 24) || cx >= ((int64_t)1 << 24))
         return fail(MCL_ERANGE, "map_upload: nz * nx too large for the brick addressing (need 16*nbz*nbx*esize < 2^24)");
     const int64_t dense_vals = (int64_t)d.nx * d.ny * d.nz;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
@@ -333,7 +337,7 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
         return fail(MCL_ENOMEM, "map_upload: staging allocation failed");
     }
     mcl_status st = MCL_OK;
-    char sent[512] = {0};
+    char sent[2 * kBrickVals * 4] = {0};
     if (d.dtype == MCL_TSDF_I16) fill_sentinels<int16_t>(sent, (int16_t)32767, es);
     else if (d.dtype == MCL_TSDF_I8) fill_sentinels<int8_t>(sent, (int8_t)127, es);
     else fill_sentinels<float>(sent, d.tau, es);
@@ -347,20 +351,20 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     } else {
         unsigned blocks = (unsigned)((nvals + 255) / 256);
         if (d.dtype == MCL_TSDF_I16)
-            brick_kernel<int16_t><<<blocks, 256, 0, stream>>>((const int16_t *)dense_dev, (int16_t *)m->dev, d.nx, d.ny, d.nz, nbx, nbz, nvals);
+            brick_kernel<int16_t><<<blocks, 256, 0, stream>>>((const int16_t *)dense_dev, (int16_t *)m->dev, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
         else if (d.dtype == MCL_TSDF_I8)
-            brick_kernel<int8_t><<<blocks, 256, 0, stream>>>((const int8_t *)dense_dev, (int8_t *)m->dev, d.nx, d.ny, d.nz, nbx, nbz, nvals);
+            brick_kernel<int8_t><<<blocks, 256, 0, stream>>>((const int8_t *)dense_dev, (int8_t *)m->dev, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
         else
-            brick_kernel<float><<<blocks, 256, 0, stream>>>((const float *)dense_dev, (float *)m->dev, d.nx, d.ny, d.nz, nbx, nbz, nvals);
+            brick_kernel<float><<<blocks, 256, 0, stream>>>((const float *)dense_dev, (float *)m->dev, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
         st = check_launch("brick_kernel");
         unsigned cblocks = (unsigned)((nbricks + 255) / 256);
         if (st == MCL_OK) {
             if (d.dtype == MCL_TSDF_I16)
-                brick_class_kernel<int16_t><<<cblocks, 256, 0, stream>>>((const int16_t *)m->dev, cls, d.nx, d.ny, d.nz, nbx, nbz, nbricks, (int16_t)32767, (int16_t)-32767);
+                brick_class_kernel<int16_t><<<cblocks, 256, 0, stream>>>((const int16_t *)m->dev, cls, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, (int16_t)32767, (int16_t)-32767);
             else if (d.dtype == MCL_TSDF_I8)
-                brick_class_kernel<int8_t><<<cblocks, 256, 0, stream>>>((const int8_t *)m->dev, cls, d.nx, d.ny, d.nz, nbx, nbz, nbricks, (int8_t)127, (int8_t)-127);
+                brick_class_kernel<int8_t><<<cblocks, 256, 0, stream>>>((const int8_t *)m->dev, cls, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, (int8_t)127, (int8_t)-127);
             else
-                brick_class_kernel<float><<<cblocks, 256, 0, stream>>>((const float *)m->dev, cls, d.nx, d.ny, d.nz, nbx, nbz, nbricks, d.tau, -d.tau);
+                brick_class_kernel<float><<<cblocks, 256, 0, stream>>>((const float *)m->dev, cls, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, d.tau, -d.tau);
             st = check_launch("brick_class_kernel");
         }
         if (st == MCL_OK && hipStreamSynchronize(stream) != hipSuccess) st = fail(MCL_EDEVICE, "map_upload: synchronisation failed");
@@ -375,10 +379,10 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     m->bytes = (size_t)total;
     MapView &v = m->view;
     v.base = static_cast<const char *>(m->dev);
-    v.cx = (uint32_t)(es * (16 * nbz - 1));
+    v.cx = (uint32_t)cx;
     v.cy = (uint32_t)cy;
     v.out_off = (uint32_t)data_bytes;
-    v.zero_off = (uint32_t)(data_bytes + 64 * es);
+    v.zero_off = (uint32_t)(data_bytes + kBrickVals * es);
     v.cls = reinterpret_cast<const uint8_t *>(static_cast<const char *>(m->dev) + cls_off);
     *out = m;
     return MCL_OK;

@@ -10,7 +10,7 @@
 //    each particle of its group broadcasts that pose to scalar registers and
 //    evaluates the 16 points of every lane: 16 independent gathers in flight;
 //  * neighbouring lanes hold neighbouring beams, so one wave-wide gather touches
-//    few 128-byte brick lines;
+//    few 128-byte lines of the flat bricks of the map;
 //  * a chunk's 64 lane sums are reduced across the wave by a fixed butterfly;
 //  * the scan is also split into pieces of 4 chunks (4096 points) so small
 //    particle counts still fill the GPU; pieces are combined pairwise.
@@ -68,7 +68,7 @@ __device__ inline float as_value(int raw) {
 }
 
 template <typename T>
-constexpr int class_shift() { return 6 + (sizeof(T) == 1 ? 0 : sizeof(T) == 2 ? 1 : 2); }
+constexpr int class_shift() { return kBrickLog2 + (sizeof(T) == 1 ? 0 : sizeof(T) == 2 ? 1 : 2); }
 
 // Lane partial sum of one particle (pose in A) over this lane's kU points.
 // Coarse level first: the class byte of each point's brick; only points in
@@ -98,7 +98,7 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum(const MapV
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         // without padding lanes the zero class cannot occur: one sentinel
-        uint32_t sent = TAIL ? m.out_off + (cls[u] - 1u) * (64u * (uint32_t)sizeof(T)) : m.out_off;
+        uint32_t sent = TAIL ? m.out_off + (cls[u] - 1u) * ((uint32_t)kBrickVals * (uint32_t)sizeof(T)) : m.out_off;
         raw[u] = load_raw<T>(m.base, cls[u] == kClassMixed ? off[u] : sent);
     }
     __builtin_amdgcn_sched_barrier(0);

@@ -50,15 +50,19 @@ __device__ inline bool voxel_ijk(const MapView &m, float gx, float gy, float gz,
 }
 
 // Byte offset of a voxel's value in the brick layout (bricks z-fastest, then x,
-// then y; inside a brick z, y, x weigh 16, 4, 1).  The element index
-//   64 (bz + nbz (bx + nbx by)) + 16 (iz & 3) + 4 (iy & 3) + (ix & 3)
-// is separable per axis, with c = ~3:
-//   Z = 16 iz,  X = ix + (16 nbz - 1)(ix & c),  Y = 4 iy + (16 nbz nbx - 4)(iy & c).
-// cx, cy hold the two coefficients times ESIZE; the upload keeps them below 2^24.
+// then y; inside a brick x, y, z weigh 1, BX, BX BY).  With V = BX BY BZ the
+// element index
+//   V (bz + nbz (bx + nbx by)) + (ix & (BX-1)) + BX (iy & (BY-1)) + BX BY (iz & (BZ-1))
+// is separable per axis (z is the fastest brick axis, so its two parts merge):
+//   Z = BX BY iz,  X = ix + (V nbz / BX - 1)(ix & ~(BX-1)),
+//   Y = BX iy + (V nbz nbx / BY - BX)(iy & ~(BY-1)).
+// cx, cy hold the two coefficients times ESIZE; the upload keeps them below
+// 2^24.  Sums wrap modulo 2^32 and the true offset is below 2^32, so the
+// wrapped sum is exact.
 template <int ESIZE>
 __device__ inline uint32_t brick_offset(const MapView &m, uint32_t ix, uint32_t iy, uint32_t iz) {
-    uint32_t lin = (ix + (iy << 2) + (iz << 4)) * (uint32_t)ESIZE;  // ESIZE (ix + 4 iy + 16 iz)
-    return __umul24(ix & ~3u, m.cx) + (__umul24(iy & ~3u, m.cy) + lin);
+    uint32_t lin = (ix + (iy << kBLX) + (iz << (kBLX + kBLY))) * (uint32_t)ESIZE;
+    return __umul24(ix & ~(uint32_t)(kBX - 1), m.cx) + (__umul24(iy & ~(uint32_t)(kBY - 1), m.cy) + lin);
 }
 
 // Byte offset read for grid coordinates g: the voxel's, or the +Q sentinel outside.
@@ -84,8 +88,9 @@ __device__ inline uint32_t tri_axis(float g, float hmax, float &f) {
     return (uint32_t)((int32_t)fl + 1);
 }
 
-// Byte offset of element (i, j, k) of a bricked grid with ESIZE bytes per
-// element is X(i) + Y(j) + Z(k) (brick_offset, separated per axis).
+// Byte offset of cell (i, j, k) of the trilinear corner-cell grid (bricks of
+// 4 x 4 x 4 cells, z-fastest, then x, then y; ESIZE bytes per cell) is
+// X(i) + Y(j) + Z(k), with the coefficients of TriView.
 template <int ESIZE>
 __device__ inline uint32_t brick_x(uint32_t cx, uint32_t ix) { return __umul24(ix & ~3u, cx) + ix * ESIZE; }
 template <int ESIZE>

@@ -102,23 +102,25 @@ def test_ragged_sizes(torch, mcl, oracle_lib, N, K, dtype):
     assert_logw_close(lw, ref, f"N={N} K={K} {dtype}")
 
 
+@pytest.mark.parametrize("block", [(8, 32, 4), (8, 8, 2), (4, 4, 4)])
 @pytest.mark.parametrize("dtype", ["i16", "i8", "f32"])
-def test_truncated_bricks(torch, mcl, oracle_lib, dtype):
-    """Maps whose bricks are wholly +-Q (mixed signs too), partly Q, or cut by the
-    map edge (dims not multiples of 4): the coarse class test must never change
-    a result."""
-    say(f"case: truncated bricks {dtype}")
+def test_truncated_bricks(torch, mcl, oracle_lib, dtype, block):
+    """Maps whose blocks (x, y, z extents; 8 x 32 x 4 is the library's brick) are
+    wholly +-Q (mixed signs too), partly Q, or cut by the map edge (dims not
+    multiples of the block): the coarse class test must never change a result."""
+    say(f"case: truncated bricks {dtype} block={block}")
     rng = np.random.default_rng(17)
-    dims = (23, 18, 14)
+    dims = (23, 45, 14)
     tmap, pts, poses = random_case(5, dims, 150, 5000, dtype)
     Q = {"i16": 32767, "i8": 127, "f32": np.float32(0.3)}[dtype]
     vals = tmap.values
     nz, ny, nx = vals.shape
-    for bz in range(0, nz, 4):
-        for by in range(0, ny, 4):
-            for bx in range(0, nx, 4):
+    sx, sy, sz = block
+    for bz in range(0, nz, sz):
+        for by in range(0, ny, sy):
+            for bx in range(0, nx, sx):
                 r = rng.random()
-                blk = vals[bz:bz + 4, by:by + 4, bx:bx + 4]
+                blk = vals[bz:bz + sz, by:by + sy, bx:bx + sx]
                 if r < 0.3:
                     blk[...] = Q
                 elif r < 0.45:
@@ -130,7 +132,7 @@ def test_truncated_bricks(torch, mcl, oracle_lib, dtype):
                     blk.flat[rng.integers(0, blk.size)] = Q - (1 if dtype != "f32" else np.float32(1e-3))
     lw = gpu_logw(torch, mcl, tmap, pts, poses, f32(0.15))
     ref = oracle_lib.sensor_update(tmap, pts, poses, f32(0.15))
-    assert_logw_close(lw, ref, f"truncated bricks {dtype}")
+    assert_logw_close(lw, ref, f"truncated bricks {dtype} {block}")
 
 
 def test_empty_scan(torch, mcl):
