@@ -272,11 +272,16 @@ size_t mcl_job_bytes(int32_t N, int32_t K);
 
 /* --------------------------------------------------------------- tuning
  * Launch shape of the sensor kernel: waves per workgroup (2, 4, 8) and, for a
- * persistent grid, workgroups per compute unit (0 = one wave per work item).
- * The shape never changes results (the summation order depends only on K). */
+ * persistent grid, workgroups per compute unit (0 = one wave per work item);
+ * where the nearest lookup of a single-filter call reads the map's coarse
+ * level: 0 = chosen per wave and chunk (default), 1 = bytes in global memory,
+ * 2 = bits copied into LDS (only for maps whose bit table fits 64 KiB; larger
+ * maps and mcl_tick always use 1).  No setting changes results (the summation
+ * order depends only on K). */
 typedef struct {
     int32_t waves_per_block;
     int32_t blocks_per_cu;
+    int32_t coarse;
 } mcl_launch_config;
 
 /* Time every launch shape on the given filter (synchronises `stream`), keep

@@ -30,7 +30,15 @@ struct SensorJob {
     int64_t elem0;        // first particle of this job in the launch
     float c;              // s^2 / (2 sigma^2)
     int32_t K, N, npiece, ngroups;
+    int32_t coarse;       // where the nearest lookup reads the coarse level (kCoarse*)
 };
+
+// Coarse level of the nearest lookup: chosen per wave and chunk (auto), or
+// forced to the mask bytes in global memory or the bits in LDS.  Results are
+// the same bits in every mode.
+constexpr int32_t kCoarseAuto = 0, kCoarseBytes = 1, kCoarseBits = 2;
+constexpr int kProbe = 2;                             // probe evaluations per chunk
+constexpr int kProbeMixed = kProbe * kChunk * 3 / 4;  // LDS when over 3/4 of them read in place
 
 // Weight normalisation and resampling of one filter.
 constexpr int kWThreads = 256;
@@ -158,6 +166,7 @@ __device__ inline int find_job_uniform(const Src &src, int64_t x, Key key) {
 struct LaunchCfg {
     int waves_per_block;  // 2, 4 or 8
     int blocks_per_cu;    // 0: one wave per work item; else a persistent grid
+    int coarse;           // kCoarseAuto, kCoarseBytes or kCoarseBits
 };
 
 LaunchCfg tuned_config(int32_t dtype, int K, int N);

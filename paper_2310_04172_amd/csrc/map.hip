@@ -37,12 +37,13 @@ __global__ __launch_bounds__(256) void brick_kernel(const T *__restrict__ dense,
     bricked[e] = v;
 }
 
-// Class byte of every brick: kClassTrunc if all its voxels inside the map
-// hold +-Q (padding voxels beyond the map are ignored), else kClassMixed.
+// Read mask of every brick, stored at slot brick + 1 (slot 0 is the +Q
+// sentinel in front): 0 if all its voxels inside the map hold +-Q (padding
+// voxels beyond the map are ignored), else -1.
 template <typename T>
-__global__ __launch_bounds__(256) void brick_class_kernel(const T *__restrict__ bricked, uint8_t *__restrict__ cls,
-                                                          int nx, int ny, int nz, int nbx, int nbz, int64_t nbricks,
-                                                          T qpos, T qneg) {
+__global__ __launch_bounds__(256) void brick_mask_kernel(const T *__restrict__ bricked, int8_t *__restrict__ mask,
+                                                         int nx, int ny, int nz, int nbx, int nbz, int64_t nbricks,
+                                                         T qpos, T qneg) {
     int64_t bi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (bi >= nbricks) return;
     const T *b = bricked + bi * kBrickVals;
@@ -52,14 +53,27 @@ __global__ __launch_bounds__(256) void brick_class_kernel(const T *__restrict__ 
         brick_voxel(bi, w, nbx, nbz, ix, iy, iz);
         if (ix < nx && iy < ny && iz < nz) trunc &= (b[w] == qpos) | (b[w] == qneg);
     }
-    cls[bi] = trunc ? kClassTrunc : kClassMixed;
+    mask[bi + 1] = trunc ? int8_t(0) : int8_t(-1);
+}
+
+// The masks as bits: bit b of word w is set when slot 32 w + b is read in place.
+__global__ __launch_bounds__(256) void read_bits_kernel(const int8_t *__restrict__ mask, int64_t nslots,
+                                                        uint32_t *__restrict__ bits, int64_t nwords) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b) {
+        const int64_t i = w * 32 + b;
+        if (i < nslots && mask[i] != 0) v |= 1u << b;
+    }
+    bits[w] = v;
 }
 
 template <typename T>
-static void fill_sentinels(char *host, T outside, int es) {
+static void fill_sentinels(char *qpos, char *zero, T outside) {
     for (int w = 0; w < kBrickVals; ++w) {
-        reinterpret_cast<T *>(host)[w] = outside;                  // +Q sentinel brick at out_off
-        reinterpret_cast<T *>(host + kBrickVals * es)[w] = T(0);  // zero sentinel brick at zero_off
+        reinterpret_cast<T *>(qpos)[w] = outside;  // +Q sentinel brick at offset 0
+        reinterpret_cast<T *>(zero)[w] = T(0);     // zero sentinel brick after the data
     }
 }
 
@@ -311,11 +325,15 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     const int es = elem_size(d.dtype);
     const int64_t nbx = (d.nx + kBX - 1) / kBX, nby = (d.ny + kBY - 1) / kBY, nbz = (d.nz + kBZ - 1) / kBZ;
     const int64_t nvals = nbx * nby * nbz * kBrickVals;
-    const int64_t data_bytes = nvals * es;
     const int64_t nbricks = nvals / kBrickVals;
-    const int64_t sent_bytes = 2 * kBrickVals * es;                // two sentinel bricks
-    const int64_t cls_off = (data_bytes + sent_bytes + 255) / 256 * 256;
-    const int64_t total = cls_off + (nbricks + 2 + 255) / 256 * 256;
+    const int64_t brick_bytes = (int64_t)kBrickVals * es;
+    const int64_t data0 = brick_bytes;                              // +Q sentinel brick in front
+    const int64_t zero_off = data0 + nvals * es;                    // zero sentinel brick after the data
+    const int64_t nslots = nbricks + 2;
+    const int64_t mask_off = (zero_off + brick_bytes + 255) / 256 * 256;
+    const int64_t nrwords = (nslots + 31) / 32;
+    const int64_t bits_off = mask_off + (nslots + 255) / 256 * 256;
+    const int64_t total = bits_off + (nrwords * 4 + 255) / 256 * 256;
     if (total >= ((int64_t)1 << 32)) return fail(MCL_ERANGE, "map_upload: map exceeds the 4 GiB device layout limit");
     const int64_t cx = (int64_t)es * (kBrickVals / kBX * nbz - 1);
     const int64_t cy = (int64_t)es * (kBrickVals / kBY * nbz * nbx - kBX);
@@ -337,35 +355,43 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
         return fail(MCL_ENOMEM, "map_upload: staging allocation failed");
     }
     mcl_status st = MCL_OK;
-    char sent[2 * kBrickVals * 4] = {0};
-    if (d.dtype == MCL_TSDF_I16) fill_sentinels<int16_t>(sent, (int16_t)32767, es);
-    else if (d.dtype == MCL_TSDF_I8) fill_sentinels<int8_t>(sent, (int8_t)127, es);
-    else fill_sentinels<float>(sent, d.tau, es);
-    const uint8_t sent_cls[2] = {kClassTrunc, kClassZero};
+    char sent_q[kBrickVals * 4] = {0}, sent_z[kBrickVals * 4] = {0};
+    if (d.dtype == MCL_TSDF_I16) fill_sentinels<int16_t>(sent_q, sent_z, (int16_t)32767);
+    else if (d.dtype == MCL_TSDF_I8) fill_sentinels<int8_t>(sent_q, sent_z, (int8_t)127);
+    else fill_sentinels<float>(sent_q, sent_z, d.tau);
+    const int8_t sent_mask[2] = {0, -1};  // +Q sentinel: read slot 0 (itself); zero sentinel: read in place
     char *base = static_cast<char *>(m->dev);
-    uint8_t *cls = reinterpret_cast<uint8_t *>(base + cls_off);
+    int8_t *mask = reinterpret_cast<int8_t *>(base + mask_off);
     if (hipMemcpyAsync(dense_dev, host_values, (size_t)(dense_vals * es), hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(base + data_bytes, sent, (size_t)sent_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(cls + nbricks, sent_cls, 2, hipMemcpyHostToDevice, stream) != hipSuccess) {
+        hipMemcpyAsync(base, sent_q, (size_t)brick_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(base + zero_off, sent_z, (size_t)brick_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(mask, &sent_mask[0], 1, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(mask + nbricks + 1, &sent_mask[1], 1, hipMemcpyHostToDevice, stream) != hipSuccess) {
         st = fail(MCL_EDEVICE, "map_upload: copy to device failed");
     } else {
         unsigned blocks = (unsigned)((nvals + 255) / 256);
+        char *data = base + data0;
         if (d.dtype == MCL_TSDF_I16)
-            brick_kernel<int16_t><<<blocks, 256, 0, stream>>>((const int16_t *)dense_dev, (int16_t *)m->dev, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
+            brick_kernel<int16_t><<<blocks, 256, 0, stream>>>((const int16_t *)dense_dev, (int16_t *)data, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
         else if (d.dtype == MCL_TSDF_I8)
-            brick_kernel<int8_t><<<blocks, 256, 0, stream>>>((const int8_t *)dense_dev, (int8_t *)m->dev, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
+            brick_kernel<int8_t><<<blocks, 256, 0, stream>>>((const int8_t *)dense_dev, (int8_t *)data, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
         else
-            brick_kernel<float><<<blocks, 256, 0, stream>>>((const float *)dense_dev, (float *)m->dev, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
+            brick_kernel<float><<<blocks, 256, 0, stream>>>((const float *)dense_dev, (float *)data, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nvals);
         st = check_launch("brick_kernel");
         unsigned cblocks = (unsigned)((nbricks + 255) / 256);
         if (st == MCL_OK) {
             if (d.dtype == MCL_TSDF_I16)
-                brick_class_kernel<int16_t><<<cblocks, 256, 0, stream>>>((const int16_t *)m->dev, cls, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, (int16_t)32767, (int16_t)-32767);
+                brick_mask_kernel<int16_t><<<cblocks, 256, 0, stream>>>((const int16_t *)data, mask, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, (int16_t)32767, (int16_t)-32767);
             else if (d.dtype == MCL_TSDF_I8)
-                brick_class_kernel<int8_t><<<cblocks, 256, 0, stream>>>((const int8_t *)m->dev, cls, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, (int8_t)127, (int8_t)-127);
+                brick_mask_kernel<int8_t><<<cblocks, 256, 0, stream>>>((const int8_t *)data, mask, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, (int8_t)127, (int8_t)-127);
             else
-                brick_class_kernel<float><<<cblocks, 256, 0, stream>>>((const float *)m->dev, cls, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, d.tau, -d.tau);
-            st = check_launch("brick_class_kernel");
+                brick_mask_kernel<float><<<cblocks, 256, 0, stream>>>((const float *)data, mask, d.nx, d.ny, d.nz, (int)nbx, (int)nbz, nbricks, d.tau, -d.tau);
+            st = check_launch("brick_mask_kernel");
+        }
+        if (st == MCL_OK) {
+            read_bits_kernel<<<(unsigned)((nrwords + 255) / 256), 256, 0, stream>>>(
+                mask, nslots, reinterpret_cast<uint32_t *>(base + bits_off), nrwords);
+            st = check_launch("read_bits_kernel");
         }
         if (st == MCL_OK && hipStreamSynchronize(stream) != hipSuccess) st = fail(MCL_EDEVICE, "map_upload: synchronisation failed");
     }
@@ -381,9 +407,11 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     v.base = static_cast<const char *>(m->dev);
     v.cx = (uint32_t)cx;
     v.cy = (uint32_t)cy;
-    v.out_off = (uint32_t)data_bytes;
-    v.zero_off = (uint32_t)(data_bytes + kBrickVals * es);
-    v.cls = reinterpret_cast<const uint8_t *>(static_cast<const char *>(m->dev) + cls_off);
+    v.data0 = (uint32_t)data0;
+    v.zero_off = (uint32_t)zero_off;
+    v.mask = reinterpret_cast<const int8_t *>(base + mask_off);
+    v.rbits = reinterpret_cast<const uint32_t *>(base + bits_off);
+    v.nrwords = (uint32_t)nrwords;
     *out = m;
     return MCL_OK;
 }

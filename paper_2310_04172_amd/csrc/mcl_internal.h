@@ -17,9 +17,11 @@ constexpr int kWave = 64;
 // brick (1024 values) is one contiguous run, x fastest, then y, then z, so an
 // int16 line of 128 bytes holds an 8 x 8 patch of one z-layer.  Bricks are
 // ordered z fastest, then x, then y (maps are flat: nz is the short axis),
-// which keeps every address coefficient below 2^24 for 24-bit multiplies.  Two
-// sentinel bricks follow: +Q (read by points outside the map) and 0 (read by
-// padding lanes past the end of a scan, contributing nothing).
+// which keeps every address coefficient below 2^24 for 24-bit multiplies.  The
+// allocation starts with a sentinel brick of +Q (read by points outside the map
+// and instead of every brick wholly at +-Q), then the bricks, then a sentinel
+// brick of zeros (read by padding lanes past the end of a scan, contributing
+// nothing).
 //
 // Why this shape: the texture units spend their cycles per cache line a
 // wave-wide gather touches.  The 64 lanes of a gather hold consecutive beams of
@@ -30,16 +32,17 @@ constexpr int kWave = 64;
 // a VLP-16-shaped scan, 10^6 particles: 12 % less time under global
 // localisation, 32 % less with the particles converged round one pose.
 //
-// Beside the values sits one class byte per brick (the coarse level of the
-// map): 1 if every voxel of the brick holds +-Q (the truncation value: free
-// space or solid beyond the band), 0 if the brick has any value inside the
-// band, 2 for the zero sentinel.  Only q^2 enters the score, so a class-1 brick
-// scores Q^2 for any point without reading its values.
+// Beside the values sits the coarse level of the map: per brick (and per
+// sentinel, in address order) a read mask, -1 if the brick has any value
+// inside the truncation band (read in place) and 0 if every voxel holds +-Q.
+// Only q^2 enters the score, so such a brick scores Q^2 for any point: the
+// lookup reads address (offset AND mask), which is the +Q sentinel at offset 0.
+// The masks are kept twice: as signed bytes in global memory, and as bits
+// (1 = read in place) small enough for the sensor kernel to hold in LDS.
 constexpr int kBLX = 3, kBLY = 5, kBLZ = 2;                 // log2 of the brick shape
 constexpr int kBX = 1 << kBLX, kBY = 1 << kBLY, kBZ = 1 << kBLZ;
 constexpr int kBrickLog2 = kBLX + kBLY + kBLZ;
 constexpr int kBrickVals = 1 << kBrickLog2;                 // 1024
-constexpr uint8_t kClassMixed = 0, kClassTrunc = 1, kClassZero = 2;
 
 struct MapView {
     const char *base;        // device: bricked values, then the sentinels
@@ -49,10 +52,15 @@ struct MapView {
     float inv_v;             // (float)(1.0 / (double)voxel)
     float ox, oy, oz;        // origin
     uint32_t cx, cy;         // ESIZE (V nbz / BX - 1), ESIZE (V nbz nbx / BY - BX), V = BX BY BZ
-    uint32_t out_off;        // byte offset of the +Q sentinel brick
+    uint32_t data0;          // byte offset of the first brick (after the +Q sentinel brick at 0)
     uint32_t zero_off;       // byte offset of the 0 sentinel brick
-    const uint8_t *cls;      // device: class byte per brick, indexed by byte offset >> (kBrickLog2 + log2 esize)
+    const int8_t *mask;      // device: read mask per brick slot, indexed by byte offset >> (kBrickLog2 + log2 esize)
+    const uint32_t *rbits;   // device: the same masks as bits, bit b of word w for slot 32 w + b
+    uint32_t nrwords;        // words of rbits (bricks + 2 sentinels, rounded up to 32)
 };
+// Largest read-bit table the sensor kernel copies into LDS (bytes); maps with
+// more bricks use the class bytes in global memory.
+constexpr uint32_t kMaxLdsBits = 64 * 1024;
 
 // The map for the trilinear lookup, one gather per point: cell (i, j, k) holds
 // the 8 voxel values at its corners (i..i+1, j..j+1, k..k+1), x fastest, so an
@@ -108,7 +116,7 @@ struct mcl_map_s {
     mcl::TriView tri;
     void *free_prefix;  // free voxels before each 64-voxel row chunk (uniform initialisation), or null
     uint64_t free_total;
-    bool sparse;        // coarse table + brick pool (view.base and view.cls unused)
+    bool sparse;        // coarse table + brick pool (view.base and view.mask unused)
     mcl::SparseView sp;
     void *sp_coarse, *sp_pool;
 };

@@ -71,11 +71,16 @@ template <typename T>
 constexpr int class_shift() { return kBrickLog2 + (sizeof(T) == 1 ? 0 : sizeof(T) == 2 ? 1 : 2); }
 
 // Lane partial sum of one particle (pose in A) over this lane's kU points.
-// Coarse level first: the class byte of each point's brick; only points in
-// bricks with values inside the truncation band read their own fine value.
+// Coarse level first: the read mask of each point's brick (a signed byte in
+// global memory): a brick wholly at +-Q reads offset 0, the +Q sentinel, so
+// only points in bricks with values inside the truncation band read their own
+// value; a gather then touches one shared line for all the others, needs no
+// branches, and all kU gathers stay in flight.  Padding lanes point at the
+// zero sentinel brick, which is read in place.
 template <typename T, bool TAIL>
 __device__ __attribute__((always_inline)) inline float lane_chunk_sum(const MapView &m, const float (&A)[12], const float (&px)[kU],
-                                       const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid) {
+                                       const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
+                                       bool count = false, int *nmixed = nullptr) {
     uint32_t off[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -86,20 +91,59 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum(const MapV
         if (TAIL) o = (u * kWave + lane < nvalid) ? o : m.zero_off;
         off[u] = o;
     }
-    uint32_t cls[kU];
+    int msk[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) cls[u] = m.cls[off[u] >> class_shift<T>()];
+    for (int u = 0; u < kU; ++u) msk[u] = m.mask[off[u] >> class_shift<T>()];
     __builtin_amdgcn_sched_barrier(0);
-    // Lanes whose brick is not mixed read the sentinel brick of their class
-    // instead (class 1 -> the +Q brick at out_off, class 2 -> the zero brick
-    // right after it): one line every such lane shares, so the gathers need no
-    // branches and all kU of them stay in flight.
+    int raw[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) raw[u] = load_raw<T>(m.base, off[u] & (uint32_t)msk[u]);
+    __builtin_amdgcn_sched_barrier(0);
+    if (count) {
+        // lookups of the wave that read in place (wave-uniform)
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) c += __builtin_popcountll(__ballot(msk[u] != 0));
+        *nmixed += c;
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        float f = as_value<T>(raw[u]);
+        s = __builtin_fmaf(f, f, s);
+    }
+    return s;
+}
+
+// The same lookup with the coarse level read from LDS: the workgroup holds the
+// map's read masks as bits, so a point costs one global gather instead of two
+// (and three more instructions).  The bit of slot b sign-extended is the mask
+// (0 or -1).  All 16 LDS reads are issued before the first gather.
+template <typename T, bool TAIL>
+__device__ __attribute__((always_inline)) inline float lane_chunk_sum_lds(const MapView &m, const uint32_t *sbits,
+                                                                          const float (&A)[12], const float (&px)[kU],
+                                                                          const float (&py)[kU], const float (&pz)[kU],
+                                                                          int lane, int nvalid) {
+    uint32_t off[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        float gx = grid_coord(A[0], A[1], A[2], A[9], px[u], py[u], pz[u]);
+        float gy = grid_coord(A[3], A[4], A[5], A[10], px[u], py[u], pz[u]);
+        float gz = grid_coord(A[6], A[7], A[8], A[11], px[u], py[u], pz[u]);
+        uint32_t o = voxel_offset<sizeof(T)>(m, gx, gy, gz);
+        if (TAIL) o = (u * kWave + lane < nvalid) ? o : m.zero_off;
+        off[u] = o;
+    }
+    uint32_t word[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) word[u] = sbits[off[u] >> (class_shift<T>() + 5)];
+    __builtin_amdgcn_sched_barrier(0);
     int raw[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-        // without padding lanes the zero class cannot occur: one sentinel
-        uint32_t sent = TAIL ? m.out_off + (cls[u] - 1u) * ((uint32_t)kBrickVals * (uint32_t)sizeof(T)) : m.out_off;
-        raw[u] = load_raw<T>(m.base, cls[u] == kClassMixed ? off[u] : sent);
+        // bit (slot & 31), sign-extended: the mask
+        const int mk = __builtin_amdgcn_sbfe((int)word[u], (int)(off[u] >> class_shift<T>()), 1);
+        raw[u] = load_raw<T>(m.base, off[u] & (uint32_t)mk);
     }
     __builtin_amdgcn_sched_barrier(0);
     float s = 0.0f;
@@ -292,13 +336,17 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_sparse(con
 }
 
 // Lookup kinds of the sensor kernel (sparse: pools below / above 2^24 slots or 4 GiB).
-constexpr int kLookNearest = 0, kLookTrilinear = 1, kLookSparse = 2, kLookSparseWide = 3;
+constexpr int kLookNearest = 0, kLookTrilinear = 1, kLookSparse = 2, kLookSparseWide = 3, kLookNearestLds = 4;
 
+// Particles [p0, p1) of the wave's group against one chunk, with lookup LK
+// (kLookNearestLds here: the coarse level read from LDS).  probe: count the
+// in-place reads of the nearest lookup into *nmixed (wave-uniform).
 template <typename T, bool TAIL, int LK>
-__device__ __attribute__((always_inline)) inline void chunk_group(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
+__device__ __attribute__((always_inline)) inline void chunk_range(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
-                                   int gcount, float &acc) {
-    for (int p = 0; p < gcount; ++p) {
+                                   int p0, int p1, float &acc, const uint32_t *sbits, bool probe = false,
+                                   int *nmixed = nullptr) {
+    for (int p = p0; p < p1; ++p) {
         float A[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) A[j] = bcast(pa[j], p);
@@ -307,16 +355,49 @@ __device__ __attribute__((always_inline)) inline void chunk_group(const SensorJo
             t = wave_sum(lane_chunk_sum_tri<T, TAIL>(J.tri, A, px, py, pz, lane, nvalid));
         else if constexpr (LK == kLookSparse || LK == kLookSparseWide)
             t = wave_sum(lane_chunk_sum_sparse<T, TAIL, LK == kLookSparseWide>(J.map, J.sp, A, px, py, pz, lane, nvalid));
+        else if constexpr (LK == kLookNearestLds)
+            t = wave_sum(lane_chunk_sum_lds<T, TAIL>(J.map, sbits, A, px, py, pz, lane, nvalid));
         else
-            t = wave_sum(lane_chunk_sum<T, TAIL>(J.map, A, px, py, pz, lane, nvalid));
+            t = wave_sum(lane_chunk_sum<T, TAIL>(J.map, A, px, py, pz, lane, nvalid, probe, nmixed));
         if (lane == p) acc += t;
+    }
+}
+
+// All particles of the group against one chunk.  With the LDS coarse level
+// available, the coarse level is read from LDS or from global memory,
+// whichever suits this wave's particles (same bits either way): the first
+// kProbe particles run with the global masks and count the in-place reads;
+// the rest take LDS when over half of those were in place (tracking: most
+// points land in the band, and LDS saves a gather per point), else stay on
+// the global masks (global localisation: most points read the shared
+// sentinel line, and the global path issues fewer instructions).
+template <typename T, bool TAIL, int LK>
+__device__ __attribute__((always_inline)) inline void chunk_group(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
+                                   const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
+                                   int gcount, float &acc, const uint32_t *sbits) {
+    if constexpr (LK == kLookNearestLds) {
+        int p0 = 0;
+        bool lds = J.coarse == kCoarseBits;
+        if (J.coarse == kCoarseAuto) {
+            int nmixed = 0;
+            p0 = min(kProbe, gcount);
+            chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, 0, p0, acc, sbits, true, &nmixed);
+            lds = nmixed > kProbeMixed;
+        }
+        if (lds)
+            chunk_range<T, TAIL, kLookNearestLds>(J, pa, px, py, pz, lane, nvalid, p0, gcount, acc, sbits);
+        else
+            chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, p0, gcount, acc, sbits);
+    } else {
+        chunk_range<T, TAIL, LK>(J, pa, px, py, pz, lane, nvalid, 0, gcount, acc, sbits);
     }
 }
 
 // One work item: particles [64 g, 64 g + 64) of a job against points
 // [4096 piece, 4096 piece + 4096).  Returns lane p's sum for particle 64 g + p.
 template <typename T, int LK>
-__device__ __attribute__((always_inline)) inline float sensor_item(const SensorJob &J, int local, int lane) {
+__device__ __attribute__((always_inline)) inline float sensor_item(const SensorJob &J, int local, int lane,
+                                                                   const uint32_t *sbits) {
     const int group = local / J.npiece;
     const int piece = local - group * J.npiece;
     const int n0 = group * kGroup;
@@ -341,9 +422,9 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
             pz[u] = J.pts[(size_t)2 * K + k];
         }
         if (nvalid == kChunk)
-            chunk_group<T, false, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc);
+            chunk_group<T, false, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc, sbits);
         else
-            chunk_group<T, true, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc);
+            chunk_group<T, true, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc, sbits);
     }
     return acc;
 }
@@ -367,10 +448,17 @@ __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJ
 // read into scalar registers per item and read again for the store, so it need
 // not stay live across the item.
 template <typename T, int WPB, typename Src, int LK = kLookNearest>
-__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == kLookTrilinear ? 2 : LK == kLookNearest ? 4 : 3))) void sensor_kernel(Src src) {
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == kLookTrilinear ? 2 : (LK == kLookNearest || LK == kLookNearestLds) ? 4 : 3))) void sensor_kernel(Src src) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nitems = src.items();
     const int64_t stride = (int64_t)gridDim.x * WPB;
+    extern __shared__ uint32_t sbits[];
+    if constexpr (LK == kLookNearestLds) {
+        // one map per launch (single-filter calls): its read bits into LDS
+        const SensorJob J0 = src.load(0);
+        for (uint32_t w = threadIdx.x; w < J0.map.nrwords; w += WPB * 64) sbits[w] = J0.map.rbits[w];
+        __syncthreads();
+    }
     for (int64_t item = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems;
          item += stride) {
         const int j = find_job_uniform(src, item, [](const SensorJob &J) { return J.item0; });
@@ -379,7 +467,7 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == 
         {
             const SensorJob J = src.load(j);
             local = (int)(item - J.item0);
-            acc = sensor_item<T, LK>(J, local, lane);
+            acc = sensor_item<T, LK>(J, local, lane, sbits);
         }
         const SensorJob J = src.load(j);
         sensor_store(J, local, lane, acc);
@@ -446,16 +534,16 @@ int device_cus() {
 
 // nitems: the item count when known on the host (sizes a one-wave-per-item
 // grid); a persistent grid does not need it.
-template <typename T, typename Src>
-static void launch_sensor_t(const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream) {
+template <typename T, typename Src, int LK = kLookNearest>
+static void launch_sensor_t(const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream, size_t lds = 0) {
     const int wpb = cfg.waves_per_block;
     int64_t blocks = (nitems + wpb - 1) / wpb;
     if (cfg.blocks_per_cu > 0) blocks = std::min<int64_t>(blocks, (int64_t)device_cus() * cfg.blocks_per_cu);
     if (blocks < 1) blocks = 1;
     switch (wpb) {
-        case 2: sensor_kernel<T, 2><<<(unsigned)blocks, 128, 0, stream>>>(src); break;
-        case 8: sensor_kernel<T, 8><<<(unsigned)blocks, 512, 0, stream>>>(src); break;
-        default: sensor_kernel<T, 4><<<(unsigned)blocks, 256, 0, stream>>>(src); break;
+        case 2: sensor_kernel<T, 2, Src, LK><<<(unsigned)blocks, 128, lds, stream>>>(src); break;
+        case 8: sensor_kernel<T, 8, Src, LK><<<(unsigned)blocks, 512, lds, stream>>>(src); break;
+        default: sensor_kernel<T, 4, Src, LK><<<(unsigned)blocks, 256, lds, stream>>>(src); break;
     }
 }
 
@@ -510,6 +598,18 @@ mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, cons
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
     const int64_t nitems = (int64_t)src.job.ngroups * npiece;
     src.n = Counts{1, nitems, N, 0};
+    if (!map->sparse && (size_t)map->view.nrwords * 4 <= kMaxLdsBits && cfg.coarse != kCoarseBytes) {
+        const size_t lds = (size_t)map->view.nrwords * 4;
+        src.job.coarse = cfg.coarse;
+        if (map->dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
+        else if (map->dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
+        else launch_sensor_t<float, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
+        mcl_status st = check_launch("sensor_kernel (read bits in LDS)");
+        if (st != MCL_OK || npiece == 1) return st;
+        int64_t cb = std::min<int64_t>((N + 255) / 256, (int64_t)device_cus() * 16);
+        combine_kernel<<<(unsigned)std::max<int64_t>(cb, 1), 256, 0, stream>>>(src);
+        return check_launch("combine_kernel");
+    }
     if (!map->sparse) return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream);
     // sparse map: one wave per work item, four waves per workgroup
     const unsigned blocks = (unsigned)((nitems + 3) / 4);

@@ -28,7 +28,7 @@ int size_class(int x) {  // ceil(log2(x)) for x >= 1
 
 bool valid_cfg(const LaunchCfg &c) {
     return (c.waves_per_block == 2 || c.waves_per_block == 4 || c.waves_per_block == 8) && c.blocks_per_cu >= 0 &&
-           c.blocks_per_cu <= 64;
+           c.blocks_per_cu <= 64 && c.coarse >= kCoarseAuto && c.coarse <= kCoarseBits;
 }
 }  // namespace
 
@@ -36,7 +36,7 @@ LaunchCfg tuned_config(int32_t dtype, int K, int N) {
     std::lock_guard<std::mutex> lk(g_tmu);
     auto it = g_tuned.find({dtype, size_class(std::max(K, 1)), size_class(std::max(N, 1))});
     if (it != g_tuned.end()) return it->second;
-    return LaunchCfg{4, 0};
+    return LaunchCfg{4, 0, kCoarseAuto};
 }
 
 }  // namespace mcl
@@ -52,8 +52,9 @@ extern "C" mcl_status mcl_set_launch_config(int32_t dtype, int32_t K, int32_t N,
         g_tuned.erase(key);
         return MCL_OK;
     }
-    LaunchCfg c{cfg->waves_per_block, cfg->blocks_per_cu};
-    if (!valid_cfg(c)) return fail(MCL_EINVAL, "set_launch_config: waves_per_block must be 2, 4 or 8 and blocks_per_cu 0..64");
+    LaunchCfg c{cfg->waves_per_block, cfg->blocks_per_cu, cfg->coarse};
+    if (!valid_cfg(c))
+        return fail(MCL_EINVAL, "set_launch_config: waves_per_block must be 2, 4 or 8, blocks_per_cu 0..64, coarse 0..2");
     g_tuned[key] = c;
     return MCL_OK;
 }
@@ -71,12 +72,12 @@ extern "C" mcl_status mcl_autotune(mcl_map map, const float *points, int32_t K, 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(MCL_EDEVICE, "autotune: event creation failed");
-    LaunchCfg bestc{4, 0};
+    LaunchCfg bestc{4, 0, kCoarseAuto};
     float best_ms = INFINITY;
     mcl_status st = MCL_OK;
     for (int wpb : {2, 4, 8}) {
         for (int bpc : {0, 2, 4, 8, 16}) {
-            LaunchCfg cfg{wpb, bpc};
+            LaunchCfg cfg{wpb, bpc, kCoarseAuto};
             if ((st = launch_sensor_cfg(map, points, K, poses, N, c, logw, cfg, stream)) != MCL_OK) break;
             float t[3];
             for (int r = 0; r < 3 && st == MCL_OK; ++r) {
@@ -105,6 +106,7 @@ extern "C" mcl_status mcl_autotune(mcl_map map, const float *points, int32_t K, 
     if (best) {
         best->waves_per_block = bestc.waves_per_block;
         best->blocks_per_cu = bestc.blocks_per_cu;
+        best->coarse = bestc.coarse;
     }
     return MCL_OK;
 }

@@ -57,21 +57,22 @@ __device__ inline bool voxel_ijk(const MapView &m, float gx, float gy, float gz,
 //   Z = BX BY iz,  X = ix + (V nbz / BX - 1)(ix & ~(BX-1)),
 //   Y = BX iy + (V nbz nbx / BY - BX)(iy & ~(BY-1)).
 // cx, cy hold the two coefficients times ESIZE; the upload keeps them below
-// 2^24.  Sums wrap modulo 2^32 and the true offset is below 2^32, so the
-// wrapped sum is exact.
+// 2^24.  data0 skips the +Q sentinel brick in front.  Sums wrap modulo 2^32
+// and the true offset is below 2^32, so the wrapped sum is exact.
 template <int ESIZE>
 __device__ inline uint32_t brick_offset(const MapView &m, uint32_t ix, uint32_t iy, uint32_t iz) {
     uint32_t lin = (ix + (iy << kBLX) + (iz << (kBLX + kBLY))) * (uint32_t)ESIZE;
-    return __umul24(ix & ~(uint32_t)(kBX - 1), m.cx) + (__umul24(iy & ~(uint32_t)(kBY - 1), m.cy) + lin);
+    return __umul24(ix & ~(uint32_t)(kBX - 1), m.cx) + (__umul24(iy & ~(uint32_t)(kBY - 1), m.cy) + lin) + m.data0;
 }
 
-// Byte offset read for grid coordinates g: the voxel's, or the +Q sentinel outside.
+// Byte offset read for grid coordinates g: the voxel's, or the +Q sentinel
+// (offset 0) outside.
 template <int ESIZE>
 __device__ inline uint32_t voxel_offset(const MapView &m, float gx, float gy, float gz) {
     uint32_t ix, iy, iz;
     bool ok = voxel_ijk(m, gx, gy, gz, ix, iy, iz);
     uint32_t off = brick_offset<ESIZE>(m, ix, iy, iz);
-    return ok ? off : m.out_off;
+    return ok ? off : 0u;
 }
 
 // Trilinear lookup, one axis: the stored values sit at the voxel centres (grid

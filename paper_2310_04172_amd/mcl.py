@@ -48,7 +48,7 @@ class FilterJob(C.Structure):
 
 
 class LaunchConfig(C.Structure):
-    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32)]
+    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("coarse", C.c_int32)]
 
 
 _lib.mcl_map_upload.argtypes = [C.POINTER(MapDesc), _P, _P, C.POINTER(_P)]
@@ -372,10 +372,11 @@ def autotune(m: Map, points, poses, sigma: float, stream=None):
     best = LaunchConfig()
     _check(_lib.mcl_autotune(m.handle, _ptr(points), K, _ptr(poses), N, float(sigma), _ptr(scratch),
                              _stream(stream), C.byref(best)), "mcl_autotune")
-    return best.waves_per_block, best.blocks_per_cu
+    return best.waves_per_block, best.blocks_per_cu, best.coarse
 
 
 def set_launch_config(dtype: str, K: int, N: int, cfg=None):
-    """cfg = (waves_per_block, blocks_per_cu), or None to clear."""
+    """cfg = (waves_per_block, blocks_per_cu[, coarse]), or None to clear;
+    coarse: 0 auto, 1 global bytes, 2 LDS bits."""
     c = None if cfg is None else C.byref(LaunchConfig(*cfg))
     _check(_lib.mcl_set_launch_config(DTYPE_CODE[dtype], K, N, c), "mcl_set_launch_config")

@@ -144,7 +144,7 @@ def test_launch_shapes_are_bit_identical(torch, mcl):
                 got = mcl.sensor_update(m, X, P, w.sigma).cpu().numpy()
                 assert np.array_equal(got, ref), (wpb, bpc)
         best = mcl.autotune(m, X, P, w.sigma)
-        assert best[0] in (2, 4, 8) and best[1] in (0, 2, 4, 8, 16)
+        assert best[0] in (2, 4, 8) and best[1] in (0, 2, 4, 8, 16) and best[2] == 0
         assert np.array_equal(mcl.sensor_update(m, X, P, w.sigma).cpu().numpy(), ref)
     finally:
         mcl.set_launch_config("i16", w.K, w.N, None)
