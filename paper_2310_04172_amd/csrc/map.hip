@@ -85,13 +85,15 @@ __global__ __launch_bounds__(256) void tri_build_kernel(MapView src, T *__restri
                                                         int64_t ncells, T outside) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ncells) return;
-    int64_t bi = e >> 6;
-    int w = (int)(e & 63);
-    int bz = (int)(bi % nbz);
-    int64_t r = bi / nbz;
-    int bx = (int)(r % nbx);
-    int by = (int)(r / nbx);
-    int ix = bx * 4 + (w & 3) - 1, iy = by * 4 + ((w >> 2) & 3) - 1, iz = bz * 4 + (w >> 4) - 1;
+    const int64_t bi = e >> kCellBrickLog2;
+    const int w = (int)(e & (kCellBrickVals - 1));
+    const int bz = (int)(bi % nbz);
+    const int64_t r = bi / nbz;
+    const int bx = (int)(r % nbx);
+    const int by = (int)(r / nbx);
+    const int ix = bx * kCX + (w & (kCX - 1)) - 1;
+    const int iy = by * kCY + ((w >> kCLX) & (kCY - 1)) - 1;
+    const int iz = bz * kCZ + (w >> (kCLX + kCLY)) - 1;
     for (int c = 0; c < 8; ++c) {
         int x = ix + (c & 1), y = iy + ((c >> 1) & 1), z = iz + (c >> 2);
         T v = outside;
@@ -101,20 +103,20 @@ __global__ __launch_bounds__(256) void tri_build_kernel(MapView src, T *__restri
     }
 }
 
-// Class byte of every brick of cells: kCellPos if all 8 corners of all its 64
-// cells are +Q, kCellNeg if all are -Q, else kCellMixed.
+// Read mask of every brick of cells, at slot brick + 1 (slot 0: the sentinel):
+// 0 if all 8 corners of all its cells are +Q, or all are -Q, else -1.
 template <typename T>
-__global__ __launch_bounds__(256) void tri_class_kernel(const T *__restrict__ cells, uint8_t *__restrict__ cls,
-                                                        int64_t nbricks, T qpos, T qneg) {
+__global__ __launch_bounds__(256) void tri_mask_kernel(const T *__restrict__ cells, int8_t *__restrict__ mask,
+                                                       int64_t nbricks, T qpos, T qneg) {
     int64_t bi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (bi >= nbricks) return;
-    const T *b = cells + bi * 64 * 8;
+    const T *b = cells + bi * kCellBrickVals * 8;
     bool pos = true, neg = true;
-    for (int w = 0; w < 64 * 8; ++w) {
+    for (int w = 0; w < kCellBrickVals * 8; ++w) {
         pos &= b[w] == qpos;
         neg &= b[w] == qneg;
     }
-    cls[bi] = pos ? kCellPos : neg ? kCellNeg : kCellMixed;
+    mask[bi + 1] = (pos || neg) ? int8_t(0) : int8_t(-1);
 }
 
 static std::mutex g_tri_mu;
@@ -125,52 +127,50 @@ mcl_status ensure_trilinear(mcl_map_s *m, hipStream_t stream) {
     if (m->tri_dev) return MCL_OK;
     const MapView &v = m->view;
     const int es = 8 * elem_size(m->dtype);  // bytes per cell
-    const int px = v.nx + 2, py = v.ny + 2, pz = v.nz + 2;
-    const int nbx = (px + 3) / 4, nby = (py + 3) / 4, nbz = (pz + 3) / 4;
-    const int64_t nvals = (int64_t)nbx * nby * nbz * kCellBrickVals;  // cells
-    const int64_t data_bytes = nvals * es;
+    const int64_t px = v.nx + 2, py = v.ny + 2, pz = v.nz + 2;
+    const int64_t nbx = (px + kCX - 1) / kCX, nby = (py + kCY - 1) / kCY, nbz = (pz + kCZ - 1) / kCZ;
+    const int64_t nvals = nbx * nby * nbz * kCellBrickVals;  // cells
     const int64_t nbricks = nvals / kCellBrickVals;
-    const int64_t cls_off = (data_bytes + 2 * es + 255) / 256 * 256;  // two sentinel cells, then the classes
-    const int64_t bytes = cls_off + (nbricks + 255) / 256 * 256;
-    const int64_t cy = (int64_t)es * (16 * (int64_t)nbz * nbx - 4);
-    if (bytes >= ((int64_t)1 << 32) || cy >= ((int64_t)1 << 24))
+    const int64_t brick_bytes = (int64_t)kCellBrickVals * es;
+    const int64_t data0 = brick_bytes;  // +Q sentinel brick of cells in front
+    const int64_t mask_off = (data0 + nvals * es + 255) / 256 * 256;
+    const int64_t bytes = mask_off + (nbricks + 1 + 255) / 256 * 256;
+    const int64_t cx = (int64_t)es * (kCellBrickVals / kCX * nbz - 1);
+    const int64_t cy = (int64_t)es * (kCellBrickVals / kCY * nbz * nbx - kCX);
+    if (bytes >= ((int64_t)1 << 32) || cy >= ((int64_t)1 << 24) || cx >= ((int64_t)1 << 24))
         return fail(MCL_ERANGE, "trilinear: the corner-cell map exceeds the brick addressing limits");
     void *dev = nullptr;
     if (hipMalloc(&dev, (size_t)bytes) != hipSuccess) return fail(MCL_ENOMEM, "trilinear: device allocation failed");
     char *base = static_cast<char *>(dev);
-    uint8_t *cls = reinterpret_cast<uint8_t *>(base + cls_off);
-    char sent[64];
-    for (int c = 0; c < 8; ++c) {
-        if (m->dtype == MCL_TSDF_I16) {
-            reinterpret_cast<int16_t *>(sent)[c] = 32767;
-            reinterpret_cast<int16_t *>(sent + es)[c] = -32767;
-        } else if (m->dtype == MCL_TSDF_I8) {
-            reinterpret_cast<int8_t *>(sent)[c] = 127;
-            reinterpret_cast<int8_t *>(sent + es)[c] = -127;
-        } else {
-            reinterpret_cast<float *>(sent)[c] = m->tau;
-            reinterpret_cast<float *>(sent + es)[c] = -m->tau;
-        }
+    int8_t *mask = reinterpret_cast<int8_t *>(base + mask_off);
+    std::vector<char> sent((size_t)brick_bytes);
+    for (int64_t c = 0; c < kCellBrickVals * 8; ++c) {
+        if (m->dtype == MCL_TSDF_I16) reinterpret_cast<int16_t *>(sent.data())[c] = 32767;
+        else if (m->dtype == MCL_TSDF_I8) reinterpret_cast<int8_t *>(sent.data())[c] = 127;
+        else reinterpret_cast<float *>(sent.data())[c] = m->tau;
     }
+    const int8_t sent_mask = 0;
     mcl_status st = MCL_OK;
-    if (hipMemcpyAsync(base + data_bytes, sent, (size_t)(2 * es), hipMemcpyHostToDevice, stream) != hipSuccess)
+    if (hipMemcpyAsync(base, sent.data(), (size_t)brick_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(mask, &sent_mask, 1, hipMemcpyHostToDevice, stream) != hipSuccess)
         st = fail(MCL_EDEVICE, "trilinear: sentinel copy failed");
     const unsigned blocks = (unsigned)((nvals + 255) / 256);
     const unsigned cblocks = (unsigned)((nbricks + 255) / 256);
     if (st == MCL_OK) {
+        char *cells = base + data0;
         if (m->dtype == MCL_TSDF_I16) {
-            tri_build_kernel<int16_t><<<blocks, 256, 0, stream>>>(v, (int16_t *)dev, nbx, nbz, nvals, (int16_t)32767);
-            tri_class_kernel<int16_t><<<cblocks, 256, 0, stream>>>((const int16_t *)dev, cls, nbricks, (int16_t)32767,
-                                                                   (int16_t)-32767);
+            tri_build_kernel<int16_t><<<blocks, 256, 0, stream>>>(v, (int16_t *)cells, (int)nbx, (int)nbz, nvals, (int16_t)32767);
+            tri_mask_kernel<int16_t><<<cblocks, 256, 0, stream>>>((const int16_t *)cells, mask, nbricks, (int16_t)32767,
+                                                                  (int16_t)-32767);
         } else if (m->dtype == MCL_TSDF_I8) {
-            tri_build_kernel<int8_t><<<blocks, 256, 0, stream>>>(v, (int8_t *)dev, nbx, nbz, nvals, (int8_t)127);
-            tri_class_kernel<int8_t><<<cblocks, 256, 0, stream>>>((const int8_t *)dev, cls, nbricks, (int8_t)127,
-                                                                  (int8_t)-127);
+            tri_build_kernel<int8_t><<<blocks, 256, 0, stream>>>(v, (int8_t *)cells, (int)nbx, (int)nbz, nvals, (int8_t)127);
+            tri_mask_kernel<int8_t><<<cblocks, 256, 0, stream>>>((const int8_t *)cells, mask, nbricks, (int8_t)127,
+                                                                 (int8_t)-127);
         } else {
-            tri_build_kernel<float><<<blocks, 256, 0, stream>>>(v, (float *)dev, nbx, nbz, nvals, m->tau);
-            tri_class_kernel<float><<<cblocks, 256, 0, stream>>>((const float *)dev, cls, nbricks, m->tau, -m->tau);
+            tri_build_kernel<float><<<blocks, 256, 0, stream>>>(v, (float *)cells, (int)nbx, (int)nbz, nvals, m->tau);
+            tri_mask_kernel<float><<<cblocks, 256, 0, stream>>>((const float *)cells, mask, nbricks, m->tau, -m->tau);
         }
-        st = check_launch("tri_build_kernel / tri_class_kernel");
+        st = check_launch("tri_build_kernel / tri_mask_kernel");
     }
     if (st == MCL_OK && hipStreamSynchronize(stream) != hipSuccess)
         st = fail(MCL_EDEVICE, "trilinear: synchronisation failed");
@@ -180,13 +180,13 @@ mcl_status ensure_trilinear(mcl_map_s *m, hipStream_t stream) {
     }
     TriView t{};
     t.base = static_cast<const char *>(dev);
-    t.cx = (uint32_t)(es * (16 * nbz - 1));
+    t.cx = (uint32_t)cx;
     t.cy = (uint32_t)cy;
+    t.data0 = (uint32_t)data0;
     t.hx = (float)v.nx;
     t.hy = (float)v.ny;
     t.hz = (float)v.nz;
-    t.pos_off = (uint32_t)data_bytes;
-    t.cls = cls;
+    t.mask = mask;
     m->tri = t;
     m->tri_bytes = (size_t)bytes;
     m->tri_dev = dev;

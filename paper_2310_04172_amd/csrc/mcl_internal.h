@@ -66,22 +66,25 @@ constexpr uint32_t kMaxLdsBits = 64 * 1024;
 // the 8 voxel values at its corners (i..i+1, j..j+1, k..k+1), x fastest, so an
 // interpolation reads one 16-byte run (int16; 8 bytes int8, 32 bytes float32).
 // Cells span i in [-1, n] per axis (corners outside the map hold +Q) and are
-// stored at index i + 1 in bricks of 4 x 4 x 4 cells (64 cells), ordered like
-// the value bricks.  Eight times the map's memory (HBM is plentiful, gathers
-// are not).
-// As for the values, a class byte per brick of cells says whether every corner
-// of its 64 cells is +Q (class 1) or every one is -Q (class 3); such points
-// read one of two sentinel cells (all +Q, all -Q) after the data instead of
-// their own.  Built on first use of the trilinear lookup.
+// stored at index i + 1 in bricks of CX x CY x CZ cells, x fastest inside a
+// brick, bricks ordered like the value bricks; a +Q sentinel brick of cells
+// comes first, at offset 0.  Eight times the map's memory (HBM is plentiful,
+// gathers are not).  As for the values, each brick of cells has a read mask,
+// -1 (read in place) unless every corner of its cells is +Q or every one is
+// -Q: such a cell interpolates to exactly +-Q, and only the square enters the
+// score, so the lookup reads offset (offset AND mask) = 0, the sentinel.
+// Built on first use of the trilinear lookup.
 struct TriView {
-    const char *base;        // device: bricked corner cells
+    const char *base;        // device: sentinel brick, then the bricked corner cells
     uint32_t cx, cy;         // brick address coefficients of the cell grid (bytes)
+    uint32_t data0;          // byte offset of the first brick of cells
     float hx, hy, hz;        // (float)n per axis: upper clamp of h
-    uint32_t pos_off;        // byte offset of the all +Q sentinel cell (the -Q one follows)
-    const uint8_t *cls;      // class byte per brick of cells, indexed by byte offset >> (6 + log2 cell bytes)
+    const int8_t *mask;      // read mask per brick slot, indexed by byte offset >> (log2 cells per brick + log2 cell bytes)
 };
-constexpr uint8_t kCellMixed = 0, kCellPos = 1, kCellNeg = 3;
-constexpr int kCellBrickVals = 64;
+constexpr int kCLX = 2, kCLY = 2, kCLZ = 2;                      // log2 of the cell-brick shape
+constexpr int kCX = 1 << kCLX, kCY = 1 << kCLY, kCZ = 1 << kCLZ;
+constexpr int kCellBrickLog2 = kCLX + kCLY + kCLZ;
+constexpr int kCellBrickVals = 1 << kCellBrickLog2;
 
 // Sparse coarse/fine map (§III: the map holds fine data only for the coarse
 // cells with distances inside the truncation band, after Akai et al.): a pool

@@ -157,8 +157,8 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_lds(const 
 
 // Trilinear lookup (§III: a pseudo-continuous map value by interpolation): one
 // gather of the point's corner cell (the 8 voxel values around it; corners
-// outside the map hold +Q; cells of uniform +Q / -Q bricks read a shared
-// sentinel cell after a class-byte lookup), interpolated along x, then y, then z by
+// outside the map hold +Q; cells of bricks wholly at +Q or wholly at -Q read
+// the shared +Q sentinel after a read-mask lookup), interpolated along x, then y, then z by
 // lerp(a, b, t) = fma(t, b - a, a) in float32.  A point clamped to h = -1 has
 // weight 0 on its inside corner and a point clamped to h = n reads two +Q
 // corners, so both give exactly Q.  Padding slots contribute 0.  Points go in
@@ -223,7 +223,7 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_tri(const 
                                                                           const float (&px)[kU], const float (&py)[kU],
                                                                           const float (&pz)[kU], int lane, int nvalid) {
     constexpr int E = 8 * sizeof(T);  // bytes per cell
-    constexpr int kShift = 6 + (E == 8 ? 3 : E == 16 ? 4 : 5);
+    constexpr int kShift = kCellBrickLog2 + (E == 8 ? 3 : E == 16 ? 4 : 5);
     float s = 0.0f;
 #pragma unroll
     for (int u0 = 0; u0 < kU; u0 += kTriU) {
@@ -239,17 +239,16 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_tri(const 
             const uint32_t ix = tri_axis(gx, tv.hx, fx[v]);
             const uint32_t iy = tri_axis(gy, tv.hy, fy[v]);
             const uint32_t iz = tri_axis(gz, tv.hz, fz[v]);
-            off[v] = brick_x<E>(tv.cx, ix) + brick_y<E>(tv.cy, iy) + brick_z<E>(iz);
+            off[v] = brick_x<E>(tv.cx, ix) + brick_y<E>(tv.cy, iy) + brick_z<E>(iz) + tv.data0;
         }
-        uint32_t cls[kTriU];
+        int msk[kTriU];
 #pragma unroll
-        for (int v = 0; v < kTriU; ++v) cls[v] = tv.cls[off[v] >> kShift];
+        for (int v = 0; v < kTriU; ++v) msk[v] = tv.mask[off[v] >> kShift];
         __builtin_amdgcn_sched_barrier(0);
-        // cells of uniform bricks read the shared sentinel cell of their sign
-        // (class 1: +Q at pos_off, class 3: -Q right after it)
+        // cells of bricks wholly at +Q or wholly at -Q read the +Q sentinel
+        // brick at offset 0 (same square)
 #pragma unroll
-        for (int v = 0; v < kTriU; ++v)
-            raw[v] = load_cell<T>(tv.base, cls[v] == kCellMixed ? off[v] : tv.pos_off + ((cls[v] >> 1) & 1u) * E);
+        for (int v = 0; v < kTriU; ++v) raw[v] = load_cell<T>(tv.base, off[v] & (uint32_t)msk[v]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < kTriU; ++v) {

@@ -90,13 +90,18 @@ __device__ inline uint32_t tri_axis(float g, float hmax, float &f) {
 }
 
 // Byte offset of cell (i, j, k) of the trilinear corner-cell grid (bricks of
-// 4 x 4 x 4 cells, z-fastest, then x, then y; ESIZE bytes per cell) is
-// X(i) + Y(j) + Z(k), with the coefficients of TriView.
+// CX x CY x CZ cells, z-fastest, then x, then y; ESIZE bytes per cell) is
+// data0 + X(i) + Y(j) + Z(k), separable as for the values, with the
+// coefficients of TriView.
 template <int ESIZE>
-__device__ inline uint32_t brick_x(uint32_t cx, uint32_t ix) { return __umul24(ix & ~3u, cx) + ix * ESIZE; }
+__device__ inline uint32_t brick_x(uint32_t cx, uint32_t ix) {
+    return __umul24(ix & ~(uint32_t)(kCX - 1), cx) + ix * ESIZE;
+}
 template <int ESIZE>
-__device__ inline uint32_t brick_y(uint32_t cy, uint32_t iy) { return __umul24(iy & ~3u, cy) + (iy << 2) * ESIZE; }
+__device__ inline uint32_t brick_y(uint32_t cy, uint32_t iy) {
+    return __umul24(iy & ~(uint32_t)(kCY - 1), cy) + (iy << kCLX) * ESIZE;
+}
 template <int ESIZE>
-__device__ inline uint32_t brick_z(uint32_t iz) { return (iz << 4) * ESIZE; }
+__device__ inline uint32_t brick_z(uint32_t iz) { return (iz << (kCLX + kCLY)) * ESIZE; }
 
 }  // namespace mcl
