@@ -54,9 +54,9 @@ __device__ inline float wave_sum(float x) {
 template <typename T>
 __device__ inline int load_raw(const char *base, uint32_t off) {
     if constexpr (sizeof(T) == 4)
-        return __float_as_int(*reinterpret_cast<const float *>(base + off));
+        return __float_as_int(*gp(reinterpret_cast<const float *>(base + off)));
     else
-        return (int)*reinterpret_cast<const T *>(base + off);
+        return (int)*gp(reinterpret_cast<const T *>(base + off));
 }
 
 template <typename T>
@@ -93,7 +93,7 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum(const MapV
     }
     int msk[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) msk[u] = m.mask[off[u] >> class_shift<T>()];
+    for (int u = 0; u < kU; ++u) msk[u] = gp(m.mask)[off[u] >> class_shift<T>()];
     __builtin_amdgcn_sched_barrier(0);
     int raw[kU];
 #pragma unroll
@@ -182,16 +182,26 @@ struct CellRaw<float> {
     float4 a, b;
 };
 
+// clang vector types (the HIP vector structs do not load through
+// address-space-qualified pointers)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
 __device__ inline CellRaw<T> load_cell(const char *base, uint32_t off) {
     CellRaw<T> r;
     if constexpr (sizeof(T) == 2) {
-        r.q = *reinterpret_cast<const uint4 *>(base + off);
+        const u32x4 v = *gp(reinterpret_cast<const u32x4 *>(base + off));
+        r.q = make_uint4(v.x, v.y, v.z, v.w);
     } else if constexpr (sizeof(T) == 1) {
-        r.q = *reinterpret_cast<const uint2 *>(base + off);
+        const u32x2 v = *gp(reinterpret_cast<const u32x2 *>(base + off));
+        r.q = make_uint2(v.x, v.y);
     } else {
-        r.a = *reinterpret_cast<const float4 *>(base + off);
-        r.b = *reinterpret_cast<const float4 *>(base + off + 16);
+        const f32x4 a = *gp(reinterpret_cast<const f32x4 *>(base + off));
+        const f32x4 b = *gp(reinterpret_cast<const f32x4 *>(base + off + 16));
+        r.a = make_float4(a.x, a.y, a.z, a.w);
+        r.b = make_float4(b.x, b.y, b.z, b.w);
     }
     return r;
 }
@@ -243,7 +253,7 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_tri(const 
         }
         int msk[kTriU];
 #pragma unroll
-        for (int v = 0; v < kTriU; ++v) msk[v] = tv.mask[off[v] >> kShift];
+        for (int v = 0; v < kTriU; ++v) msk[v] = gp(tv.mask)[off[v] >> kShift];
         __builtin_amdgcn_sched_barrier(0);
         // cells of bricks wholly at +Q or wholly at -Q read the +Q sentinel
         // brick at offset 0 (same square)
@@ -276,9 +286,9 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_tri(const 
 template <typename T>
 __device__ inline int load_raw64(const char *p) {
     if constexpr (sizeof(T) == 4)
-        return __float_as_int(*reinterpret_cast<const float *>(p));
+        return __float_as_int(*gp(reinterpret_cast<const float *>(p)));
     else
-        return (int)*reinterpret_cast<const T *>(p);
+        return (int)*gp(reinterpret_cast<const T *>(p));
 }
 
 template <typename T, bool TAIL, bool WIDE>
@@ -416,9 +426,9 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             int k = min(kc + u * kWave + lane, ke - 1);  // padding slots are masked later
-            px[u] = J.pts[k];
-            py[u] = J.pts[(size_t)K + k];
-            pz[u] = J.pts[(size_t)2 * K + k];
+            px[u] = gp(J.pts)[k];
+            py[u] = gp(J.pts)[(size_t)K + k];
+            pz[u] = gp(J.pts)[(size_t)2 * K + k];
         }
         if (nvalid == kChunk)
             chunk_group<T, false, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc, sbits);
@@ -455,7 +465,7 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == 
     if constexpr (LK == kLookNearestLds) {
         // one map per launch (single-filter calls): its read bits into LDS
         const SensorJob J0 = src.load(0);
-        for (uint32_t w = threadIdx.x; w < J0.map.nrwords; w += WPB * 64) sbits[w] = J0.map.rbits[w];
+        for (uint32_t w = threadIdx.x; w < J0.map.nrwords; w += WPB * 64) sbits[w] = gp(J0.map.rbits)[w];
         __syncthreads();
     }
     for (int64_t item = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems;
@@ -546,10 +556,17 @@ static void launch_sensor_t(const Src &src, int64_t nitems, LaunchCfg cfg, hipSt
     }
 }
 
+// lds > 0: every job of the launch reads the same dense map, whose read bits
+// (nrwords * 4 <= lds bytes) each workgroup copies into LDS; the coarse level
+// is then chosen per wave (the jobs' `coarse` field).
 template <typename Src>
 mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int64_t nelems, bool combine,
-                             LaunchCfg cfg, hipStream_t stream) {
-    if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t>(src, nitems, cfg, stream);
+                             LaunchCfg cfg, hipStream_t stream, size_t lds) {
+    if (lds > 0) {
+        if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
+        else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
+        else launch_sensor_t<float, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
+    } else if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t>(src, nitems, cfg, stream);
     else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t>(src, nitems, cfg, stream);
     else launch_sensor_t<float>(src, nitems, cfg, stream);
     mcl_status st = check_launch("sensor_kernel");
@@ -560,9 +577,9 @@ mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int6
 }
 
 template mcl_status launch_sensor_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t, int64_t,
-                                                           bool, LaunchCfg, hipStream_t);
+                                                           bool, LaunchCfg, hipStream_t, size_t);
 template mcl_status launch_sensor_src<OneJob<SensorJob>>(int32_t, const OneJob<SensorJob> &, int64_t, int64_t,
-                                                         bool, LaunchCfg, hipStream_t);
+                                                         bool, LaunchCfg, hipStream_t, size_t);
 
 SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
                           float *logw, float *part) {
@@ -598,18 +615,10 @@ mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, cons
     const int64_t nitems = (int64_t)src.job.ngroups * npiece;
     src.n = Counts{1, nitems, N, 0};
     if (!map->sparse && (size_t)map->view.nrwords * 4 <= kMaxLdsBits && cfg.coarse != kCoarseBytes) {
-        const size_t lds = (size_t)map->view.nrwords * 4;
         src.job.coarse = cfg.coarse;
-        if (map->dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
-        else if (map->dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
-        else launch_sensor_t<float, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
-        mcl_status st = check_launch("sensor_kernel (read bits in LDS)");
-        if (st != MCL_OK || npiece == 1) return st;
-        int64_t cb = std::min<int64_t>((N + 255) / 256, (int64_t)device_cus() * 16);
-        combine_kernel<<<(unsigned)std::max<int64_t>(cb, 1), 256, 0, stream>>>(src);
-        return check_launch("combine_kernel");
+        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, (size_t)map->view.nrwords * 4);
     }
-    if (!map->sparse) return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream);
+    if (!map->sparse) return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, 0);
     // sparse map: one wave per work item, four waves per workgroup
     const unsigned blocks = (unsigned)((nitems + 3) / 4);
     if (map->sp.small) {

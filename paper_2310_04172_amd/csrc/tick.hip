@@ -17,7 +17,7 @@ namespace mcl {
 
 SensorJob make_sensor_job(const mcl_map_s *, const float *, int, const float *, int, float, float *, float *);
 template <typename Src>
-mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t);
+mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t, size_t);
 template <typename Src>
 mcl_status launch_normalize_src(const Src &, int, int64_t, int64_t, hipStream_t);
 template <typename Src>
@@ -52,10 +52,11 @@ struct GraphKey {
     int mask;
     int wpb, bpc;
     int64_t items[3], elems, blocks, eblocks, ejobs;
+    int64_t lds[3];  // LDS bytes for the read bits of a group's shared map, or 0
     bool operator<(const GraphKey &o) const {
-        return std::tie(mask, wpb, bpc, items[0], items[1], items[2], elems, blocks, eblocks, ejobs) <
-               std::tie(o.mask, o.wpb, o.bpc, o.items[0], o.items[1], o.items[2], o.elems, o.blocks, o.eblocks,
-                        o.ejobs);
+        return std::tie(mask, wpb, bpc, items[0], items[1], items[2], elems, blocks, eblocks, ejobs, lds[0], lds[1],
+                        lds[2]) < std::tie(o.mask, o.wpb, o.bpc, o.items[0], o.items[1], o.items[2], o.elems,
+                                           o.blocks, o.eblocks, o.ejobs, o.lds[0], o.lds[1], o.lds[2]);
     }
 };
 
@@ -180,6 +181,12 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     // the previous tick's table copy must have left the staging buffer
     if (S.pending && hipEventSynchronize(S.copied) != hipSuccess) return fail(MCL_EDEVICE, "tick: event wait failed");
 
+    // launch shape and coarse-level mode: those tuned for the largest filter
+    int big = 0;
+    for (int j = 1; j < n_jobs; ++j)
+        if ((int64_t)jobs[j].N * jobs[j].K > (int64_t)jobs[big].N * jobs[big].K) big = j;
+    const LaunchCfg cfg = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
+
     Counts *cnt = reinterpret_cast<Counts *>(S.host);
     WeightJob *wtbl = reinterpret_cast<WeightJob *>(S.host + kWeightTblOff);
     EstJob *etbl = reinterpret_cast<EstJob *>(S.host + kEstTblOff);
@@ -211,6 +218,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             }
             SensorJob &J = stbl[s];
             J = make_sensor_job(m, F.points, F.K, F.poses, F.N, c, F.logw, part);
+            J.coarse = cfg.coarse;
             J.item0 = items;
             J.elem0 = elems;
             items += (int64_t)J.ngroups * J.npiece;
@@ -265,13 +273,20 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     // The launch chain reads every size from the device tables; grids are sized
     // for the totals (under a graph, for their power-of-two buckets, so a
     // replay serves any tick that fits; surplus waves exit at once).
-    int big = 0;
-    for (int j = 1; j < n_jobs; ++j)
-        if ((int64_t)jobs[j].N * jobs[j].K > (int64_t)jobs[big].N * jobs[big].K) big = j;
-    LaunchCfg cfg = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
     const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
     const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
-    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu, {0, 0, 0}, 0, 0, 0, 0};
+    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu, {0, 0, 0}, 0, 0, 0, 0, {0, 0, 0}};
+    // A storage-type group whose jobs all read one map with a small enough bit
+    // table gets the kernel that holds those bits in LDS (a power of two bytes,
+    // so a graph serves any such map up to that size).
+    for (int g = 0; g < kGroups && cfg.coarse != kCoarseBytes; ++g) {
+        if (g_begin[g + 1] == g_begin[g]) continue;
+        const mcl_map_s *m0 = jobs[order[g_begin[g]]].map;
+        bool shared = true;
+        for (int s = g_begin[g] + 1; s < g_begin[g + 1] && shared; ++s) shared = jobs[order[s]].map == m0;
+        const int64_t bits = (int64_t)m0->view.nrwords * 4;
+        if (shared && bits <= (int64_t)kMaxLdsBits) key.lds[g] = std::max<int64_t>(bucket(bits), 1024);
+    }
     for (int g = 0; g < kGroups; ++g) key.items[g] = use_graph ? bucket(cnt[g].items) : cnt[g].items;
     key.elems = use_graph ? bucket(welem) : welem;
     key.blocks = use_graph ? bucket(wblk) : wblk;
@@ -283,7 +298,8 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             JobTable<SensorJob> src{reinterpret_cast<const SensorJob *>(S.dev + kSensorTblOff + g * kSensorTblBytes),
                                     dcnt + g};
             // under a graph every group may combine (a job with one piece is skipped inside)
-            mcl_status st = launch_sensor_src(g, src, key.items[g], key.elems, use_graph || combine[g], cfg, stream);
+            mcl_status st =
+                launch_sensor_src(g, src, key.items[g], key.elems, use_graph || combine[g], cfg, stream, (size_t)key.lds[g]);
             if (st != MCL_OK) return st;
         }
         JobTable<WeightJob> wsrc{dwt, dcnt + kWeightCnt};

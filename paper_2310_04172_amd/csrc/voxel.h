@@ -7,6 +7,15 @@
 
 namespace mcl {
 
+// The same pointer in the global address space.  Pointers that reach a kernel
+// through a job table in memory are generic to the compiler, which then emits
+// FLAT loads with a 64-bit address add per load; every pointer here is to
+// device memory, so loads through gp() are plain global loads.
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T *gp(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
 // Per-particle constants of the index recipe (pose prologue):
 //   a_jk = r_jk * inv_v  (pa[0..8]),  b_j = (t_j - o_j) * inv_v  (pa[9..11]).
 // poses: [12][N] rows r00 .. r22 tx ty tz.
@@ -14,10 +23,10 @@ __device__ inline void pose_consts(const float *__restrict__ poses, int N, int n
                                    float pa[12]) {
 #pragma clang fp contract(off)
 #pragma unroll
-    for (int j = 0; j < 9; ++j) pa[j] = poses[(size_t)j * N + n] * m.inv_v;
-    float dx = poses[(size_t)9 * N + n] - m.ox;
-    float dy = poses[(size_t)10 * N + n] - m.oy;
-    float dz = poses[(size_t)11 * N + n] - m.oz;
+    for (int j = 0; j < 9; ++j) pa[j] = gp(poses)[(size_t)j * N + n] * m.inv_v;
+    float dx = gp(poses)[(size_t)9 * N + n] - m.ox;
+    float dy = gp(poses)[(size_t)10 * N + n] - m.oy;
+    float dz = gp(poses)[(size_t)11 * N + n] - m.oz;
     // adding +0.0 turns a -0.0 offset into +0.0 and leaves every other value
     // unchanged, so that translations of -0.0 and +0.0 select alike
     pa[9] = dx * m.inv_v + 0.0f;

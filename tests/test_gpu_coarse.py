@@ -127,3 +127,32 @@ def test_bit_table_too_large_for_lds(torch, mcl, oracle_lib):
     ref = oracle_lib.sensor_update(tmap, pts, poses, f32(0.075))
     assert np.all(np.abs(outs[0] - ref) <= RTOL * np.abs(ref))
     assert np.unique(np.round(ref, 3)).size > N // 2
+
+
+def test_tick_on_one_map_modes_agree(torch, mcl):
+    """A batched tick whose filters share one map holds that map's read bits in
+    LDS; clustered and spread filters, every coarse mode, and the single-filter
+    calls give the same bits."""
+    say("case: coarse modes in a batched tick on one map")
+    rng = np.random.default_rng(5)
+    dims = (40, 70, 30)
+    tmap = banded_map(rng, dims, "i16")
+    m = mcl.Map.from_tsdf(tmap)
+    ext = np.array(dims) * 0.1
+    filters = []
+    for i, (N, K) in enumerate([(3000, 5000), (700, 1500), (64, 9000), (5, 4096)]):
+        t = ext * 0.5 + rng.normal(0, 0.05, (N, 3)) if i % 2 else rng.uniform(0, 1, (N, 3)) * ext
+        poses = poses_from(random_rotations(rng, N), t)
+        pts = rng.normal(0, 0.3 * ext.mean(), (3, K)).astype(np.float32)
+        filters.append(mcl.Filter(m, dev(torch, pts), dev(torch, poses), f32(0.15), int(rng.integers(0, 2 ** 63))))
+    singles = [mcl.sensor_update(m, f.points, f.poses, f.sigma).cpu().numpy() for f in filters]
+    try:
+        for mode in (0, 1, 2):
+            mcl.set_launch_config("i16", 5000, 3000, (4, 0, mode))
+            mcl.tick(filters)
+            torch.cuda.synchronize()
+            for i, f in enumerate(filters):
+                got = f.logw.cpu().numpy()
+                assert np.array_equal(got.view(np.uint32), singles[i].view(np.uint32)), (mode, i)
+    finally:
+        mcl.set_launch_config("i16", 5000, 3000, None)
