@@ -497,6 +497,7 @@ def run_served(args):
     res = {}
     for name, kw in (("served", dict(plain=False, graph=args.graph)), ("plain_sequential", dict(plain=True))):
         eng = Engine(make_robots(), init_particles, budget_bytes=budget, max_evals_per_tick=args.tick_evals, seed=5,
+                     n_streams=args.streams,
                      **kw)
         st = eng.run(sw.trace)
         res[name] = st.summary()
@@ -511,7 +512,8 @@ def run_served(args):
                                    "0.05 m; 1024x1024x256 at 0.1 m), 256 robots, Poisson 10 Hz, first 5 updates "
                                    "global (N 262k-1M) then tracking (N 4k-32k), 16x1800 / 64x1024 scans",
                        "trace_s": args.trace_seconds, "robots": len(sw.robots), "budget_GiB": args.budget_gib,
-                       "graph": args.graph, "tick_evals_cap": args.tick_evals})
+                       "graph": args.graph, "tick_evals_cap": args.tick_evals,
+                       "streams": args.streams})
     out["steps"] = sv["completed"]
     out["warmup"] = 0
     out["latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"]}
@@ -533,6 +535,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--graph", action="store_true", help="served: replay ticks from captured graphs")
     ap.add_argument("--tick-evals", type=float, default=3e10, help="served: cap on particle-point evals per tick")
+    ap.add_argument("--streams", type=int, default=2, help="served: streams (ticks in flight at once)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the sensor kernel's launch shape first")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the batched workload's particle counts")
