@@ -138,9 +138,10 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
         co, va = to_bricks(w.tmap)
         m = mcl.Map.from_bricks(w.tmap.dims, w.tmap.voxel, w.tmap.origin, w.tmap.tau, w.tmap.dtype, co, va)
         nb = ((w.tmap.nx + 3) // 4) * ((w.tmap.ny + 3) // 4) * ((w.tmap.nz + 3) // 4)
-        sparse_info = {"stored_bricks": int(co.shape[0]), "bricks": nb,
-                       "device_bytes": int((nb + 31) // 32 * 8 + (co.shape[0] + 2) * va.itemsize * 64),
-                       "dense_device_bytes": int(nb * 64 * va.itemsize + nb)}
+        dense = mcl.Map.from_tsdf(w.tmap)
+        sparse_info = {"stored_bricks": int(co.shape[0]), "bricks": nb, "device_bytes": m.device_bytes,
+                       "dense_device_bytes": dense.device_bytes}
+        dense.close()
         log(f"sparse map: {json.dumps(sparse_info)}")
     else:
         m = mcl.Map.from_tsdf(w.tmap)

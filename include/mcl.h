@@ -81,8 +81,10 @@ mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_values, voi
  * Akai et al.).  The grid is cut into 4x4x4 bricks (brick (bx, by, bz) holds
  * voxels 4bx..4bx+3 etc.); only the listed bricks are stored, every other
  * voxel reads +Q (+tau): free or unobserved space.  Memory grows with the
- * number of stored bricks, and the map may exceed the 4 GiB limit of the dense
- * layout (limits: nbx*nby*nbz < 2^31 bricks, nbz*nbx < 2^24).  The sensor
+ * number of stored bricks (the library keeps them in 8x32x4-voxel blocks, a
+ * block being stored when any of its bricks is listed; mcl_map_bytes reports
+ * the total), and the map may exceed the 4 GiB limit of the dense layout
+ * (limits: nbx*nby*nbz < 2^31 bricks, nx*nz < 2^29 voxels).  The sensor
  * update gives exactly the results of the dense map with the same values; the
  * trilinear lookup, the uniform initialisation and mcl_tick reject sparse maps.
  *   nstored:      number of listed bricks, >= 0.
@@ -95,6 +97,11 @@ mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t nstored, cons
 
 /* Release a map.  The caller must ensure no enqueued work still reads it. */
 mcl_status mcl_map_free(mcl_map map);
+
+/* Device bytes a map holds: its values, coarse level and sentinels, plus the
+ * trilinear corner-cell copy once mcl_sensor_update_trilinear has built it.
+ * 0 for a NULL map. */
+size_t mcl_map_bytes(mcl_map map);
 
 /* Sensor update, endpoint model (§III, Eq. 3).  For every particle n:
  *     logw[n] = -(1 / (2 sigma^2)) * sum_k m(x_n, z_k)^2

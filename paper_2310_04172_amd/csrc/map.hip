@@ -242,11 +242,16 @@ extern "C" mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t ns
     if (nstored < 0) return fail(MCL_EINVAL, "map_upload_bricks: nstored must be >= 0");
     const int64_t nbx = (d.nx + 3) / 4, nby = (d.ny + 3) / 4, nbz = (d.nz + 3) / 4;
     const int64_t nbricks = nbx * nby * nbz;
-    if (nbricks >= ((int64_t)1 << 31) || nbz * nbx >= ((int64_t)1 << 24) || nstored + 2 >= ((int64_t)1 << 31))
-        return fail(MCL_ERANGE, "map_upload_bricks: too many bricks (need nbx*nby*nbz < 2^31, nbz*nbx < 2^24)");
+    // super-brick grid: kSX x kSY x kSZ voxels = (kSX/4) x (kSY/4) x (kSZ/4) listed bricks
+    constexpr int PX = kSX / 4, PY = kSY / 4, PZ = kSZ / 4;
+    const int64_t nsx = (nbx + PX - 1) / PX, nsy = (nby + PY - 1) / PY, nsz = (nbz + PZ - 1) / PZ;
+    const int64_t nsuper = nsx * nsy * nsz;
+    if (nbricks >= ((int64_t)1 << 31) || nsz * nsx >= ((int64_t)1 << 24) || nstored + 2 >= ((int64_t)1 << 31))
+        return fail(MCL_ERANGE, "map_upload_bricks: too many bricks (need nbx*nby*nbz < 2^31 and nx*nz < 2^29)");
     const int es = elem_size(d.dtype);
-    // which input brick sits at each brick index (-1: not stored)
+    // which input brick sits at each brick index (-1: not stored), and which super-bricks hold one
     std::vector<int32_t> at((size_t)nbricks, -1);
+    std::vector<uint8_t> held((size_t)nsuper, 0);
     for (int64_t i = 0; i < nstored; ++i) {
         const int32_t bx = brick_coords[3 * i], by = brick_coords[3 * i + 1], bz = brick_coords[3 * i + 2];
         if (bx < 0 || by < 0 || bz < 0 || bx >= nbx || by >= nby || bz >= nbz)
@@ -254,61 +259,85 @@ extern "C" mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t ns
         int32_t &slot = at[(size_t)(bz + nbz * (bx + nbx * (int64_t)by))];
         if (slot >= 0) return fail(MCL_EINVAL, "map_upload_bricks: brick " + std::to_string(i) + " listed twice");
         slot = (int32_t)i;
+        held[(size_t)(bz / PZ + nsz * (bx / PX + nsx * (int64_t)(by / PY)))] = 1;
     }
-    // rank table {mask, stored before} per 32 bricks, and the pool in brick-index order
-    const int64_t ngroups = (nbricks + 31) / 32;
-    std::vector<uint32_t> coarse((size_t)ngroups * 2, 0u);
-    const size_t brick_bytes = (size_t)64 * es;
-    const size_t pool_bytes = (size_t)(nstored + 2) * brick_bytes;
+    // the pool (slot 0 +Q, slot 1 zeros, then the stored super-bricks in index order)
+    int64_t nheld = 0;
+    for (uint8_t h : held) nheld += h;
+    const size_t super_bytes = (size_t)kSuperVals * es;
+    const size_t pool_bytes = (size_t)(nheld + 2) * super_bytes;
+    const bool small = pool_bytes < ((size_t)1 << 32);
+    if (!small && nheld + 2 >= ((int64_t)1 << 32)) return fail(MCL_ERANGE, "map_upload_bricks: too many stored super-bricks");
     std::vector<char> pool_h(pool_bytes, 0);
-    for (int w = 0; w < 64; ++w) {  // slot 0: +Q; slot 1 stays zero
-        if (d.dtype == MCL_TSDF_I16) reinterpret_cast<int16_t *>(pool_h.data())[w] = 32767;
-        else if (d.dtype == MCL_TSDF_I8) reinterpret_cast<int8_t *>(pool_h.data())[w] = 127;
-        else reinterpret_cast<float *>(pool_h.data())[w] = d.tau;
-    }
-    const char *src = static_cast<const char *>(brick_values);
-    uint32_t rank = 0;
-    for (int64_t g = 0; g < ngroups; ++g) {
-        uint32_t mask = 0;
-        coarse[(size_t)g * 2 + 1] = rank;
-        for (int k = 0; k < 32 && g * 32 + k < nbricks; ++k) {
-            const int32_t i = at[(size_t)(g * 32 + k)];
-            if (i < 0) continue;
-            mask |= 1u << k;
-            std::memcpy(pool_h.data() + (size_t)(2 + rank) * brick_bytes, src + (size_t)i * brick_bytes, brick_bytes);
-            ++rank;
+    auto fill_q = [&](char *dst) {
+        for (int w = 0; w < kSuperVals; ++w) {
+            if (d.dtype == MCL_TSDF_I16) reinterpret_cast<int16_t *>(dst)[w] = 32767;
+            else if (d.dtype == MCL_TSDF_I8) reinterpret_cast<int8_t *>(dst)[w] = 127;
+            else reinterpret_cast<float *>(dst)[w] = d.tau;
         }
-        coarse[(size_t)g * 2] = mask;
+    };
+    fill_q(pool_h.data());
+    // table: per super-brick the byte offset (or slot) of its pool slot; then outside, padding
+    std::vector<uint32_t> table((size_t)nsuper + 2, 0u);
+    auto entry = [&](int64_t slot) { return small ? (uint32_t)((size_t)slot * super_bytes) : (uint32_t)slot; };
+    table[(size_t)nsuper] = entry(0);
+    table[(size_t)nsuper + 1] = entry(1);
+    const char *src = static_cast<const char *>(brick_values);
+    int64_t next = 2;
+    for (int64_t si = 0; si < nsuper; ++si) {
+        if (!held[(size_t)si]) {
+            table[(size_t)si] = entry(0);
+            continue;
+        }
+        table[(size_t)si] = entry(next);
+        char *dst = pool_h.data() + (size_t)next * super_bytes;
+        ++next;
+        fill_q(dst);
+        const int64_t sz = si % nsz, rr = si / nsz, sx = rr % nsx, sy = rr / nsx;
+        for (int c = 0; c < PX * PY * PZ; ++c) {
+            const int64_t bx = sx * PX + c % PX, by = sy * PY + (c / PX) % PY, bz = sz * PZ + c / (PX * PY);
+            if (bx >= nbx || by >= nby || bz >= nbz) continue;
+            const int32_t i = at[(size_t)(bz + nbz * (bx + nbx * by))];
+            if (i < 0) continue;
+            const char *b = src + (size_t)i * 64 * es;  // listed brick, in-brick index x + 4 y + 16 z
+            for (int v = 0; v < 64; ++v) {
+                const int x = (int)(bx - sx * PX) * 4 + (v & 3), y = (int)(by - sy * PY) * 4 + ((v >> 2) & 3),
+                          z = (int)(bz - sz * PZ) * 4 + (v >> 4);
+                std::memcpy(dst + (size_t)(x + kSX * (y + kSY * z)) * es, b + (size_t)v * es, es);
+            }
+        }
     }
     mcl_map_s *m = new (std::nothrow) mcl_map_s();
     if (!m) return fail(MCL_ENOMEM, "map_upload_bricks: host allocation failed");
-    if (hipMalloc(&m->sp_coarse, coarse.size() * 4) != hipSuccess) {
+    if (hipMalloc(&m->sp_table, table.size() * 4) != hipSuccess) {
         delete m;
         return fail(MCL_ENOMEM, "map_upload_bricks: device allocation failed");
     }
     if (hipMalloc(&m->sp_pool, pool_bytes) != hipSuccess) {
-        (void)hipFree(m->sp_coarse);
+        (void)hipFree(m->sp_table);
         delete m;
         return fail(MCL_ENOMEM, "map_upload_bricks: device allocation failed");
     }
     hipStream_t stream = static_cast<hipStream_t>(stream_);
-    bool ok = hipMemcpyAsync(m->sp_coarse, coarse.data(), coarse.size() * 4, hipMemcpyHostToDevice, stream) == hipSuccess &&
+    bool ok = hipMemcpyAsync(m->sp_table, table.data(), table.size() * 4, hipMemcpyHostToDevice, stream) == hipSuccess &&
               hipMemcpyAsync(m->sp_pool, pool_h.data(), pool_bytes, hipMemcpyHostToDevice, stream) == hipSuccess &&
               hipStreamSynchronize(stream) == hipSuccess;
     if (!ok) {
-        (void)hipFree(m->sp_coarse);
+        (void)hipFree(m->sp_table);
         (void)hipFree(m->sp_pool);
         delete m;
         return fail(MCL_EDEVICE, "map_upload_bricks: copy to device failed");
     }
     fill_common(m, d);
     m->sparse = true;
-    m->bytes = coarse.size() * 4 + pool_bytes;
-    m->sp.coarse = static_cast<const uint2 *>(m->sp_coarse);
+    m->bytes = table.size() * 4 + pool_bytes;
+    m->sp.table = static_cast<const uint32_t *>(m->sp_table);
     m->sp.pool = static_cast<const char *>(m->sp_pool);
-    m->sp.nbz = (uint32_t)nbz;
-    m->sp.nbzx = (uint32_t)(nbz * nbx);
-    m->sp.small = (nstored + 2 < ((int64_t)1 << 24) && pool_bytes < ((size_t)1 << 32)) ? 1u : 0u;
+    m->sp.nsz = (uint32_t)nsz;
+    m->sp.nszx = (uint32_t)(nsz * nsx);
+    m->sp.outside = (uint32_t)nsuper;
+    m->sp.pad = (uint32_t)nsuper + 1;
+    m->sp.small = small ? 1u : 0u;
     *out = m;
     return MCL_OK;
 }
@@ -416,11 +445,13 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
     return MCL_OK;
 }
 
+extern "C" size_t mcl_map_bytes(mcl_map map) { return map ? map->bytes + map->tri_bytes : 0; }
+
 extern "C" mcl_status mcl_map_free(mcl_map map) {
     if (!map) return fail(MCL_EINVAL, "map_free: NULL map");
     hipError_t e = hipSuccess;
     if (map->dev) e = hipFree(map->dev);
-    if (map->sp_coarse && hipFree(map->sp_coarse) != hipSuccess) e = hipErrorInvalidValue;
+    if (map->sp_table && hipFree(map->sp_table) != hipSuccess) e = hipErrorInvalidValue;
     if (map->sp_pool && hipFree(map->sp_pool) != hipSuccess) e = hipErrorInvalidValue;
     if (map->tri_dev && hipFree(map->tri_dev) != hipSuccess) e = hipErrorInvalidValue;
     if (map->free_prefix && hipFree(map->free_prefix) != hipSuccess) e = hipErrorInvalidValue;

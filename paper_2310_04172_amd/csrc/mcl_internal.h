@@ -87,19 +87,29 @@ constexpr int kCellBrickLog2 = kCLX + kCLY + kCLZ;
 constexpr int kCellBrickVals = 1 << kCellBrickLog2;
 
 // Sparse coarse/fine map (§III: the map holds fine data only for the coarse
-// cells with distances inside the truncation band, after Akai et al.): a pool
-// of the stored 4x4x4 bricks (64 values each, in brick-index order) and a
-// coarse rank table: per 32 consecutive brick indices a 32-bit mask of the
-// stored ones and the number stored before them, 8 bytes per 32 bricks, so the
-// table of a 2-million-brick map is 0.5 MB and stays in L2.  A stored brick's
-// slot is 2 + base + popcount(mask below it); slot 0 is a brick of +Q
-// (unstored bricks, points outside the map), slot 1 a brick of zeros (padding
-// lanes).  A lookup is two dependent gathers (rank entry, then value).
+// cells with distances inside the truncation band, after Akai et al.).  The
+// caller lists 4x4x4 bricks; the library stores them in super-bricks of
+// SX x SY x SZ voxels (flat, like the dense bricks and for the same reason: the
+// beams of one gather fall in fewer lines), a super-brick being stored when
+// any of its bricks is listed, its unlisted bricks holding +Q.  A pool of the
+// stored super-bricks (x fastest inside) and the coarse level: a table with one
+// 32-bit entry per super-brick (super index = sz + nsz (sx + nsx sy)), the byte
+// offset of its slot in the pool, or of slot 0 (all +Q) when it is not stored.
+// Two more entries follow for points outside the map (slot 0) and for padding
+// lanes (slot 1, all zeros).  With super-bricks the table is small (0.5 MiB for a
+// 1024 x 1024 x 128 map) and stays in L2, so a lookup is two dependent gathers
+// (table entry, then value) and no rank arithmetic.  Pools of 4 GiB and more
+// keep slot numbers in the table and 64-bit addresses.
+constexpr int kSLX = 3, kSLY = 5, kSLZ = 2;                      // log2 of the super-brick shape (voxels)
+constexpr int kSX = 1 << kSLX, kSY = 1 << kSLY, kSZ = 1 << kSLZ;
+constexpr int kSuperLog2 = kSLX + kSLY + kSLZ;
+constexpr int kSuperVals = 1 << kSuperLog2;
 struct SparseView {
-    const uint2 *coarse;     // device [2 ngroups]: {mask, stored before} per 32 bricks
-    const char *pool;        // device [nslots][64] values
-    uint32_t nbz, nbzx;      // brick index = bz + nbz bx + nbz nbx by (both < 2^24)
-    uint32_t small;          // pool below 2^24 slots and 4 GiB: 32-bit offsets
+    const uint32_t *table;   // device [nsuper + 2]: byte offset (or slot, wide pools) per super-brick
+    const char *pool;        // device [nslots][kSuperVals] values
+    uint32_t nsz, nszx;      // super index = sz + nsz sx + nsz nsx sy (both < 2^24)
+    uint32_t outside, pad;   // table indices of the outside (+Q) and padding (zero) entries
+    uint32_t small;          // pool below 4 GiB: the table holds byte offsets
 };
 
 }  // namespace mcl
@@ -121,7 +131,7 @@ struct mcl_map_s {
     uint64_t free_total;
     bool sparse;        // coarse table + brick pool (view.base and view.mask unused)
     mcl::SparseView sp;
-    void *sp_coarse, *sp_pool;
+    void *sp_table, *sp_pool;
 };
 
 namespace mcl {

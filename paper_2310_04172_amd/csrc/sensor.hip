@@ -279,9 +279,9 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_tri(const 
     return s;
 }
 
-// Sparse map (rank table + brick pool): the brick's rank entry first, then the
-// value in the pool; points outside the map read slot 0 (the +Q brick) and
-// padding slots slot 1 (zeros).  Same index recipe, values and summation order
+// Sparse map (offset table + super-brick pool): the super-brick's table entry
+// first, then the value in the pool; points outside the map read slot 0 (+Q)
+// and padding slots slot 1 (zeros).  Same index recipe, values and summation order
 // as the dense layout, so a map gives the same bits in either form.
 template <typename T>
 __device__ inline int load_raw64(const char *p) {
@@ -296,7 +296,8 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_sparse(con
                                                                              const float (&A)[12], const float (&px)[kU],
                                                                              const float (&py)[kU], const float (&pz)[kU],
                                                                              int lane, int nvalid) {
-    uint32_t bidx[kU], wv[kU], sel[kU];  // sel: 0 inside, 1 outside (+Q), 2 padding (0)
+    constexpr uint32_t ES = sizeof(T);
+    uint32_t sidx[kU], wv[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const float gx = grid_coord(A[0], A[1], A[2], A[9], px[u], py[u], pz[u]);
@@ -304,35 +305,26 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_sparse(con
         const float gz = grid_coord(A[6], A[7], A[8], A[11], px[u], py[u], pz[u]);
         uint32_t ix, iy, iz;
         const bool ok = voxel_ijk(m, gx, gy, gz, ix, iy, iz);
-        const uint32_t b = __umul24(ix >> 2, sp.nbz) + __umul24(iy >> 2, sp.nbzx) + (iz >> 2);
-        bidx[u] = ok ? b : 0u;  // any entry in range; outside lanes ignore it
-        sel[u] = ok ? 0u : 1u;
-        if (TAIL) sel[u] = (u * kWave + lane < nvalid) ? sel[u] : 2u;
-        wv[u] = (ix & 3u) + ((iy & 3u) << 2) + ((iz & 3u) << 4);
+        uint32_t b = __umul24(ix >> kSLX, sp.nsz) + __umul24(iy >> kSLY, sp.nszx) + (iz >> kSLZ);
+        b = ok ? b : sp.outside;
+        if (TAIL) b = (u * kWave + lane < nvalid) ? b : sp.pad;
+        sidx[u] = b;
+        wv[u] = ((ix & (kSX - 1u)) + ((iy & (kSY - 1u)) << kSLX) + ((iz & (kSZ - 1u)) << (kSLX + kSLY))) * ES;
     }
-    // each group of 64 bricks is two half-entries {mask of 32 bricks, stored before them}
-    uint2 ent[kU];
+    uint32_t ent[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) ent[u] = sp.coarse[bidx[u] >> 5];
+    for (int u = 0; u < kU; ++u) ent[u] = gp(sp.table)[sidx[u]];
     __builtin_amdgcn_sched_barrier(0);
-    uint32_t slot[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const uint32_t k = bidx[u] & 31u;
-        const uint32_t below = (uint32_t)__popc(ent[u].x & ((1u << k) - 1u));
-        const uint32_t s0 = (ent[u].x >> k) & 1u ? 2u + ent[u].y + below : 0u;
-        slot[u] = sel[u] == 0u ? s0 : sel[u] - 1u;
-    }
     int raw[kU];
     if constexpr (!WIDE) {
-        // pool below 2^24 slots and 4 GiB: 24-bit multiplies and 32-bit offsets
+        // pool below 4 GiB: the entry is the slot's byte offset; slot 0 (+Q)
+        // is read at its first value, so such lanes share one line
 #pragma unroll
-        for (int u = 0; u < kU; ++u)
-            raw[u] = load_raw<T>(sp.pool, __umul24(slot[u], 64u * sizeof(T)) + wv[u] * (uint32_t)sizeof(T));
+        for (int u = 0; u < kU; ++u) raw[u] = load_raw<T>(sp.pool, ent[u] ? ent[u] + wv[u] : 0u);
     } else {
 #pragma unroll
         for (int u = 0; u < kU; ++u)
-            raw[u] = load_raw64<T>(sp.pool + ((uint64_t)slot[u] * (64u * sizeof(T)) + wv[u] * (uint32_t)sizeof(T)));
+            raw[u] = load_raw64<T>(sp.pool + (ent[u] ? (uint64_t)ent[u] * ((uint32_t)kSuperVals * ES) + wv[u] : 0u));
     }
     __builtin_amdgcn_sched_barrier(0);
     float s = 0.0f;

@@ -66,6 +66,8 @@ _lib.mcl_debug_philox.argtypes = [_P, _P]
 _lib.mcl_tick.argtypes = [C.POINTER(FilterJob), _I, _I, _P]
 _lib.mcl_job_bytes.argtypes = [_I, _I]
 _lib.mcl_job_bytes.restype = C.c_size_t
+_lib.mcl_map_bytes.argtypes = [_P]
+_lib.mcl_map_bytes.restype = C.c_size_t
 _lib.mcl_autotune.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P, C.POINTER(LaunchConfig)]
 _lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_last_error.restype = C.c_char_p
@@ -162,6 +164,10 @@ class Map:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def device_bytes(self) -> int:
+        return int(_lib.mcl_map_bytes(self._h))
 
     def close(self):
         if getattr(self, "_h", None):

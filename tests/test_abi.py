@@ -28,7 +28,7 @@ def test_header_declares_the_boundary():
     for f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
               "mcl_debug_voxel_indices", "mcl_last_error", "mcl_tick", "mcl_job_bytes", "mcl_autotune",
               "mcl_set_launch_config", "mcl_pose_estimate", "mcl_sensor_update_trilinear", "mcl_motion_update",
-              "mcl_init_uniform", "mcl_map_upload_bricks"):
+              "mcl_init_uniform", "mcl_map_upload_bricks", "mcl_map_bytes"):
         assert f in names
 
 
@@ -112,6 +112,7 @@ def test_tick_and_tuning_argument_errors(mcl):
     jobs[1].est_idx = P(0x7100)
     assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL and b"without est_mean" in lib.mcl_last_error()
     assert lib.mcl_job_bytes(0, 5) == 0
+    assert lib.mcl_map_bytes(None) == 0
     assert lib.mcl_job_bytes(1000, 28800) > 1000 * 120
     bad = mcl.LaunchConfig(3, 0)
     assert lib.mcl_set_launch_config(0, 1000, 1000, C.byref(bad)) == mcl.MCL_EINVAL

@@ -120,7 +120,10 @@ def test_global_workload_sparse_equals_dense(torch, mcl):
     ld = mcl.sensor_update(dm, X, P, w.sigma).cpu().numpy()
     assert np.array_equal(ls.view(np.uint32), ld.view(np.uint32))
     nb = ((w.tmap.nx + 3) // 4) * ((w.tmap.ny + 3) // 4) * ((w.tmap.nz + 3) // 4)
-    say(f"stored bricks {co.shape[0]} of {nb} ({co.shape[0] / nb:.1%})")
+    say(f"stored bricks {co.shape[0]} of {nb} ({co.shape[0] / nb:.1%}); device bytes sparse {sm.device_bytes}, "
+        f"dense {dm.device_bytes}")
+    # listed values (2 B each) <= sparse footprint < dense footprint
+    assert co.shape[0] * 64 * 2 <= sm.device_bytes < dm.device_bytes // 2
 
 
 def test_sparse_guards(torch, mcl):
