@@ -26,8 +26,8 @@ constexpr int kWave = 64;
 // Why this shape: the texture units spend their cycles per cache line a
 // wave-wide gather touches.  The 64 lanes of a gather hold consecutive beams of
 // one LiDAR ring, which sweep sideways at nearly one height; flat, elongated
-// bricks put those points in fewer value lines, and a brick class byte (below)
-// then covers a larger horizontal patch, so the class lines touched per gather
+// bricks put those points in fewer value lines, and a brick read mask (below)
+// then covers a larger horizontal patch, so the mask lines touched per gather
 // drop too.  Measured against 4 x 4 x 4 bricks on a 1024 x 1024 x 128 map with
 // a VLP-16-shaped scan, 10^6 particles: 12 % less time under global
 // localisation, 32 % less with the particles converged round one pose.
@@ -59,7 +59,7 @@ struct MapView {
     uint32_t nrwords;        // words of rbits (bricks + 2 sentinels, rounded up to 32)
 };
 // Largest read-bit table the sensor kernel copies into LDS (bytes); maps with
-// more bricks use the class bytes in global memory.
+// more bricks use the mask bytes in global memory.
 constexpr uint32_t kMaxLdsBits = 64 * 1024;
 
 // The map for the trilinear lookup, one gather per point: cell (i, j, k) holds
