@@ -156,3 +156,38 @@ def test_tick_on_one_map_modes_agree(torch, mcl):
                 assert np.array_equal(got.view(np.uint32), singles[i].view(np.uint32)), (mode, i)
     finally:
         mcl.set_launch_config("i16", 5000, 3000, None)
+
+
+def test_tick_graph_replay_follows_the_map(torch, mcl):
+    """A graph captured for a tick on map A replays for the same sizes on map B
+    (same dimensions, other values): the LDS read bits must be B's.  Every
+    replay is checked against the single-filter calls, with eager work between
+    the replays."""
+    say("case: tick graph replay across maps of one size")
+    rng = np.random.default_rng(9)
+    dims = (40, 70, 30)
+    maps = []
+    for k in range(2):
+        tmap = banded_map(rng, dims, "i16")
+        if k == 1:  # flip which slabs hold band values
+            tmap.values[...] = np.roll(tmap.values, 3, axis=0)
+        maps.append(mcl.Map.from_tsdf(tmap))
+    ext = np.array(dims) * 0.1
+    s = torch.cuda.Stream()
+    for rep, mi in enumerate((0, 1, 0, 1)):
+        filters = []
+        for i, (N, K) in enumerate([(2000, 3000), (300, 5000)]):
+            t = ext * 0.5 + rng.normal(0, 0.05, (N, 3)) if i else rng.uniform(0, 1, (N, 3)) * ext
+            poses = poses_from(random_rotations(rng, N), t)
+            pts = rng.normal(0, 0.3 * ext.mean(), (3, K)).astype(np.float32)
+            filters.append(mcl.Filter(maps[mi], dev(torch, pts), dev(torch, poses), f32(0.15),
+                                      int(rng.integers(0, 2 ** 63))))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            mcl.tick(filters, graph=True, stream=s)
+        s.synchronize()
+        got = [f.logw.cpu().numpy() for f in filters]
+        _ = torch.ones(1 << 20, device="cuda").sum().item()
+        for i, f in enumerate(filters):
+            ref = mcl.sensor_update(f.map, f.points, f.poses, f.sigma).cpu().numpy()
+            assert np.array_equal(got[i].view(np.uint32), ref.view(np.uint32)), (rep, i)
