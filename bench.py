@@ -96,20 +96,45 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per sensor launch from the committed counter summary, if it was taken
-    on the kernel sources as they are now (else None)."""
+def profiled_counters():
+    """The committed counter summary of the sensor kernel, if it was taken on the
+    kernel sources as they are now (else None)."""
     path = os.path.join(ROOT, "profiles", "sensor_kernel_global_counters.txt")
     try:
         text = open(path).read()
     except OSError:
         return None
-    if kernel_source_hash() not in text:
-        return None
-    for line in text.splitlines():
+    return text if kernel_source_hash() in text else None
+
+
+def profiled_traffic():
+    """HBM bytes per sensor launch from the committed counter summary (or None)."""
+    text = profiled_counters()
+    for line in (text or "").splitlines():
         if line.startswith("traffic_bytes_per_launch:"):
             return float(line.split(":")[1])
     return None
+
+
+def profiled_limiter():
+    """Busy fractions of the units that bound the sensor kernel, from the committed
+    counter summary (or None): the texture-data path returning the gathered
+    values, the texture-address path issuing them, and VALU lane utilisation."""
+    text = profiled_counters()
+    if text is None:
+        return None
+    out = {}
+    for line in text.splitlines():
+        t = line.split()
+        if len(t) >= 4 and t[0] in ("TD_TD_BUSY_sum", "TA_TA_BUSY_sum") and t[2] == "->":
+            out["td_busy" if t[0].startswith("TD") else "ta_busy"] = float(t[3].rstrip("%")) / 100.0
+        if len(t) >= 2 and t[0] == "VALUUtilization":
+            out["valu_lane_utilisation"] = float(t[1]) / 100.0
+    if not out:
+        return None
+    out["unit"] = "texture data path (gathers)"
+    out["source"] = "profiles/sensor_kernel_global_counters.txt"
+    return out
 
 
 def percentile(xs, q):
@@ -217,6 +242,8 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
                            "traffic": profiled_traffic() if workload_key == "global" else None,
                            "kernel": "sensor_kernel", "algorithmic_flops_per_launch": flops,
                            "algorithmic_tsdf_bytes_per_launch": 2.0 * evals}
+        if workload_key == "global":
+            out["roofline"]["limiter"] = profiled_limiter()
     return out
 
 
