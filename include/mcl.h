@@ -84,7 +84,7 @@ mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_values, voi
  * number of stored bricks (the library keeps them in 8x32x4-voxel blocks, a
  * block being stored when any of its bricks is listed; mcl_map_bytes reports
  * the total), and the map may exceed the 4 GiB limit of the dense layout
- * (limits: nbx*nby*nbz < 2^31 bricks, nx*nz < 2^29 voxels).  The sensor
+ * (limits: nbx*nby*nbz < 2^31 bricks, ceil(nx/8)*ceil(ny/32) < 2^24).  The sensor
  * update gives exactly the results of the dense map with the same values; the
  * trilinear lookup, the uniform initialisation and mcl_tick reject sparse maps.
  *   nstored:      number of listed bricks, >= 0.
@@ -280,11 +280,12 @@ size_t mcl_job_bytes(int32_t N, int32_t K);
 /* --------------------------------------------------------------- tuning
  * Launch shape of the sensor kernel: waves per workgroup (2, 4, 8) and, for a
  * persistent grid, workgroups per compute unit (0 = one wave per work item);
- * where the nearest lookup of a single-filter call reads the map's coarse
- * level: 0 = chosen per wave and chunk (default), 1 = bytes in global memory,
- * 2 = bits copied into LDS (only for maps whose bit table fits 64 KiB; larger
- * maps and mcl_tick always use 1).  No setting changes results (the summation
- * order depends only on K). */
+ * where the nearest lookup reads the map's coarse level: 0 = chosen per wave
+ * and chunk (default), 1 = bytes in global memory, 2 = bits copied into LDS
+ * (only for maps whose bit table fits 64 KiB, and in mcl_tick only for a
+ * storage type whose filters all share one map; otherwise 1).  Sparse maps
+ * use a fixed shape.  No setting changes results (the summation order depends
+ * only on K). */
 typedef struct {
     int32_t waves_per_block;
     int32_t blocks_per_cu;

@@ -246,8 +246,9 @@ extern "C" mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t ns
     constexpr int PX = kSX / 4, PY = kSY / 4, PZ = kSZ / 4;
     const int64_t nsx = (nbx + PX - 1) / PX, nsy = (nby + PY - 1) / PY, nsz = (nbz + PZ - 1) / PZ;
     const int64_t nsuper = nsx * nsy * nsz;
-    if (nbricks >= ((int64_t)1 << 31) || nsz * nsx >= ((int64_t)1 << 24) || nstored + 2 >= ((int64_t)1 << 31))
-        return fail(MCL_ERANGE, "map_upload_bricks: too many bricks (need nbx*nby*nbz < 2^31 and nx*nz < 2^29)");
+    if (nbricks >= ((int64_t)1 << 31) || nsx * nsy >= ((int64_t)1 << 24) || nstored + 2 >= ((int64_t)1 << 31))
+        return fail(MCL_ERANGE,
+                    "map_upload_bricks: too many bricks (need nbx*nby*nbz < 2^31 and ceil(nx/8)*ceil(ny/32) < 2^24)");
     const int es = elem_size(d.dtype);
     // which input brick sits at each brick index (-1: not stored), and which super-bricks hold one
     std::vector<int32_t> at((size_t)nbricks, -1);
@@ -259,7 +260,7 @@ extern "C" mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t ns
         int32_t &slot = at[(size_t)(bz + nbz * (bx + nbx * (int64_t)by))];
         if (slot >= 0) return fail(MCL_EINVAL, "map_upload_bricks: brick " + std::to_string(i) + " listed twice");
         slot = (int32_t)i;
-        held[(size_t)(bz / PZ + nsz * (bx / PX + nsx * (int64_t)(by / PY)))] = 1;
+        held[(size_t)(bx / PX + nsx * (by / PY + nsy * (int64_t)(bz / PZ)))] = 1;
     }
     // the pool (slot 0 +Q, slot 1 zeros, then the stored super-bricks in index order)
     int64_t nheld = 0;
@@ -293,7 +294,7 @@ extern "C" mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t ns
         char *dst = pool_h.data() + (size_t)next * super_bytes;
         ++next;
         fill_q(dst);
-        const int64_t sz = si % nsz, rr = si / nsz, sx = rr % nsx, sy = rr / nsx;
+        const int64_t sx = si % nsx, rr = si / nsx, sy = rr % nsy, sz = rr / nsy;
         for (int c = 0; c < PX * PY * PZ; ++c) {
             const int64_t bx = sx * PX + c % PX, by = sy * PY + (c / PX) % PY, bz = sz * PZ + c / (PX * PY);
             if (bx >= nbx || by >= nby || bz >= nbz) continue;
@@ -333,8 +334,8 @@ extern "C" mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t ns
     m->bytes = table.size() * 4 + pool_bytes;
     m->sp.table = static_cast<const uint32_t *>(m->sp_table);
     m->sp.pool = static_cast<const char *>(m->sp_pool);
-    m->sp.nsz = (uint32_t)nsz;
-    m->sp.nszx = (uint32_t)(nsz * nsx);
+    m->sp.nsx = (uint32_t)nsx;
+    m->sp.nsxy = (uint32_t)(nsx * nsy);
     m->sp.outside = (uint32_t)nsuper;
     m->sp.pad = (uint32_t)nsuper + 1;
     m->sp.small = small ? 1u : 0u;

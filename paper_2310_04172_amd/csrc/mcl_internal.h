@@ -93,8 +93,12 @@ constexpr int kCellBrickVals = 1 << kCellBrickLog2;
 // beams of one gather fall in fewer lines), a super-brick being stored when
 // any of its bricks is listed, its unlisted bricks holding +Q.  A pool of the
 // stored super-bricks (x fastest inside) and the coarse level: a table with one
-// 32-bit entry per super-brick (super index = sz + nsz (sx + nsx sy)), the byte
-// offset of its slot in the pool, or of slot 0 (all +Q) when it is not stored.
+// 32-bit entry per super-brick, the byte offset of its slot in the pool, or of
+// slot 0 (all +Q) when it is not stored.  The table runs x fastest, then y,
+// then z (super index = sx + nsx (sy + nsy sz)): a 128-byte line of entries is
+// a 12.8 m x 1.6 m strip (at 5 cm voxels) of one height layer, and the beams of
+// one gather sweep sideways at nearly one height, so they share few lines
+// (2.4 lines per gather on the warehouse workload against 3.8 with z fastest).
 // Two more entries follow for points outside the map (slot 0) and for padding
 // lanes (slot 1, all zeros).  With super-bricks the table is small (0.5 MiB for a
 // 1024 x 1024 x 128 map) and stays in L2, so a lookup is two dependent gathers
@@ -107,7 +111,7 @@ constexpr int kSuperVals = 1 << kSuperLog2;
 struct SparseView {
     const uint32_t *table;   // device [nsuper + 2]: byte offset (or slot, wide pools) per super-brick
     const char *pool;        // device [nslots][kSuperVals] values
-    uint32_t nsz, nszx;      // super index = sz + nsz sx + nsz nsx sy (both < 2^24)
+    uint32_t nsx, nsxy;      // super index = sx + nsx sy + nsx nsy sz (both < 2^24)
     uint32_t outside, pad;   // table indices of the outside (+Q) and padding (zero) entries
     uint32_t small;          // pool below 4 GiB: the table holds byte offsets
 };

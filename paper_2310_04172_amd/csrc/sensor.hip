@@ -305,7 +305,7 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_sparse(con
         const float gz = grid_coord(A[6], A[7], A[8], A[11], px[u], py[u], pz[u]);
         uint32_t ix, iy, iz;
         const bool ok = voxel_ijk(m, gx, gy, gz, ix, iy, iz);
-        uint32_t b = __umul24(ix >> kSLX, sp.nsz) + __umul24(iy >> kSLY, sp.nszx) + (iz >> kSLZ);
+        uint32_t b = (ix >> kSLX) + __umul24(iy >> kSLY, sp.nsx) + __umul24(iz >> kSLZ, sp.nsxy);
         b = ok ? b : sp.outside;
         if (TAIL) b = (u * kWave + lane < nvalid) ? b : sp.pad;
         sidx[u] = b;
@@ -336,7 +336,7 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_sparse(con
     return s;
 }
 
-// Lookup kinds of the sensor kernel (sparse: pools below / above 2^24 slots or 4 GiB).
+// Lookup kinds of the sensor kernel (sparse: pools below / above 4 GiB).
 constexpr int kLookNearest = 0, kLookTrilinear = 1, kLookSparse = 2, kLookSparseWide = 3, kLookNearestLds = 4;
 
 // Particles [p0, p1) of the wave's group against one chunk, with lookup LK
@@ -449,15 +449,29 @@ __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJ
 // read into scalar registers per item and read again for the store, so it need
 // not stay live across the item.
 template <typename T, int WPB, typename Src, int LK = kLookNearest>
-__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == kLookTrilinear ? 2 : (LK == kLookNearest || LK == kLookNearestLds) ? 4 : 3))) void sensor_kernel(Src src) {
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == kLookTrilinear ? 2 : (LK == kLookNearest || LK == kLookNearestLds || LK == kLookSparse) ? 4 : 3))) void sensor_kernel(Src src) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nitems = src.items();
     const int64_t stride = (int64_t)gridDim.x * WPB;
-    extern __shared__ uint32_t sbits[];
+    extern __shared__ __align__(16) uint32_t sbits[];
     if constexpr (LK == kLookNearestLds) {
-        // one map per launch (single-filter calls): its read bits into LDS
+        // one map per launch: its read bits into LDS, in 16-byte pieces, four
+        // loads in flight per thread before the stores (the bit table sits in
+        // a 256-byte aligned, 256-byte padded region; the LDS allocation is
+        // rounded up to 16 bytes).  Indexes past the end are clamped to the
+        // last piece, which is then loaded and stored again with its own value.
         const SensorJob J0 = src.load(0);
-        for (uint32_t w = threadIdx.x; w < J0.map.nrwords; w += WPB * 64) sbits[w] = gp(J0.map.rbits)[w];
+        const uint32_t n4 = (J0.map.nrwords + 3u) >> 2;
+        const u32x4 *from = reinterpret_cast<const u32x4 *>(J0.map.rbits);
+        u32x4 *to = reinterpret_cast<u32x4 *>(sbits);
+        constexpr uint32_t kT = WPB * 64;
+        for (uint32_t w0 = threadIdx.x; w0 < n4; w0 += 4 * kT) {
+            u32x4 v[4];
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) v[i] = gp(from)[min(w0 + i * kT, n4 - 1u)];
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) to[min(w0 + i * kT, n4 - 1u)] = v[i];
+        }
         __syncthreads();
     }
     for (int64_t item = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems;
@@ -606,9 +620,10 @@ mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, cons
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
     const int64_t nitems = (int64_t)src.job.ngroups * npiece;
     src.n = Counts{1, nitems, N, 0};
-    if (!map->sparse && (size_t)map->view.nrwords * 4 <= kMaxLdsBits && cfg.coarse != kCoarseBytes) {
+    const size_t lds_bytes = (((size_t)map->view.nrwords + 3) & ~(size_t)3) * 4;  // 16-byte pieces
+    if (!map->sparse && lds_bytes <= kMaxLdsBits && cfg.coarse != kCoarseBytes) {
         src.job.coarse = cfg.coarse;
-        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, (size_t)map->view.nrwords * 4);
+        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, lds_bytes);
     }
     if (!map->sparse) return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, 0);
     // sparse map: one wave per work item, four waves per workgroup

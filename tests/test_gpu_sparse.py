@@ -40,6 +40,10 @@ def sparse_of(mcl, tmap, coords, values):
     return mcl.Map.from_bricks(tmap.dims, tmap.voxel, tmap.origin, tmap.tau, tmap.dtype, coords, values)
 
 
+def assert_bits(got, ref, what):
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), what
+
+
 def case(seed, dims, dtype, N, K):
     rng = np.random.default_rng(seed)
     nx, ny, nz = dims
@@ -68,12 +72,57 @@ def test_sparse_matches_oracle_and_dense(torch, mcl, oracle_lib, N, K, dtype):
     sm = sparse_of(mcl, tmap, co, va)
     dm = mcl.Map.from_tsdf(tmap)
     X, P = dev(torch, pts), dev(torch, poses)
-    ls = mcl.sensor_update(sm, X, P, f32(0.15)).cpu().numpy()
     ld = mcl.sensor_update(dm, X, P, f32(0.15)).cpu().numpy()
-    assert np.array_equal(ls.view(np.uint32), ld.view(np.uint32))
+    ls = mcl.sensor_update(sm, X, P, f32(0.15)).cpu().numpy()
+    assert_bits(ls, ld, "sparse vs dense")
     ref = oracle_lib.sensor_update_bricks(tmap.dims, tmap.voxel, tmap.origin, tmap.tau, dtype, co, va, pts, poses,
                                           f32(0.15))
     assert np.all(np.abs(ls - ref) <= RTOL * np.abs(ref))
+
+
+def banded_case(seed, dims, dtype, N, K, clustered):
+    """Values inside the band only in thin z slabs and one x half, +-Q
+    elsewhere: many blocks are not stored, so the offset table mixes stored
+    and unstored entries along every axis."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    Q = {"i16": 32767, "i8": 127, "f32": np.float32(0.3)}[dtype]
+    np_t = {"i16": np.int16, "i8": np.int8, "f32": np.float32}[dtype]
+    vals = np.where(rng.random((nz, ny, nx)) < 0.5, Q, -Q).astype(np_t)
+    for z0 in range(2, nz, 11):
+        band = vals[z0:z0 + 2, :, : nx // 2]
+        if dtype == "f32":
+            band[...] = rng.uniform(-0.3, 0.3, band.shape)
+        else:
+            band[...] = rng.integers(-Q, Q + 1, band.shape)
+    tmap = make_map(vals, 0.1, origin=(-0.3, 0.2, -0.1), tau=0.3, dtype=dtype)
+    ext = np.array(dims) * 0.1
+    if clustered:
+        c = rng.uniform(0.3, 0.7, 3) * ext
+        t = c + rng.normal(0, 0.05, (N, 3))
+        rot = random_rotations(rng, 1)
+        poses = poses_from(np.repeat(rot, N, axis=0), t)
+    else:
+        poses = poses_from(random_rotations(rng, N), rng.uniform(0, 1, (N, 3)) * ext)
+    pts = rng.normal(0, 0.3 * ext.mean(), (3, K)).astype(np.float32)
+    return tmap, pts, poses
+
+
+@pytest.mark.parametrize("N,K", [(65, 4097), (200, 9000)])
+@pytest.mark.parametrize("dtype", ["i16", "i8", "f32"])
+@pytest.mark.parametrize("clustered", [False, True])
+def test_stored_blocks_with_gaps(torch, mcl, oracle_lib, N, K, dtype, clustered):
+    say(f"case: sparse banded N={N} K={K} {dtype} clustered={clustered}")
+    tmap, pts, poses = banded_case(7 * N + K, (203, 150, 45), dtype, N, K, clustered)
+    co, va = to_bricks(tmap)
+    sm = sparse_of(mcl, tmap, co, va)
+    dm = mcl.Map.from_tsdf(tmap)
+    X, P = dev(torch, pts), dev(torch, poses)
+    ld = mcl.sensor_update(dm, X, P, f32(0.15)).cpu().numpy()
+    assert_bits(mcl.sensor_update(sm, X, P, f32(0.15)).cpu().numpy(), ld, "banded sparse vs dense")
+    ref = oracle_lib.sensor_update_bricks(tmap.dims, tmap.voxel, tmap.origin, tmap.tau, dtype, co, va, pts, poses,
+                                          f32(0.15))
+    assert np.all(np.abs(ld - ref) <= RTOL * np.abs(ref))
 
 
 def test_empty_listing_reads_q(torch, mcl, oracle_lib):
@@ -109,6 +158,40 @@ def test_map_beyond_the_dense_limit(torch, mcl, oracle_lib):
     assert np.unique(np.round(ref, 3)).size > N // 2     # the region is actually read
 
 
+def test_pool_past_4gib(torch, mcl, oracle_lib):
+    """float32 blocks of 8 x 32 x 4 voxels take 4 KiB each, so 1.2 M stored
+    blocks make a pool past 4 GiB: the table then holds slot numbers and the
+    lookup forms 64-bit addresses.  One brick listed per block for y < 120 m,
+    every brick of a region round the particles; parity with the oracle."""
+    say("case: sparse pool past 4 GiB (float32, 1.2 M stored blocks)")
+    rng = np.random.default_rng(31)
+    dims = (4096, 4096, 128)
+    nbx, nby, nbz = 1024, 1024, 32
+    listed = np.zeros((nbz, nby, nbx), bool)
+    listed[:, 0:600:8, 0::2] = True           # the first brick of every block with block y < 75
+    listed[4:20, 400:440, 800:840] = True     # all bricks of the region
+    bz, by, bx = np.nonzero(listed)
+    co = np.stack([bx, by, bz], 1).astype(np.int32)
+    del listed
+    tau = f32(0.15)
+    va = rng.uniform(-0.15, 0.15, (co.shape[0], 64)).astype(np.float32)
+    v = f32(0.05)
+    sm = mcl.Map.from_bricks(dims, v, (0.0, 0.0, 0.0), tau, "f32", co, va)
+    say(f"stored bricks {co.shape[0]}, device bytes {sm.device_bytes}")
+    assert sm.device_bytes > 2 ** 32
+    lo = np.array([800 * 4, 400 * 4, 4 * 4]) * v
+    hi = np.array([840 * 4, 440 * 4, 20 * 4]) * v
+    N, K = 130, 3000
+    poses = poses_from(random_rotations(rng, N), rng.uniform(lo, hi, (N, 3)))
+    pts = rng.normal(0, 1.5, (3, K)).astype(np.float32)
+    ls = mcl.sensor_update(sm, dev(torch, pts), dev(torch, poses), f32(0.075)).cpu().numpy()
+    del sm
+    ref = oracle_lib.sensor_update_bricks(dims, v, (0.0, 0.0, 0.0), tau, "f32", co, va, pts, poses, f32(0.075),
+                                          nthreads=8)
+    assert np.all(np.abs(ls - ref) <= RTOL * np.abs(ref))
+    assert np.unique(np.round(ref, 3)).size > N // 2
+
+
 def test_global_workload_sparse_equals_dense(torch, mcl):
     w = configs.config2()
     say("case: sparse warehouse map, N = 10^6")
@@ -116,9 +199,13 @@ def test_global_workload_sparse_equals_dense(torch, mcl):
     sm = sparse_of(mcl, w.tmap, co, va)
     dm = mcl.Map.from_tsdf(w.tmap)
     X, P = dev(torch, w.points), dev(torch, w.poses)
-    ls = mcl.sensor_update(sm, X, P, w.sigma).cpu().numpy()
     ld = mcl.sensor_update(dm, X, P, w.sigma).cpu().numpy()
-    assert np.array_equal(ls.view(np.uint32), ld.view(np.uint32))
+    assert_bits(mcl.sensor_update(sm, X, P, w.sigma).cpu().numpy(), ld, "global workload")
+    # particles converged round the true pose (most points in the band)
+    xyz, rpy = configs.gaussian_particles(np.random.default_rng(4), *w.gt, w.N, s_xyz=0.05, s_rpy_deg=1.0)
+    Pc = dev(torch, configs.poses_soa(xyz, rpy))
+    ldc = mcl.sensor_update(dm, X, Pc, w.sigma).cpu().numpy()
+    assert_bits(mcl.sensor_update(sm, X, Pc, w.sigma).cpu().numpy(), ldc, "global workload, converged")
     nb = ((w.tmap.nx + 3) // 4) * ((w.tmap.ny + 3) // 4) * ((w.tmap.nz + 3) // 4)
     say(f"stored bricks {co.shape[0]} of {nb} ({co.shape[0] / nb:.1%}); device bytes sparse {sm.device_bytes}, "
         f"dense {dm.device_bytes}")
