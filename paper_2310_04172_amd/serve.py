@@ -4,10 +4,11 @@ Requests (a robot's new scan) arrive over time.  The engine keeps every
 admitted robot's particle set resident in device memory and, whenever one of
 its streams is free, gathers the waiting requests of robots that are not
 already on the GPU into one batched tick (``mcl_tick``: sensor update,
-normalisation and resampling of every filter in one launch per stage).  Two
-streams let a new tick start while the previous one still runs, so requests
-that arrive meanwhile are admitted as slots and memory free up and their work
-overlaps on the device.
+normalisation and resampling of every filter in one launch per stage).  Up to
+``n_streams * depth`` ticks are in flight: with two streams a new tick runs
+beside the previous one on the device; with one stream and depth 2 the next
+tick is queued behind the running one, so the device never waits for the host
+between ticks and a tick never shares the device with another.
 
 * Latest wins: a robot keeps at most one waiting request; a newer scan replaces
   an older one that has not started (counted as dropped, as a localiser drops
@@ -97,7 +98,7 @@ class Engine:
     trace served one request at a time with the single-filter calls)."""
 
     def __init__(self, robots, init_particles, budget_bytes: int = 64 << 30, max_evals_per_tick: float = 1.2e11,
-                 n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0):
+                 n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0, depth: int = 1):
         import torch
         self.torch = torch
         self.robots = robots
@@ -108,6 +109,7 @@ class Engine:
         self.graph = graph and not plain
         self.seed = seed
         self.streams = [torch.cuda.Stream() for _ in range(1 if plain else n_streams)]
+        self.depth = 1 if plain else max(1, int(depth))    # ticks in flight per stream
         self.used = 0
         self.stats = ServeStats()
 
@@ -171,7 +173,7 @@ class Engine:
         ref.synchronize()
         t_ref = time.perf_counter() - t0
         inflight = collections.deque()        # (event, robots, stream index)
-        busy = [False] * len(self.streams)
+        busy = [0] * len(self.streams)        # ticks in flight per stream
         ptr = 0
         while True:
             now = time.perf_counter() - t0
@@ -192,9 +194,9 @@ class Engine:
                     for r in rs:
                         self._finish(r, t_done)
                     inflight.remove(item)
-                    busy[si] = False
+                    busy[si] -= 1
                     progressed = True
-            free = [i for i, b in enumerate(busy) if not b]
+            free = [i for i, b in enumerate(busy) if b < self.depth]
             if free:
                 cands = sorted((r for r in self.robots if r.pending is not None and r.in_flight is None),
                                key=lambda r: r.pending)
@@ -224,7 +226,7 @@ class Engine:
                         ev = torch.cuda.Event(enable_timing=True)
                         ev.record(s)
                     inflight.append((ev, batch, si))
-                    busy[si] = True
+                    busy[si] += 1
                     st.ticks += 1
                     progressed = True
             if ptr >= len(trace) and not inflight and (not drain or not any(
