@@ -525,7 +525,7 @@ def run_served(args):
     res = {}
     for name, kw in (("served", dict(plain=False, graph=args.graph)), ("plain_sequential", dict(plain=True))):
         eng = Engine(make_robots(), init_particles, budget_bytes=budget, max_evals_per_tick=args.tick_evals, seed=5,
-                     n_streams=args.streams, depth=args.depth,
+                     n_streams=args.streams, depth=args.depth, order=args.order,
                      **kw)
         st = eng.run(sw.trace)
         res[name] = st.summary()
@@ -541,7 +541,7 @@ def run_served(args):
                                    "global (N 262k-1M) then tracking (N 4k-32k), 16x1800 / 64x1024 scans",
                        "trace_s": args.trace_seconds, "robots": len(sw.robots), "budget_GiB": args.budget_gib,
                        "graph": args.graph, "tick_evals_cap": args.tick_evals,
-                       "streams": args.streams, "depth": args.depth})
+                       "streams": args.streams, "depth": args.depth, "order": args.order})
     out["steps"] = sv["completed"]
     out["warmup"] = 0
     out["latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"]}
@@ -562,9 +562,11 @@ def main():
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--graph", action="store_true", help="served: replay ticks from captured graphs")
-    ap.add_argument("--tick-evals", type=float, default=3e10, help="served: cap on particle-point evals per tick")
+    ap.add_argument("--tick-evals", type=float, default=5e9, help="served: cap on particle-point evals per tick")
     ap.add_argument("--streams", type=int, default=2, help="served: streams")
     ap.add_argument("--depth", type=int, default=1, help="served: ticks in flight per stream")
+    ap.add_argument("--order", choices=("fifo", "stale"), default="stale",
+                    help="served: oldest scan first, or the robot with the oldest last update first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the sensor kernel's launch shape first")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the batched workload's particle counts")

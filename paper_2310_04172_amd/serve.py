@@ -13,6 +13,10 @@ between ticks and a tick never shares the device with another.
 * Latest wins: a robot keeps at most one waiting request; a newer scan replaces
   an older one that has not started (counted as dropped, as a localiser drops
   stale scans).  A robot has at most one update in flight.
+* Order: waiting requests are taken oldest scan first (``order="fifo"``), or
+  the robot whose last completed update is oldest first (``order="stale"``:
+  every robot's pose is kept as fresh as the device allows; under overload the
+  scan served is then one that arrived recently, not one that waited longest).
 * Admission: a robot becomes resident when its device state (``mcl_job_bytes``)
   fits the memory budget; until then its request waits.
 * Latency is measured from a request's arrival to the GPU completion of its
@@ -63,6 +67,7 @@ class Robot:
     pending: float | None = None
     in_flight: float | None = None
     evals_done: int = 0
+    last_done: float = -1.0     # completion time of the last update (-1: none yet)
 
     @property
     def K(self):
@@ -98,7 +103,8 @@ class Engine:
     trace served one request at a time with the single-filter calls)."""
 
     def __init__(self, robots, init_particles, budget_bytes: int = 64 << 30, max_evals_per_tick: float = 1.2e11,
-                 n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0, depth: int = 1):
+                 n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0, depth: int = 1,
+                 order: str = "fifo"):
         import torch
         self.torch = torch
         self.robots = robots
@@ -110,6 +116,9 @@ class Engine:
         self.seed = seed
         self.streams = [torch.cuda.Stream() for _ in range(1 if plain else n_streams)]
         self.depth = 1 if plain else max(1, int(depth))    # ticks in flight per stream
+        if order not in ("fifo", "stale"):
+            raise ValueError("order must be 'fifo' or 'stale'")
+        self.order = order
         self.used = 0
         self.stats = ServeStats()
 
@@ -143,6 +152,7 @@ class Engine:
         self.stats.evals += n_evals
         r.evals_done += n_evals
         r.in_flight = None
+        r.last_done = t_done
         r.completed += 1
         r.poses, r.spare = r.spare, r.poses          # the resampled set is the new particle set
         r.filt.poses, r.filt.poses_out = r.poses, r.spare
@@ -198,8 +208,8 @@ class Engine:
                     progressed = True
             free = [i for i, b in enumerate(busy) if b < self.depth]
             if free:
-                cands = sorted((r for r in self.robots if r.pending is not None and r.in_flight is None),
-                               key=lambda r: r.pending)
+                key = (lambda r: r.pending) if self.order == "fifo" else (lambda r: (r.last_done, r.pending))
+                cands = sorted((r for r in self.robots if r.pending is not None and r.in_flight is None), key=key)
                 batch, evals = [], 0.0
                 for r in cands:
                     if not self._admit(r):

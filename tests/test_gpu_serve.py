@@ -14,14 +14,14 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-@pytest.mark.parametrize("n_streams,depth", [(2, 1), (1, 2)])
-def test_served_equals_alone(n_streams, depth):
+@pytest.mark.parametrize("n_streams,depth,order", [(2, 1, "fifo"), (1, 2, "fifo"), (2, 1, "stale")])
+def test_served_equals_alone(n_streams, depth, order):
     import torch
     from paper_2310_04172_amd import mcl
     from paper_2310_04172_amd.serve import Engine, Robot, update_draw
     from workloads import served
 
-    say(f"case: served engine, small trace, {n_streams} streams x {depth} ticks")
+    say(f"case: served engine, small trace, {n_streams} streams x {depth} ticks, order {order}")
     sw = served.build(n_robots=12, trace_s=2.0, rate_hz=10.0, scans_per_map=2, map_subset=[0, 3])
     for sp in sw.robots:          # keep the test small: scale particle counts down
         sp.n_global = 1 + sp.n_global // 64
@@ -45,7 +45,7 @@ def test_served_equals_alone(n_streams, depth):
 
     big = max(mcl.job_bytes(sp.n_global, scans[sp.map_idx][sp.scan_idx].shape[1]) for sp in sw.robots)
     eng = Engine(robots(), init, budget_bytes=3 * big, max_evals_per_tick=2e9, seed=9, n_streams=n_streams,
-                 depth=depth)
+                 depth=depth, order=order)
     st = eng.run(sw.trace)
     summ = st.summary()
     say(f"served: {summ}")
