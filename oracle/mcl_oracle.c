@@ -69,8 +69,12 @@
  *        l_n = -(s^2 / (2 sigma^2)) * sum_k m_k^2.
  *
  *  Normalisation (§V-A sums the weights for normalisation), float64:
- *        m = max_n l_n ;  S = sum_n exp(l_n - m) in index order ;
+ *        m = max_n l_n ;  S = sum_n exp(l_n - m) ;
  *        log Z = m + log S ;  w_n = exp(l_n - log Z) ;
+ *    S is meant exactly: the terms are added with compensation (Neumaier's
+ *    variant of Kahan summation), so the computed S is within 2 units of
+ *    rounding of the terms' exact sum whatever N is, where a plain sum in index
+ *    order could drift by up to N - 1 units.
  *        W_n = floor(w_n * 2^42)  (64-bit fixed point, for an integer scan).
  *
  *  Resampling (§III: a new particle set is drawn from the weighted one).
@@ -495,8 +499,14 @@ int oracle_normalize(const double *logw, int32_t N, double *w, uint64_t *wq, dou
     double m = logw[0];
     for (int32_t n = 1; n < N; ++n)
         if (logw[n] > m) m = logw[n];
-    double S = 0.0;
-    for (int32_t n = 0; n < N; ++n) S += exp(logw[n] - m);
+    double S = 0.0, comp = 0.0;
+    for (int32_t n = 0; n < N; ++n) {
+        const double t = exp(logw[n] - m);
+        const double y = S + t;
+        comp += fabs(S) >= fabs(t) ? (S - y) + t : (t - y) + S;  /* the rounding error of S + t, exactly */
+        S = y;
+    }
+    S += comp;
     double lz = m + log(S);
     for (int32_t n = 0; n < N; ++n) {
         double wn = exp(logw[n] - lz);

@@ -240,18 +240,37 @@ def check_chain_properties(lw, wq, idx, pout, poses):
     assert np.array_equal(pout, poses[:, idx])
 
 
+U64 = 2.0 ** -53     # unit roundoff of float64
+
+
 def check_weight_stages(torch, mcl, oracle_lib, lw32, poses, u):
     """Normalisation and resampling, each fed the same oracle-made input as the
-    oracle: log-sum-exp and weights within ulps, fixed-point weights within one
-    unit, resampled indices and gathered poses bit-exact."""
+    oracle: log-sum-exp and weights within the bound below, fixed-point weights
+    within one unit plus that bound, resampled indices and gathered poses
+    bit-exact.
+
+    Bound on log Z.  The oracle's S is within 2u of the exact sum of its terms
+    (compensated sum), each term within 1 ulp of its exponential.  The GPU adds
+    each thread's 16 terms in order, then a tree of depth 8 per block of 4096,
+    then scales each block sum by exp(m_b - m) (2 roundings) and adds the block
+    sums, at most 2 per thread for N <= 2^21, in another tree of depth 8: at most
+    36 roundings on the way of any term, each term within 2 ulps.  All terms are
+    positive, so the two S differ by at most (36 + 2 + 2 + 1) u relative, and log S
+    by as much in absolute terms; the log and m + log S round once on each side.
+    Weights: the exponent l_n - log Z differs by the log Z bound plus one
+    rounding of the subtraction on each side, and exp adds 2 ulps per side."""
     lw32 = np.ascontiguousarray(lw32, np.float32)
     wt, wq, lz = mcl.normalize(dev(torch, lw32))
     w_ref, wq_ref, lz_ref = oracle_lib.normalize(lw32.astype(np.float64))
     wt, wq, lz = wt.cpu().numpy(), wq.cpu().numpy(), float(lz.cpu().numpy()[0])
-    assert abs(lz - lz_ref) <= 8 * np.spacing(abs(lz_ref)) + 1e-300
-    np.testing.assert_allclose(wt, w_ref, rtol=1e-12, atol=1e-300)
+    log_s = lz_ref - float(lw32.max())
+    tol_lz = 41 * U64 + np.spacing(abs(log_s)) + np.spacing(abs(lz_ref))
+    assert abs(lz - lz_ref) <= tol_lz, (lz, lz_ref, tol_lz)
+    lw64 = lw32.astype(np.float64)
+    rtol_w = tol_lz + np.spacing(np.max(np.abs(lw64 - lz_ref))) + 4 * U64
+    np.testing.assert_allclose(wt, w_ref, rtol=rtol_w, atol=1e-300)
     diff = np.abs(wq.astype(np.int64) - wq_ref.astype(np.int64))
-    assert np.all(diff <= 1 + 1e-10 * wq_ref.astype(np.float64))
+    assert np.all(diff <= 1 + rtol_w * wq_ref.astype(np.float64))
     idx, pout = mcl.resample(dev(torch, wq_ref), u, dev(torch, poses))
     idx_ref = oracle_lib.resample(wq_ref, u)
     assert np.array_equal(idx.cpu().numpy(), idx_ref)
@@ -293,6 +312,44 @@ def test_config2_full_size_sampled(torch, mcl, oracle_lib, cfg2):
     ps = np.ascontiguousarray(w.poses[:, sub[:32]])
     got = mcl.debug_voxel_indices(m, dev(torch, w.points), dev(torch, ps)).cpu().numpy()
     assert np.array_equal(got, oracle_lib.voxel_indices(w.tmap, w.points, ps))
+
+
+# ------------------------------------------------------------ maximum sizes
+def test_max_points(torch, mcl, oracle_lib):
+    """K = MCL_MAX_POINTS: 256 pieces of 4096 points per particle, whose partial
+    sums the combine kernel adds in its deepest tree; 70 particles (one full
+    and one ragged group)."""
+    K, N = mcl.MAX_POINTS, 70
+    say(f"case: sensor update at K = {K}, N = {N}")
+    tmap, pts, poses = random_case(77, (40, 36, 20), N, K, "i16")
+    lw = gpu_logw(torch, mcl, tmap, pts, poses, f32(0.15))
+    ref = oracle_lib.sensor_update(tmap, pts, poses, f32(0.15), nthreads=8)
+    assert_logw_close(lw, ref, "K = MCL_MAX_POINTS")
+
+
+def test_max_particles(torch, mcl, oracle_lib):
+    """N = MCL_MAX_PARTICLES: first with K = 1 against the oracle everywhere,
+    then normalisation and resampling of the result; then with K =
+    MCL_MAX_POINTS as well (2.2e12 evaluations, 8.4 M work items, a 2 GiB
+    partials workspace) against the oracle on sampled particles."""
+    N = mcl.MAX_PARTICLES
+    say(f"case: sensor update at N = {N}, K = 1")
+    tmap, pts1, poses = random_case(78, (40, 36, 20), N, 1, "i16")
+    m = mcl.Map.from_tsdf(tmap)
+    P = dev(torch, poses)
+    lw = mcl.sensor_update(m, dev(torch, pts1), P, f32(0.15)).cpu().numpy()
+    ref = oracle_lib.sensor_update(tmap, pts1, poses, f32(0.15), nthreads=8)
+    assert_logw_close(lw, ref, "N = MCL_MAX_PARTICLES, K = 1")
+    check_weight_stages(torch, mcl, oracle_lib, ref.astype(np.float32), poses, 0x0123456789ABCDEF)
+    K = mcl.MAX_POINTS
+    say(f"case: sensor update at N = {N}, K = {K}")
+    rng = np.random.default_rng(79)
+    ext = np.array(tmap.dims) * tmap.voxel
+    pts = rng.normal(0, 0.4 * ext.mean(), size=(3, K)).astype(np.float32)
+    lw = mcl.sensor_update(m, dev(torch, pts), P, f32(0.15)).cpu().numpy()
+    sub = np.r_[0, 1, 63, 64, N // 2, N - 65, N - 64, N - 1, rng.integers(0, N, 16)]
+    ref = oracle_lib.sensor_update(tmap, pts, np.ascontiguousarray(poses[:, sub]), f32(0.15), nthreads=8)
+    assert_logw_close(lw[sub], ref, "N = MCL_MAX_PARTICLES, K = MCL_MAX_POINTS (sampled)")
 
 
 # ------------------------------------------------------------ weights edges
