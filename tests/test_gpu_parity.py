@@ -352,6 +352,34 @@ def test_max_particles(torch, mcl, oracle_lib):
     assert_logw_close(lw[sub], ref, "N = MCL_MAX_PARTICLES, K = MCL_MAX_POINTS (sampled)")
 
 
+def test_dense_map_near_4gib(torch, mcl, oracle_lib):
+    """int16 2048 x 2048 x 496 voxels: 4.16 GB of bricks, 97 % of the dense
+    layout's 32-bit offset range, so the address sums wrap modulo 2^32 on the
+    way to offsets near 2^32.  Values inside the band in the two far corners,
+    particles in both (offsets near 0 and near 2^32); parity with the oracle."""
+    say("case: dense int16 map of 4.16 GB")
+    rng = np.random.default_rng(41)
+    nx, ny, nz = 2048, 2048, 496
+    vals = np.full((nz, ny, nx), 32767, np.int16)
+    vals[-40:, -256:, -256:] = rng.integers(-32767, 32768, (40, 256, 256)).astype(np.int16)
+    vals[:40, :256, :256] = rng.integers(-32767, 32768, (40, 256, 256)).astype(np.int16)
+    v = 0.05
+    tmap = make_map(vals, v, origin=(0.0, 0.0, 0.0), tau=0.15, dtype="i16")
+    m = mcl.Map.from_tsdf(tmap)
+    assert 4.1e9 < m.device_bytes < 2 ** 32
+    N, K = 128, 4096
+    lo = np.array([128, 128, 20]) * v
+    hi = np.array([nx - 128, ny - 128, nz - 20]) * v
+    t = np.where(np.arange(N)[:, None] % 2 == 0, lo, hi) + rng.uniform(-3, 3, (N, 3)) * np.array([1, 1, 0.2])
+    poses = poses_from(random_rotations(rng, N), t)
+    pts = rng.normal(0, 2.0, (3, K)).astype(np.float32)
+    lw = mcl.sensor_update(m, dev(torch, pts), dev(torch, poses), f32(0.075)).cpu().numpy()
+    del m
+    ref = oracle_lib.sensor_update(tmap, pts, poses, f32(0.075), nthreads=8)
+    assert_logw_close(lw, ref, "4.16 GB map")
+    assert np.unique(np.round(ref[0::2], 3)).size > N // 4 and np.unique(np.round(ref[1::2], 3)).size > N // 4
+
+
 # ------------------------------------------------------------ weights edges
 def test_normalize_resample_edges(torch, mcl, oracle_lib):
     say("case: weight edge cases")
