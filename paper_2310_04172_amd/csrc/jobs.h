@@ -86,8 +86,13 @@ size_t estimate_ws_bytes(int N);
 void bind_estimate_ws(EstJob &J, void *ws);
 
 // ------------------------------------------------------------ job sources
-// Copy a wave-uniform descriptor out of memory into scalar registers: every
-// lane reads the same words, readfirstlane makes the copy provably uniform.
+// Copy a descriptor at a wave-uniform address into scalar registers.  The
+// job tables are written before the kernels that read them start and never
+// during them, so they are read as constant memory: scalar loads, which the
+// compiler may repeat where registers run short.  (Read as ordinary memory
+// through vector loads and readfirstlane, the sensor kernel's descriptor
+// fields had to be spilled to vector-register lanes and restored once per
+// particle, 9 extra instructions per 16 evaluations.)
 template <typename T>
 __device__ __attribute__((always_inline)) inline T load_uniform(const T *p) {
     static_assert(sizeof(T) % 4 == 0, "descriptor size must be a multiple of 4");
@@ -95,9 +100,9 @@ __device__ __attribute__((always_inline)) inline T load_uniform(const T *p) {
         T v;
         int w[sizeof(T) / 4];
     } u;
-    const int *q = reinterpret_cast<const int *>(p);
+    const __attribute__((address_space(4))) int *q = (const __attribute__((address_space(4))) int *)p;
 #pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) u.w[i] = __builtin_amdgcn_readfirstlane(q[i]);
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) u.w[i] = q[i];
     return u.v;
 }
 
