@@ -86,7 +86,8 @@ mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_values, voi
  * the total), and the map may exceed the 4 GiB limit of the dense layout
  * (limits: nbx*nby*nbz < 2^31 bricks, ceil(nx/8)*ceil(ny/32) < 2^24).  The sensor
  * update gives exactly the results of the dense map with the same values; the
- * trilinear lookup, the uniform initialisation and mcl_tick reject sparse maps.
+ * trilinear lookup and the uniform initialisation reject sparse maps, and
+ * mcl_tick those whose blocks take 4 GiB or more.
  *   nstored:      number of listed bricks, >= 0.
  *   brick_coords: HOST [nstored][3] int32 (bx, by, bz), each brick at most once.
  *   brick_values: HOST [nstored][64] values of the storage type, in-brick index
@@ -236,9 +237,12 @@ mcl_status mcl_init_uniform(mcl_map map, float *poses, int32_t N, float max_tilt
  * particle counts and scan sizes).  mcl_tick runs, for every filter, exactly
  * mcl_sensor_update, then mcl_normalize, then (for filters that ask for it)
  * mcl_pose_estimate on the normalised weights and the input poses, then
- * mcl_resample: each stage is one launch over all filters together, and every
- * filter's results are bit for bit those of the single-filter calls.  Buffers follow the rules of the
- * single-filter calls; all buffers of all jobs must be distinct. */
+ * mcl_resample: each stage is one launch over all filters together (the
+ * sensor update one launch per storage type and map kind, dense or sparse),
+ * and every filter's results are bit for bit those of the single-filter
+ * calls.  Sparse maps are accepted when their blocks take less than 4 GiB
+ * (MCL_EINVAL otherwise).  Buffers follow the rules of the single-filter
+ * calls; all buffers of all jobs must be distinct. */
 #define MCL_MAX_JOBS 4096
 
 typedef struct {
@@ -262,7 +266,7 @@ typedef struct {
 } mcl_filter_job;
 
 /* Flag for mcl_tick: the launch chain is captured into a HIP graph the first
- * time (per stream and per mix of map storage types) and replayed afterwards;
+ * time (per stream and per mix of map storage types and kinds) and replayed afterwards;
  * job tables are copied to the device before each replay.  Needs a
  * non-default stream. */
 #define MCL_TICK_GRAPH 1

@@ -4,6 +4,7 @@
 // graph (per stream, per storage-type mix and launch shape) and replayed every
 // tick after the tables are copied in.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -19,6 +20,8 @@ SensorJob make_sensor_job(const mcl_map_s *, const float *, int, const float *, 
 template <typename Src>
 mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t, size_t);
 template <typename Src>
+mcl_status launch_sensor_sparse_src(int32_t, const Src &, int64_t, int64_t, bool, hipStream_t);
+template <typename Src>
 mcl_status launch_normalize_src(const Src &, int, int64_t, int64_t, hipStream_t);
 template <typename Src>
 mcl_status launch_resample_src(const Src &, int64_t, int64_t, hipStream_t);
@@ -28,14 +31,19 @@ size_t weight_ws_bytes(int N);
 void bind_weight_ws(WeightJob &J, void *ws);
 
 constexpr int kMaxJobs = MCL_MAX_JOBS;
-constexpr int kGroups = 3;  // storage types
+// Sensor groups: storage type (0..2) for dense maps, storage type + 3 for
+// sparse maps; each group present gets one sensor launch.
+constexpr int kTypes = 3;
+constexpr int kGroups = 2 * kTypes;
+
+inline int job_group(const mcl_filter_job &F) { return F.map->dtype + (F.map->sparse ? kTypes : 0); }
 
 static constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Device/staging layout: Counts[kGroups + 2] | SensorJob[kGroups][kMaxJobs] |
-// WeightJob[kMaxJobs] | EstJob[kMaxJobs].  Each storage type has its own sensor
-// table at a fixed place, so a captured chain stays valid however the jobs of a
-// tick split among the types.  Counts: one per storage type, the weights', the
+// WeightJob[kMaxJobs] | EstJob[kMaxJobs].  Each sensor group has its own table
+// at a fixed place, so a captured chain stays valid however the jobs of a tick
+// split among the groups.  Counts: one per sensor group, the weights', the
 // estimates'.
 static constexpr int kWeightCnt = kGroups, kEstCnt = kGroups + 1;
 static constexpr size_t kCountsBytes = align256(sizeof(Counts) * (kGroups + 2));
@@ -51,12 +59,12 @@ namespace {
 struct GraphKey {
     int mask;
     int wpb, bpc;
-    int64_t items[3], elems, blocks, eblocks, ejobs;
-    int64_t lds[3];  // LDS bytes for the read bits of a group's shared map, or 0
+    std::array<int64_t, kGroups> items;
+    int64_t elems, blocks, eblocks, ejobs;
+    std::array<int64_t, kGroups> lds;  // LDS bytes for the read bits of a group's shared map, or 0
     bool operator<(const GraphKey &o) const {
-        return std::tie(mask, wpb, bpc, items[0], items[1], items[2], elems, blocks, eblocks, ejobs, lds[0], lds[1],
-                        lds[2]) < std::tie(o.mask, o.wpb, o.bpc, o.items[0], o.items[1], o.items[2], o.elems,
-                                           o.blocks, o.eblocks, o.ejobs, o.lds[0], o.lds[1], o.lds[2]);
+        return std::tie(mask, wpb, bpc, items, elems, blocks, eblocks, ejobs, lds) <
+               std::tie(o.mask, o.wpb, o.bpc, o.items, o.elems, o.blocks, o.eblocks, o.ejobs, o.lds);
     }
 };
 
@@ -131,20 +139,21 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         if (st != MCL_OK) return st;
     }
     for (int j = 0; j < n_jobs; ++j)
-        if (jobs[j].map->sparse)
-            return fail(MCL_EINVAL, "tick: job " + std::to_string(j) + ": sparse maps are not supported in a batched tick");
+        if (jobs[j].map->sparse && !jobs[j].map->sp.small)
+            return fail(MCL_EINVAL, "tick: job " + std::to_string(j) +
+                                        ": sparse maps with a pool of 4 GiB or more are not supported in a batched tick");
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const bool use_graph = (flags & MCL_TICK_GRAPH) != 0;
     if (use_graph && stream == nullptr) return fail(MCL_EINVAL, "tick: graph replay needs a non-default stream");
 
-    // storage-type groups: one sensor launch per type present
+    // sensor groups: one sensor launch per group present
     std::vector<int> order(n_jobs);
     for (int j = 0; j < n_jobs; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].map->dtype < jobs[b].map->dtype; });
-    int g_begin[kGroups + 1] = {0, 0, 0, 0};
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return job_group(jobs[a]) < job_group(jobs[b]); });
+    int g_begin[kGroups + 1] = {};
     for (int g = 0; g < kGroups; ++g) {
         int c = 0;
-        for (int j = 0; j < n_jobs; ++j) c += jobs[j].map->dtype == g;
+        for (int j = 0; j < n_jobs; ++j) c += job_group(jobs[j]) == g;
         g_begin[g + 1] = g_begin[g] + c;
     }
     int mask = 0;
@@ -194,7 +203,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     int64_t eblk = 0, eelem = 0;
     int ne = 0;
     char *ws = S.dev + kTablesBytes;
-    bool combine[kGroups] = {false, false, false};
+    bool combine[kGroups] = {};
     int64_t wblk = 0, welem = 0;
     for (int g = 0; g < kGroups; ++g) {
         int64_t items = 0, elems = 0;
@@ -275,11 +284,11 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     // replay serves any tick that fits; surplus waves exit at once).
     const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
     const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
-    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu, {0, 0, 0}, 0, 0, 0, 0, {0, 0, 0}};
-    // A storage-type group whose jobs all read one map with a small enough bit
-    // table gets the kernel that holds those bits in LDS (a power of two bytes,
-    // so a graph serves any such map up to that size).
-    for (int g = 0; g < kGroups && cfg.coarse != kCoarseBytes; ++g) {
+    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu, {}, 0, 0, 0, 0, {}};
+    // A dense group whose jobs all read one map with a small enough bit table
+    // gets the kernel that holds those bits in LDS (a power of two bytes, so a
+    // graph serves any such map up to that size).
+    for (int g = 0; g < kTypes && cfg.coarse != kCoarseBytes; ++g) {
         if (g_begin[g + 1] == g_begin[g]) continue;
         const mcl_map_s *m0 = jobs[order[g_begin[g]]].map;
         bool shared = true;
@@ -299,7 +308,10 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
                                     dcnt + g};
             // under a graph every group may combine (a job with one piece is skipped inside)
             mcl_status st =
-                launch_sensor_src(g, src, key.items[g], key.elems, use_graph || combine[g], cfg, stream, (size_t)key.lds[g]);
+                g < kTypes ? launch_sensor_src(g, src, key.items[g], key.elems, use_graph || combine[g], cfg, stream,
+                                               (size_t)key.lds[g])
+                           : launch_sensor_sparse_src(g - kTypes, src, key.items[g], key.elems, use_graph || combine[g],
+                                                      stream);
             if (st != MCL_OK) return st;
         }
         JobTable<WeightJob> wsrc{dwt, dcnt + kWeightCnt};

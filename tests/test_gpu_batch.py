@@ -13,7 +13,7 @@ import pytest
 
 from tests.helpers import make_map, poses_from, random_rotations
 from workloads import configs
-from workloads.tsdf import f32
+from workloads.tsdf import f32, to_bricks
 
 pytestmark = pytest.mark.gpu
 
@@ -148,6 +148,56 @@ def test_launch_shapes_are_bit_identical(torch, mcl):
         assert np.array_equal(mcl.sensor_update(m, X, P, w.sigma).cpu().numpy(), ref)
     finally:
         mcl.set_launch_config("i16", w.K, w.N, None)
+
+
+@pytest.fixture(scope="module")
+def mixed_maps(torch, mcl, maps):
+    """The same small maps, the first three also held as sparse brick pools
+    (every sensor group of a tick: dense and sparse, each storage type)."""
+    out = list(maps)
+    for t, _ in maps[:3]:
+        co, va = to_bricks(t)
+        out.append((t, mcl.Map.from_bricks(t.dims, t.voxel, t.origin, t.tau, t.dtype, co, va)))
+    return out
+
+
+MIXED = [(4, 1, 1), (5, 63, 1025), (6, 65, 9000), (0, 1000, 5000), (4, 130, 0), (5, 5000, 4096),
+         (6, 7, 4097), (1, 4097, 300), (4, 2000, 12000), (2, 300, 2000), (3, 90, 700)]
+
+
+def test_tick_with_sparse_maps(torch, mcl, mixed_maps):
+    """Dense and sparse maps of every storage type in one tick, eager and from
+    captured graphs with new contents and another job count: every filter
+    gets the single-filter calls' bits (a sparse map gives the dense map's)."""
+    say("case: tick with dense and sparse maps")
+    filters = job_set(torch, mcl, 31, mixed_maps, MIXED)
+    mcl.tick(filters)
+    got = [outputs(torch, f) for f in filters]
+    for i, f in enumerate(filters):
+        assert_same(got[i], single(torch, mcl, f), f"eager job {i} (N={f.N}, K={f.K})")
+    s = torch.cuda.Stream()
+    for rep, (seed, specs) in enumerate([(32, MIXED), (33, MIXED[::-1][:7]), (34, MIXED)]):
+        filters = job_set(torch, mcl, seed, mixed_maps, specs)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            mcl.tick(filters, graph=True, stream=s)
+        s.synchronize()
+        got = [outputs(torch, f) for f in filters]
+        _ = torch.ones(1 << 20, device="cuda").sum().item()
+        for i, f in enumerate(filters):
+            assert_same(got[i], single(torch, mcl, f), f"replay {rep} job {i}")
+    # a filter on a sparse map gives every bit it gives on the dense map with the same values
+    t0, dm = mixed_maps[0]
+    sm = mixed_maps[4][1]
+    rng = np.random.default_rng(35)
+    ext = np.array(t0.dims) * t0.voxel
+    P = dev(torch, poses_from(random_rotations(rng, 300), rng.uniform(0, 1, (300, 3)) * ext))
+    X = dev(torch, rng.normal(0, 0.3 * ext.mean(), size=(3, 3000)).astype(np.float32))
+    a = mcl.Filter(sm, X, P, f32(0.2), 7, want_estimate=True)
+    b = mcl.Filter(dm, X, P, f32(0.2), 7, want_estimate=True)
+    mcl.tick([a])
+    mcl.tick([b])
+    assert_same(outputs(torch, a), outputs(torch, b), "sparse vs dense map")
 
 
 def test_tick_alone_equals_in_mix(torch, mcl, maps):

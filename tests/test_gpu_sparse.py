@@ -222,9 +222,6 @@ def test_sparse_guards(torch, mcl):
         mcl.sensor_update_trilinear(sm, dev(torch, pts), P, f32(0.1))
     with pytest.raises(mcl.MclError):
         mcl.init_uniform(sm, 10, 0.0, 1)
-    f = mcl.Filter(sm, dev(torch, pts), P, f32(0.1), 1)
-    with pytest.raises(mcl.MclError):
-        mcl.tick([f])
     with pytest.raises(mcl.MclError):   # a brick listed twice
         sparse_of(mcl, tmap, np.r_[co[:1], co[:1]], np.r_[va[:1], va[:1]])
     with pytest.raises(mcl.MclError):   # outside the brick grid
