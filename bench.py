@@ -215,6 +215,23 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
     log(f"step {ms_step:.3f} ms, sensor kernel {sensor_ms:.3f} ms")
     est = time_estimate(torch, mcl, logw, poses, stream)
     log(f"pose estimate {est['us']:.2f} us, {est['achieved_GBs']:.0f} GB/s")
+    tick_lat = None
+    if workload_key == "small":
+        # the same update as one graph-replayed tick (one call, one launch of
+        # a captured chain): the latency a small filter sees on the batched path
+        f = mcl.Filter(m, pts, poses, w.sigma, w.u, want_w=False)
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        tl = []
+        for i in range(args.warmup + args.steps):
+            t1 = time.perf_counter()
+            with torch.cuda.stream(side):
+                mcl.tick([f], graph=True, stream=side)
+            side.synchronize()
+            if i >= args.warmup:
+                tl.append((time.perf_counter() - t1) * 1e3)
+        tick_lat = {"p50": percentile(tl, 50), "p99": percentile(tl, 99), "mean": float(np.mean(tl))}
+        log(f"graph-replayed tick: p50 {tick_lat['p50']:.3f} ms, p99 {tick_lat['p99']:.3f} ms")
     if args.copy_calib_mib:
         n = args.copy_calib_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -231,6 +248,8 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
                                " + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
                        "workload_key": workload_key, "sensor_update_ms": sensor_ms})
     out["latency_ms"] = {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}
+    if tick_lat:
+        out["tick_graph_latency_ms"] = tick_lat
     out["pose_estimate"] = est
     if sparse_info:
         out["config"]["sparse_map"] = sparse_info

@@ -14,9 +14,22 @@ constexpr int kU = 16;                            // points per lane per chunk
 constexpr int kChunk = kWave * kU;                // 1024
 constexpr int kChunksPerPiece = 4;
 constexpr int kPiece = kChunk * kChunksPerPiece;  // 4096 points
-constexpr int kGroup = 64;                        // particles per wave item
+constexpr int kGroup = 64;                        // particles per group (lane p holds particle p's pose)
 
 inline int sensor_pieces(int K) { return K <= 0 ? 1 : (K + kPiece - 1) / kPiece; }
+
+// Work items are (group, piece, run): a launch with few (group, piece) pairs
+// splits each group's particles into nsub runs of 64 / nsub (a power of two up
+// to 64), one work item each, until it has about kTargetItems items (four per
+// wave slot of the chip), so small filters still spread over the chip.  A run
+// only selects which particles' loops a wave executes: every particle's sum is
+// formed in the same order whatever nsub is.
+constexpr int64_t kTargetItems = 16384;
+inline int sensor_runs(int64_t pairs) {
+    int s = 1;
+    while (s < kGroup && pairs * s < kTargetItems) s *= 2;
+    return s;
+}
 
 struct SensorJob {
     MapView map;
@@ -31,14 +44,14 @@ struct SensorJob {
     float c;              // s^2 / (2 sigma^2)
     int32_t K, N, npiece, ngroups;
     int32_t coarse;       // where the nearest lookup reads the coarse level (kCoarse*)
+    int32_t nsub;         // runs per group (work items per (group, piece) pair)
 };
 
 // Coarse level of the nearest lookup: chosen per wave and chunk (auto), or
 // forced to the mask bytes in global memory or the bits in LDS.  Results are
 // the same bits in every mode.
 constexpr int32_t kCoarseAuto = 0, kCoarseBytes = 1, kCoarseBits = 2;
-constexpr int kProbe = 2;                             // probe evaluations per chunk
-constexpr int kProbeMixed = kProbe * kChunk * 3 / 4;  // LDS when over 3/4 of them read in place
+constexpr int kProbe = 2;  // probe particles per chunk; LDS when over 3/4 of their lookups read in place
 
 // Weight normalisation and resampling of one filter.
 constexpr int kWThreads = 256;

@@ -364,44 +364,61 @@ __device__ __attribute__((always_inline)) inline void chunk_range(const SensorJo
     }
 }
 
-// All particles of the group against one chunk.  With the LDS coarse level
-// available, the coarse level is read from LDS or from global memory,
-// whichever suits this wave's particles (same bits either way): the first
-// kProbe particles run with the global masks and count the in-place reads;
-// the rest take LDS when over half of those were in place (tracking: most
-// points land in the band, and LDS saves a gather per point), else stay on
-// the global masks (global localisation: most points read the shared
+// The wave's run of particles [p0, p1) against one chunk.  With the LDS
+// coarse level available, the coarse level is read from LDS or from global
+// memory, whichever suits this wave's particles (same bits either way): the
+// first kProbe particles run with the global masks and count the in-place
+// reads; the rest take LDS when over 3/4 of those were in place (tracking:
+// most points land in the band, and LDS saves a gather per point), else stay
+// on the global masks (global localisation: most points read the shared
 // sentinel line, and the global path issues fewer instructions).
 template <typename T, bool TAIL, int LK>
 __device__ __attribute__((always_inline)) inline void chunk_group(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
-                                   int gcount, float &acc, const uint32_t *sbits) {
+                                   int p0, int p1, float &acc, const uint32_t *sbits) {
     if constexpr (LK == kLookNearestLds) {
-        int p0 = 0;
+        int q0 = p0;
         bool lds = J.coarse == kCoarseBits;
         if (J.coarse == kCoarseAuto) {
             int nmixed = 0;
-            p0 = min(kProbe, gcount);
-            chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, 0, p0, acc, sbits, true, &nmixed);
-            lds = nmixed > kProbeMixed;
+            q0 = min(p0 + kProbe, p1);
+            chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, p0, q0, acc, sbits, true, &nmixed);
+            lds = 4 * nmixed > 3 * kChunk * (q0 - p0);
         }
         if (lds)
-            chunk_range<T, TAIL, kLookNearestLds>(J, pa, px, py, pz, lane, nvalid, p0, gcount, acc, sbits);
+            chunk_range<T, TAIL, kLookNearestLds>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
         else
-            chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, p0, gcount, acc, sbits);
+            chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
     } else {
-        chunk_range<T, TAIL, LK>(J, pa, px, py, pz, lane, nvalid, 0, gcount, acc, sbits);
+        chunk_range<T, TAIL, LK>(J, pa, px, py, pz, lane, nvalid, p0, p1, acc, sbits);
     }
 }
 
-// One work item: particles [64 g, 64 g + 64) of a job against points
+// Coordinates of work item `local` of a job: its group of 64 particles, its
+// piece of 4096 points and its run [p0, p1) of the group's particles (empty
+// when the group is short).
+struct ItemPos {
+    int n0, piece, p0, p1;
+};
+__device__ __attribute__((always_inline)) inline ItemPos item_pos(const SensorJob &J, int local) {
+    const int per = J.npiece * J.nsub;
+    const int group = local / per;
+    const int rem = local - group * per;
+    const int piece = rem / J.nsub;
+    const int run = kGroup / J.nsub;
+    const int p0 = (rem - piece * J.nsub) * run;
+    const int n0 = group * kGroup;
+    return ItemPos{n0, piece, p0, min(p0 + run, min(kGroup, J.N - n0))};
+}
+
+// One work item: particles 64 g + [p0, p1) of a job against points
 // [4096 piece, 4096 piece + 4096).  Returns lane p's sum for particle 64 g + p.
 template <typename T, int LK>
 __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJob &J, int local, int lane,
                                                                    const uint32_t *sbits) {
-    const int group = local / J.npiece;
-    const int piece = local - group * J.npiece;
-    const int n0 = group * kGroup;
+    const ItemPos ip = item_pos(J, local);
+    if (ip.p0 >= ip.p1) return 0.0f;
+    const int n0 = ip.n0, piece = ip.piece;
     const int gcount = min(kGroup, J.N - n0);
     const MapView &m = J.map;
     const int K = J.K;
@@ -423,9 +440,9 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
             pz[u] = gp(J.pts)[(size_t)2 * K + k];
         }
         if (nvalid == kChunk)
-            chunk_group<T, false, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc, sbits);
+            chunk_group<T, false, LK>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits);
         else
-            chunk_group<T, true, LK>(J, pa, px, py, pz, lane, nvalid, gcount, acc, sbits);
+            chunk_group<T, true, LK>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits);
     }
     return acc;
 }
@@ -433,14 +450,12 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
 // Output of a work item: l directly (one piece) or the piece's partial sums.
 __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJob &J, int local, int lane,
                                                                    float acc) {
-    const int group = local / J.npiece;
-    const int piece = local - group * J.npiece;
-    const int n0 = group * kGroup;
-    if (lane < min(kGroup, J.N - n0)) {
+    const ItemPos ip = item_pos(J, local);
+    if (lane >= ip.p0 && lane < ip.p1) {
         if (J.npiece == 1)
-            J.logw[n0 + lane] = -(acc * J.c);
+            J.logw[ip.n0 + lane] = -(acc * J.c);
         else
-            J.part[(size_t)piece * J.N + n0 + lane] = acc;
+            J.part[(size_t)ip.piece * J.N + ip.n0 + lane] = acc;
     }
 }
 
@@ -620,6 +635,7 @@ SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const f
     J.N = N;
     J.npiece = sensor_pieces(K);
     J.ngroups = (N + kGroup - 1) / kGroup;
+    J.nsub = sensor_runs((int64_t)J.ngroups * J.npiece);
     return J;
 }
 
@@ -637,7 +653,7 @@ mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, cons
     }
     using Src = OneJob<SensorJob>;
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
-    const int64_t nitems = (int64_t)src.job.ngroups * npiece;
+    const int64_t nitems = (int64_t)src.job.ngroups * npiece * src.job.nsub;
     src.n = Counts{1, nitems, N, 0};
     const size_t lds_bytes = (((size_t)map->view.nrwords + 3) & ~(size_t)3) * 4;  // 16-byte pieces
     if (!map->sparse && lds_bytes <= kMaxLdsBits && cfg.coarse != kCoarseBytes) {
@@ -682,7 +698,7 @@ mcl_status launch_sensor_trilinear(mcl_map_s *map, const float *pts, int K, cons
     using Src = OneJob<SensorJob>;
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
     src.job.tri = map->tri;
-    const int64_t nitems = (int64_t)src.job.ngroups * npiece;
+    const int64_t nitems = (int64_t)src.job.ngroups * npiece * src.job.nsub;
     src.n = Counts{1, nitems, N, 0};
     const unsigned blocks = (unsigned)((nitems + 3) / 4);
     if (map->dtype == MCL_TSDF_I16) sensor_kernel<int16_t, 4, Src, kLookTrilinear><<<blocks, 256, 0, stream>>>(src);

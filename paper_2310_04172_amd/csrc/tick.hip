@@ -1,7 +1,7 @@
 // Batched tick: sensor update, normalisation, pose estimate and resampling of
 // many filters in one launch per stage.  Job tables and totals live in device memory, so the
 // launch chain does not depend on the job set: it is captured once into a HIP
-// graph (per stream, per storage-type mix and launch shape) and replayed every
+// graph (per stream, per mix of sensor groups and launch shape) and replayed every
 // tick after the tables are copied in.
 #include <algorithm>
 #include <array>
@@ -195,6 +195,11 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     for (int j = 1; j < n_jobs; ++j)
         if ((int64_t)jobs[j].N * jobs[j].K > (int64_t)jobs[big].N * jobs[big].K) big = j;
     const LaunchCfg cfg = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
+    // runs per group, one value for the whole tick, from its total (group, piece) pairs
+    int64_t pairs = 0;
+    for (int j = 0; j < n_jobs; ++j)
+        pairs += (int64_t)((jobs[j].N + kGroup - 1) / kGroup) * sensor_pieces(jobs[j].K);
+    const int nsub = sensor_runs(pairs);
 
     Counts *cnt = reinterpret_cast<Counts *>(S.host);
     WeightJob *wtbl = reinterpret_cast<WeightJob *>(S.host + kWeightTblOff);
@@ -230,7 +235,8 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             J.coarse = cfg.coarse;
             J.item0 = items;
             J.elem0 = elems;
-            items += (int64_t)J.ngroups * J.npiece;
+            J.nsub = nsub;
+            items += (int64_t)J.ngroups * J.npiece * J.nsub;
             elems += F.N;
             W.logw = F.logw;
             W.w = F.w;

@@ -185,6 +185,8 @@ def test_pool_past_4gib(torch, mcl, oracle_lib):
     poses = poses_from(random_rotations(rng, N), rng.uniform(lo, hi, (N, 3)))
     pts = rng.normal(0, 1.5, (3, K)).astype(np.float32)
     ls = mcl.sensor_update(sm, dev(torch, pts), dev(torch, poses), f32(0.075)).cpu().numpy()
+    with pytest.raises(mcl.MclError):   # a batched tick takes sparse maps below 4 GiB only
+        mcl.tick([mcl.Filter(sm, dev(torch, pts), dev(torch, poses), f32(0.075), 1)])
     del sm
     ref = oracle_lib.sensor_update_bricks(dims, v, (0.0, 0.0, 0.0), tau, "f32", co, va, pts, poses, f32(0.075),
                                           nthreads=8)
