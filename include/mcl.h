@@ -238,10 +238,12 @@ mcl_status mcl_init_uniform(mcl_map map, float *poses, int32_t N, float max_tilt
  * mcl_sensor_update, then mcl_normalize, then (for filters that ask for it)
  * mcl_pose_estimate on the normalised weights and the input poses, then
  * mcl_resample: each stage is one launch over all filters together (the
- * sensor update one launch per storage type and map kind, dense or sparse),
- * and every filter's results are bit for bit those of the single-filter
- * calls.  Sparse maps are accepted when their blocks take less than 4 GiB
- * (MCL_EINVAL otherwise).  Buffers follow the rules of the single-filter
+ * sensor update one launch per storage type and lookup: nearest on dense
+ * maps, nearest on sparse maps, trilinear on dense maps), and every filter's
+ * results are bit for bit those of the single-filter calls (the trilinear
+ * lookup's corner cells are built on the map's first trilinear use, as by
+ * mcl_sensor_update_trilinear).  Sparse maps are accepted when their blocks
+ * take less than 4 GiB (MCL_EINVAL otherwise).  Buffers follow the rules of the single-filter
  * calls; all buffers of all jobs must be distinct. */
 #define MCL_MAX_JOBS 4096
 
@@ -263,7 +265,13 @@ typedef struct {
                                weighted set (as mcl_pose_estimate); needs w       */
     int32_t *est_idx;       /* device out [1] best particle, or NULL              */
     float *est_pose;        /* device out [12] best particle's pose, or NULL      */
+    int32_t lookup;         /* MCL_LOOKUP_NEAREST (as mcl_sensor_update) or
+                               MCL_LOOKUP_TRILINEAR (as mcl_sensor_update_trilinear,
+                               dense maps only)                                   */
 } mcl_filter_job;
+
+#define MCL_LOOKUP_NEAREST 0
+#define MCL_LOOKUP_TRILINEAR 1
 
 /* Flag for mcl_tick: the launch chain is captured into a HIP graph the first
  * time (per stream and per mix of map storage types and kinds) and replayed afterwards;

@@ -618,6 +618,25 @@ mcl_status launch_sensor_sparse_src(int32_t dtype, const Src &src, int64_t nitem
 
 template mcl_status launch_sensor_sparse_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t,
                                                                   int64_t, bool, hipStream_t);
+
+// Trilinear lookup (the jobs' corner cells built): one wave per work item,
+// four waves per workgroup, as for a single call.
+template <typename Src>
+mcl_status launch_sensor_tri_src(int32_t dtype, const Src &src, int64_t nitems, int64_t nelems, bool combine,
+                                 hipStream_t stream) {
+    const unsigned blocks = (unsigned)std::max<int64_t>((nitems + 3) / 4, 1);
+    if (dtype == MCL_TSDF_I16) sensor_kernel<int16_t, 4, Src, kLookTrilinear><<<blocks, 256, 0, stream>>>(src);
+    else if (dtype == MCL_TSDF_I8) sensor_kernel<int8_t, 4, Src, kLookTrilinear><<<blocks, 256, 0, stream>>>(src);
+    else sensor_kernel<float, 4, Src, kLookTrilinear><<<blocks, 256, 0, stream>>>(src);
+    mcl_status st = check_launch("sensor_kernel (trilinear)");
+    if (st != MCL_OK || !combine) return st;
+    int64_t cb = std::min<int64_t>((nelems + 255) / 256, (int64_t)device_cus() * 16);
+    combine_kernel<<<(unsigned)std::max<int64_t>(cb, 1), 256, 0, stream>>>(src);
+    return check_launch("combine_kernel");
+}
+
+template mcl_status launch_sensor_tri_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t,
+                                                               int64_t, bool, hipStream_t);
 template mcl_status launch_sensor_src<OneJob<SensorJob>>(int32_t, const OneJob<SensorJob> &, int64_t, int64_t,
                                                          bool, LaunchCfg, hipStream_t, size_t);
 

@@ -22,6 +22,8 @@ mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, Launc
 template <typename Src>
 mcl_status launch_sensor_sparse_src(int32_t, const Src &, int64_t, int64_t, bool, hipStream_t);
 template <typename Src>
+mcl_status launch_sensor_tri_src(int32_t, const Src &, int64_t, int64_t, bool, hipStream_t);
+template <typename Src>
 mcl_status launch_normalize_src(const Src &, int, int64_t, int64_t, hipStream_t);
 template <typename Src>
 mcl_status launch_resample_src(const Src &, int64_t, int64_t, hipStream_t);
@@ -31,12 +33,17 @@ size_t weight_ws_bytes(int N);
 void bind_weight_ws(WeightJob &J, void *ws);
 
 constexpr int kMaxJobs = MCL_MAX_JOBS;
-// Sensor groups: storage type (0..2) for dense maps, storage type + 3 for
-// sparse maps; each group present gets one sensor launch.
+// Sensor groups: storage type (0..2) + 3 x kind, the kind being the nearest
+// lookup on a dense map (0), on a sparse map (1) or the trilinear lookup on a
+// dense map (2); each group present gets one sensor launch.
 constexpr int kTypes = 3;
-constexpr int kGroups = 2 * kTypes;
+constexpr int kKindDense = 0, kKindSparse = 1, kKindTri = 2;
+constexpr int kGroups = 3 * kTypes;
 
-inline int job_group(const mcl_filter_job &F) { return F.map->dtype + (F.map->sparse ? kTypes : 0); }
+inline int job_kind(const mcl_filter_job &F) {
+    return F.map->sparse ? kKindSparse : F.lookup == MCL_LOOKUP_TRILINEAR ? kKindTri : kKindDense;
+}
+inline int job_group(const mcl_filter_job &F) { return F.map->dtype + kTypes * job_kind(F); }
 
 static constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -117,6 +124,10 @@ mcl_status check_job(const mcl_filter_job &J, int j) {
     if (!J.est_mean && (J.est_idx || J.est_pose))
         return fail(MCL_EINVAL, at + "est_idx or est_pose without est_mean");
     if (J.est_mean && !J.w) return fail(MCL_EINVAL, at + "a pose estimate needs the weights w");
+    if (J.lookup != MCL_LOOKUP_NEAREST && J.lookup != MCL_LOOKUP_TRILINEAR)
+        return fail(MCL_EINVAL, at + "lookup must be MCL_LOOKUP_NEAREST or MCL_LOOKUP_TRILINEAR");
+    if (J.lookup == MCL_LOOKUP_TRILINEAR && J.map->sparse)
+        return fail(MCL_EINVAL, at + "the trilinear lookup needs a dense map");
     return MCL_OK;
 }
 
@@ -145,6 +156,12 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const bool use_graph = (flags & MCL_TICK_GRAPH) != 0;
     if (use_graph && stream == nullptr) return fail(MCL_EINVAL, "tick: graph replay needs a non-default stream");
+    // corner cells of maps read by the trilinear lookup (built once per map)
+    for (int j = 0; j < n_jobs; ++j)
+        if (job_kind(jobs[j]) == kKindTri) {
+            mcl_status st = ensure_trilinear(jobs[j].map, stream);
+            if (st != MCL_OK) return st;
+        }
 
     // sensor groups: one sensor launch per group present
     std::vector<int> order(n_jobs);
@@ -232,6 +249,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             }
             SensorJob &J = stbl[s];
             J = make_sensor_job(m, F.points, F.K, F.poses, F.N, c, F.logw, part);
+            if (job_kind(F) == kKindTri) J.tri = m->tri;
             J.coarse = cfg.coarse;
             J.item0 = items;
             J.elem0 = elems;
@@ -313,11 +331,12 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             JobTable<SensorJob> src{reinterpret_cast<const SensorJob *>(S.dev + kSensorTblOff + g * kSensorTblBytes),
                                     dcnt + g};
             // under a graph every group may combine (a job with one piece is skipped inside)
+            const int type = g % kTypes, kind = g / kTypes;
+            const bool comb = use_graph || combine[g];
             mcl_status st =
-                g < kTypes ? launch_sensor_src(g, src, key.items[g], key.elems, use_graph || combine[g], cfg, stream,
-                                               (size_t)key.lds[g])
-                           : launch_sensor_sparse_src(g - kTypes, src, key.items[g], key.elems, use_graph || combine[g],
-                                                      stream);
+                kind == kKindDense  ? launch_sensor_src(type, src, key.items[g], key.elems, comb, cfg, stream, (size_t)key.lds[g])
+                : kind == kKindSparse ? launch_sensor_sparse_src(type, src, key.items[g], key.elems, comb, stream)
+                                      : launch_sensor_tri_src(type, src, key.items[g], key.elems, comb, stream);
             if (st != MCL_OK) return st;
         }
         JobTable<WeightJob> wsrc{dwt, dcnt + kWeightCnt};

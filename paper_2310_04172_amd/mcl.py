@@ -30,6 +30,7 @@ _I = C.c_int32
 MCL_OK, MCL_EINVAL, MCL_ENOMEM, MCL_EDEVICE, MCL_ERANGE = 0, -1, -2, -3, -4
 MAX_JOBS = 4096
 TICK_GRAPH = 1
+LOOKUP_NEAREST, LOOKUP_TRILINEAR = 0, 1
 MAX_PARTICLES = 1 << 21
 MAX_POINTS = 1 << 20
 WQ_SHIFT = 42
@@ -44,7 +45,8 @@ class MapDesc(C.Structure):
 class FilterJob(C.Structure):
     _fields_ = [("map", _P), ("points", _P), ("K", C.c_int32), ("poses", _P), ("N", C.c_int32),
                 ("sigma", C.c_float), ("logw", _P), ("w", _P), ("wq", _P), ("log_z", _P), ("u", C.c_uint64),
-                ("idx", _P), ("poses_out", _P), ("est_mean", _P), ("est_idx", _P), ("est_pose", _P)]
+                ("idx", _P), ("poses_out", _P), ("est_mean", _P), ("est_idx", _P), ("est_pose", _P),
+                ("lookup", C.c_int32)]
 
 
 class LaunchConfig(C.Structure):
@@ -321,13 +323,14 @@ class Filter:
     """
 
     def __init__(self, m: Map, points, poses, sigma: float, u: int, want_w: bool = True, resample_poses: bool = True,
-                 want_estimate: bool = False):
+                 want_estimate: bool = False, trilinear: bool = False):
         import torch
         self.map = m
         self.points = points
         self.poses = poses
         self.sigma = float(sigma)
         self.u = int(u)
+        self.trilinear = bool(trilinear)   # the sensor update as mcl_sensor_update_trilinear
         N = poses.shape[1]
         dev = poses.device
         self.logw = torch.empty(N, dtype=torch.float32, device=dev)
@@ -358,7 +361,7 @@ class Filter:
         return FilterJob(self.map.handle, _ptr(self.points) if self.K else None, self.K, _ptr(self.poses), self.N,
                          self.sigma, _ptr(self.logw), _ptr(self.w), _ptr(self.wq), _ptr(self.log_z),
                          self.u & (2 ** 64 - 1), _ptr(self.idx), _ptr(self.poses_out), _ptr(self.est_mean),
-                         _ptr(self.est_idx), _ptr(self.est_pose))
+                         _ptr(self.est_idx), _ptr(self.est_pose), LOOKUP_TRILINEAR if self.trilinear else LOOKUP_NEAREST)
 
 
 def tick(filters, graph: bool = False, stream=None):

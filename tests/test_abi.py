@@ -111,6 +111,9 @@ def test_tick_and_tuning_argument_errors(mcl):
     jobs[1].est_mean = None
     jobs[1].est_idx = P(0x7100)
     assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL and b"without est_mean" in lib.mcl_last_error()
+    jobs[1].est_idx = None
+    jobs[1].lookup = 5   # neither nearest nor trilinear
+    assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL and b"lookup must be" in lib.mcl_last_error()
     assert lib.mcl_job_bytes(0, 5) == 0
     assert lib.mcl_map_bytes(None) == 0
     assert lib.mcl_job_bytes(1000, 28800) > 1000 * 120

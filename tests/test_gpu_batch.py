@@ -66,7 +66,7 @@ def job_set(torch, mcl, seed, maps, specs):
 
 
 def single(torch, mcl, f):
-    lw = mcl.sensor_update(f.map, f.points, f.poses, f.sigma)
+    lw = (mcl.sensor_update_trilinear if f.trilinear else mcl.sensor_update)(f.map, f.points, f.poses, f.sigma)
     w, wq, lz = mcl.normalize(lw)
     idx, pout = mcl.resample(wq, f.u, f.poses)
     est = mcl.pose_estimate(w, f.poses) if f.est_mean is not None else ()
@@ -198,6 +198,35 @@ def test_tick_with_sparse_maps(torch, mcl, mixed_maps):
     mcl.tick([a])
     mcl.tick([b])
     assert_same(outputs(torch, a), outputs(torch, b), "sparse vs dense map")
+
+
+def test_tick_with_trilinear_lookups(torch, mcl, mixed_maps):
+    """Trilinear filters (dense maps) beside nearest ones on dense and sparse
+    maps in one tick, eager and replayed: every filter gets the bits of its
+    single-filter calls; a sparse map with the trilinear lookup is refused."""
+    say("case: tick with trilinear, nearest and sparse jobs")
+    s = torch.cuda.Stream()
+    sparse = {id(m) for _, m in mixed_maps[4:]}
+    for rep, (seed, specs) in enumerate([(41, MIXED), (42, MIXED[::-1]), (43, MIXED[:6])]):
+        filters = job_set(torch, mcl, seed, mixed_maps, specs)
+        for i, f in enumerate(filters):
+            f.trilinear = i % 3 != 2 and id(f.map) not in sparse   # two of three dense-map filters
+        torch.cuda.synchronize()
+        if rep == 0:
+            mcl.tick(filters)
+        else:
+            with torch.cuda.stream(s):
+                mcl.tick(filters, graph=True, stream=s)
+            s.synchronize()
+        got = [outputs(torch, f) for f in filters]
+        _ = torch.ones(1 << 20, device="cuda").sum().item()
+        assert any(f.trilinear for f in filters)
+        for i, f in enumerate(filters):
+            assert_same(got[i], single(torch, mcl, f), f"rep {rep} job {i} (trilinear {f.trilinear})")
+    bad = job_set(torch, mcl, 44, mixed_maps, [(4, 10, 100)])[0]
+    bad.trilinear = True
+    with pytest.raises(mcl.MclError):
+        mcl.tick([bad])
 
 
 def test_tick_alone_equals_in_mix(torch, mcl, maps):
