@@ -274,7 +274,7 @@ typedef struct {
 #define MCL_LOOKUP_TRILINEAR 1
 
 /* Flag for mcl_tick: the launch chain is captured into a HIP graph the first
- * time (per stream and per mix of map storage types and kinds) and replayed afterwards;
+ * time (per stream and per mix of storage types and lookups) and replayed afterwards;
  * job tables are copied to the device before each replay.  Needs a
  * non-default stream. */
 #define MCL_TICK_GRAPH 1
