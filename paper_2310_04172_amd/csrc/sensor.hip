@@ -305,15 +305,20 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_sparse(con
         const float gz = grid_coord(A[6], A[7], A[8], A[11], px[u], py[u], pz[u]);
         uint32_t ix, iy, iz;
         const bool ok = voxel_ijk(m, gx, gy, gz, ix, iy, iz);
-        uint32_t b = (ix >> kSLX) + __umul24(iy >> kSLY, sp.nsx) + __umul24(iz >> kSLZ, sp.nsxy);
+        // two 24-bit multiply-adds (the empty asm keeps the compiler from
+        // turning them into multiplies and a three-way add)
+        uint32_t b = __umul24(iy >> kSLY, sp.nsx) + (ix >> kSLX);
+        asm volatile("" : "+v"(b));
+        b = __umul24(iz >> kSLZ, sp.nsxy) + b;
         b = ok ? b : sp.outside;
         if (TAIL) b = (u * kWave + lane < nvalid) ? b : sp.pad;
-        sidx[u] = b;
+        sidx[u] = b << 2;   // byte offset of the entry: 32 bits (the table has under 2^28 entries), so
+                            // the gather takes the table base in scalar registers and no 64-bit add
         wv[u] = ((ix & (kSX - 1u)) + ((iy & (kSY - 1u)) << kSLX) + ((iz & (kSZ - 1u)) << (kSLX + kSLY))) * ES;
     }
     uint32_t ent[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) ent[u] = gp(sp.table)[sidx[u]];
+    for (int u = 0; u < kU; ++u) ent[u] = *gp(reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(sp.table) + sidx[u]));
     __builtin_amdgcn_sched_barrier(0);
     int raw[kU];
     if constexpr (!WIDE) {
