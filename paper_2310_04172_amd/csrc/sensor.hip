@@ -249,7 +249,7 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_tri(const 
             const uint32_t ix = tri_axis(gx, tv.hx, fx[v]);
             const uint32_t iy = tri_axis(gy, tv.hy, fy[v]);
             const uint32_t iz = tri_axis(gz, tv.hz, fz[v]);
-            off[v] = brick_x<E>(tv.cx, ix) + brick_y<E>(tv.cy, iy) + brick_z<E>(iz) + tv.data0;
+            off[v] = cell_offset<E>(tv, ix, iy, iz);
         }
         int msk[kTriU];
 #pragma unroll

@@ -114,18 +114,21 @@ __device__ inline uint32_t tri_axis(float g, float hmax, float &f) {
 }
 
 // Byte offset of cell (i, j, k) of the trilinear corner-cell grid (bricks of
-// CX x CY x CZ cells, z-fastest, then x, then y; ESIZE bytes per cell) is
-// data0 + X(i) + Y(j) + Z(k), separable as for the values, with the
-// coefficients of TriView.
+// CX x CY x CZ cells, z-fastest, then x, then y; ESIZE bytes per cell):
+//   data0 + ESIZE (i + CX j + CX CY k) + cx (i & ~(CX-1)) + cy (j & ~(CY-1)),
+// separable as for the values, with the coefficients of TriView, and
+// evaluated the same way (shift-add chain, two 24-bit multiply-adds).
 template <int ESIZE>
-__device__ inline uint32_t brick_x(uint32_t cx, uint32_t ix) {
-    return __umul24(ix & ~(uint32_t)(kCX - 1), cx) + ix * ESIZE;
+__device__ inline uint32_t cell_offset(const TriView &tv, uint32_t ix, uint32_t iy, uint32_t iz) {
+    uint32_t lin = ix + (iy << kCLX);
+    asm volatile("" : "+v"(lin));
+    lin += iz << (kCLX + kCLY);
+    asm volatile("" : "+v"(lin));
+    uint32_t base = lin * (uint32_t)ESIZE + tv.data0;
+    asm volatile("" : "+v"(base));
+    uint32_t t = __umul24(iy & ~(uint32_t)(kCY - 1), tv.cy) + base;
+    asm volatile("" : "+v"(t));
+    return __umul24(ix & ~(uint32_t)(kCX - 1), tv.cx) + t;
 }
-template <int ESIZE>
-__device__ inline uint32_t brick_y(uint32_t cy, uint32_t iy) {
-    return __umul24(iy & ~(uint32_t)(kCY - 1), cy) + (iy << kCLX) * ESIZE;
-}
-template <int ESIZE>
-__device__ inline uint32_t brick_z(uint32_t iz) { return (iz << (kCLX + kCLY)) * ESIZE; }
 
 }  // namespace mcl
