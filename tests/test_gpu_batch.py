@@ -238,3 +238,16 @@ def test_tick_alone_equals_in_mix(torch, mcl, maps):
     for i in (0, 3, 8):
         mcl.tick([filters[i]])
         assert_same(outputs(torch, filters[i]), mixed[i], f"job {i} alone")
+
+
+def test_runs_do_not_change_bits(torch, mcl, maps):
+    """A small filter alone has few (group, piece) pairs, so its groups are
+    split into 64 runs; beside a large filter (over 16,384 pairs) a tick uses
+    one run per group.  Both must give the same bits."""
+    say("case: run split alone vs one run in a large tick")
+    small, big = job_set(torch, mcl, 51, maps, [(0, 100, 1000), (1, 300000, 60000)])
+    mcl.tick([small])
+    alone = outputs(torch, small)
+    mcl.tick([small, big])
+    assert_same(outputs(torch, small), alone, "small filter in a large tick")
+    assert_same(outputs(torch, big), single(torch, mcl, big), "large filter")
