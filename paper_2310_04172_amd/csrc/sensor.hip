@@ -3,11 +3,12 @@
 // holds it, and sum the squared values; l_n = -c * sum, c = s^2 / (2 sigma^2).
 //
 // Work decomposition (gfx950, 64-lane waves):
-//  * a wave owns a group of up to 64 particles; lane p keeps particle p's pose
-//    constants in 12 registers and its running sum;
+//  * a wave owns a group of up to 64 particles, or a run of them when the
+//    launch has few groups; lane p keeps particle p's pose constants in 12
+//    registers and its running sum;
 //  * the scan is cut into chunks of 1024 points; a wave loads a chunk into
 //    registers (16 points per lane, lane l holding points l, l+64, ...), then for
-//    each particle of its group broadcasts that pose to scalar registers and
+//    each particle of its run broadcasts that pose to scalar registers and
 //    evaluates the 16 points of every lane: 16 independent gathers in flight;
 //  * neighbouring lanes hold neighbouring beams, so one wave-wide gather touches
 //    few 128-byte lines of the flat bricks of the map;
