@@ -63,6 +63,24 @@ def test_normalize_special_cases(oracle_lib):
     assert lz2 - lz1 == pytest.approx(3000.0, rel=1e-14)
 
 
+def test_normalize_sum_is_exact_for_many_small_terms(oracle_lib):
+    """log Z is defined by the exact sum S: one particle at l = 0 and 10^6 at
+    l = ln(1e-17) give S = 1 + 10^6 exp(ln 1e-17), log Z = log1p of the rest.
+    Each small term is below half an ulp of 1, so a plain running sum stays at
+    exactly 1 (log Z = 0); the oracle must see the 1e-11."""
+    n = 10 ** 6
+    small = math.log(1e-17)
+    lw = np.full(n + 1, small)
+    lw[0] = 0.0
+    w, wq, lz = oracle_lib.normalize(lw)
+    term = math.exp(small)            # the float64 term both sides add
+    exact = math.log1p(n * term)      # about 1e-11
+    # S itself is a float64 near 1, so log S is good to about an ulp of 1
+    # absolute (a plain sum would be off by the whole 1e-11)
+    assert abs(lz - exact) <= 2 * 2.0 ** -52
+    assert w[0] == pytest.approx(1.0 / (1.0 + n * term), rel=1e-15)
+
+
 def test_normalize_single_particle(oracle_lib):
     w, wq, lz = oracle_lib.normalize(np.array([-77.25]))
     assert w[0] == 1.0 and wq[0] == SCALE and lz == -77.25
