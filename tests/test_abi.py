@@ -121,3 +121,29 @@ def test_tick_and_tuning_argument_errors(mcl):
     assert lib.mcl_set_launch_config(0, 1000, 1000, C.byref(bad)) == mcl.MCL_EINVAL
     assert lib.mcl_set_launch_config(5, 1000, 1000, None) == mcl.MCL_EINVAL
     assert lib.mcl_autotune(None, None, 0, None, 0, 0.1, None, None, None) == mcl.MCL_EINVAL
+
+
+def test_binding_structs_match_the_header(mcl, tmp_path):
+    """The ctypes mirrors of the header's structs have its sizes and field
+    offsets (a C program built from the header with gcc prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"mcl_map_desc": mcl.MapDesc, "mcl_filter_job": mcl.FilterJob, "mcl_launch_config": mcl.LaunchConfig}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "mcl.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
