@@ -12,7 +12,9 @@ Prints one JSON line.  `value` is particle-point evaluations per second
 update) measured with HIP events on its stream; `cpu_baseline` times the CPU
 oracle on a bounded particle sample of the same workload.
 
-Other workloads (not the default line): --workload sparse (the default workload with the
+Other workloads (not the default line): --workload converged (the default map and scan
+with the particles Gaussian round the true pose, 0.05 m / 1 degree: tracking's steady
+state), --workload sparse (the default workload with the
 map held as a sparse coarse/fine brick pool), --workload loop (the whole MCL loop on the
 device: uniform initialisation, then motion, sensor, normalise, estimate, resample per
 iteration, with per-stage times), --workload trilinear (the default workload with
@@ -96,10 +98,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_counters():
-    """The committed counter summary of the sensor kernel, if it was taken on the
-    kernel sources as they are now (else None)."""
-    path = os.path.join(ROOT, "profiles", "sensor_kernel_global_counters.txt")
+def profiled_counters(key="global"):
+    """The committed counter summary of the sensor kernel on workload `key`, if
+    it was taken on the kernel sources as they are now (else None)."""
+    path = os.path.join(ROOT, "profiles", f"sensor_kernel_{key}_counters.txt")
     try:
         text = open(path).read()
     except OSError:
@@ -107,20 +109,20 @@ def profiled_counters():
     return text if kernel_source_hash() in text else None
 
 
-def profiled_traffic():
+def profiled_traffic(key="global"):
     """HBM bytes per sensor launch from the committed counter summary (or None)."""
-    text = profiled_counters()
+    text = profiled_counters(key)
     for line in (text or "").splitlines():
         if line.startswith("traffic_bytes_per_launch:"):
             return float(line.split(":")[1])
     return None
 
 
-def profiled_limiter():
+def profiled_limiter(key="global"):
     """Busy fractions of the units that bound the sensor kernel, from the committed
     counter summary (or None): the texture-data path returning the gathered
     values, the texture-address path issuing them, and VALU lane utilisation."""
-    text = profiled_counters()
+    text = profiled_counters(key)
     if text is None:
         return None
     out = {}
@@ -133,7 +135,7 @@ def profiled_limiter():
     if not out:
         return None
     out["unit"] = "texture data path (gathers)"
-    out["source"] = "profiles/sensor_kernel_global_counters.txt"
+    out["source"] = f"profiles/sensor_kernel_{key}_counters.txt"
     return out
 
 
@@ -258,11 +260,11 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
         achieved = flops / (sensor_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / FP32_PEAK_TFLOPS,
-                           "traffic": profiled_traffic() if workload_key == "global" else None,
+                           "traffic": profiled_traffic(workload_key) if workload_key in ("global", "converged") else None,
                            "kernel": "sensor_kernel", "algorithmic_flops_per_launch": flops,
                            "algorithmic_tsdf_bytes_per_launch": 2.0 * evals}
-        if workload_key == "global":
-            out["roofline"]["limiter"] = profiled_limiter()
+        if workload_key in ("global", "converged"):
+            out["roofline"]["limiter"] = profiled_limiter(workload_key)
     return out
 
 
@@ -575,7 +577,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="global", choices=["global", "small", "batched", "served", "precision", "estimate", "trilinear", "loop",
+    ap.add_argument("--workload", default="global", choices=["global", "converged", "small", "batched", "served", "precision", "estimate", "trilinear", "loop",
                                                     "sparse"])
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
@@ -611,13 +613,15 @@ def main():
         out = run_loop(args)
     else:
         t0 = time.perf_counter()
-        w = configs.config1() if args.workload == "small" else configs.config2()
+        w = (configs.config1() if args.workload == "small" else
+             configs.config2_converged() if args.workload == "converged" else configs.config2())
         log(f"workload built in {time.perf_counter() - t0:.1f} s: N={w.N} K={w.K}")
         out = run_single(args, w, args.workload, trilinear=args.workload == "trilinear",
                          sparse=args.workload == "sparse")
-        if args.workload in ("trilinear", "sparse"):
-            out["metric"] = METRIC + (" [trilinear lookup]" if args.workload == "trilinear" else " [sparse map]")
-        if not args.no_cpu_baseline and args.workload not in ("trilinear", "sparse"):
+        if args.workload in ("trilinear", "sparse", "converged"):
+            out["metric"] = METRIC + {"trilinear": " [trilinear lookup]", "sparse": " [sparse map]",
+                                      "converged": " [particles converged]"}[args.workload]
+        if not args.no_cpu_baseline and args.workload not in ("trilinear", "sparse", "converged"):
             out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

@@ -213,6 +213,19 @@ def config2(n_particles=1_000_000) -> Workload:
                     tmap, pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), draw_u(2), (gxyz, grpy))
 
 
+def config2_converged(n_particles=1_000_000) -> Workload:
+    """The global-localisation map and scan with the particles converged: Gaussian
+    round the true pose (0.05 m, 1 degree), the steady state of tracking."""
+    sc, tmap = warehouse_map(2)
+    gxyz, grpy = ground_truth_pose(rng(2, 1), sc, (1.0, 1.0), (50.2, 50.2), sc.floor_z)
+    R, t = pose_matrix(gxyz, grpy)
+    pts = raycast_scan(sc, tmap, R, t, beam_dirs(azimuths=1800, **VLP16), 100.0, 0.03, rng(2, 2))
+    xyz, rpy = gaussian_particles(rng(2, 9), gxyz, grpy, n_particles, s_xyz=0.05, s_rpy_deg=1.0)
+    return Workload("plain-converged: 1024x1024x128@0.05m int16 warehouse, VLP-16 16x1800, N=1e6 "
+                    "Gaussian round the true pose (0.05 m, 1 deg)",
+                    tmap, pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), draw_u(2), (gxyz, grpy))
+
+
 def config3(n_particles=262_144, dtype="i16") -> Workload:
     sc, tmap = warehouse_map(2, keep_d64=True)
     if dtype != "i16":
