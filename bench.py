@@ -75,7 +75,7 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
     t0 = time.perf_counter()
     lw = oracle.sensor_update(w.tmap, w.points, ps, w.sigma, nthreads=threads)
     _, wq, _ = oracle.normalize(lw)
-    oracle.resample(wq, w.u)
+    oracle.resample_seeded(wq, w.seed, 0)
     dt = time.perf_counter() - t0
     evals = n * w.K
     return {"value": evals / dt / 1e9, "unit": "G particle-point evals/s", "cores": threads, "kind": "oracle",
@@ -197,7 +197,7 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
             b.record(stream)
             ev.append((a, b))
         mcl.normalize(logw, None, wq, lz, want_w=False, stream=stream)
-        mcl.resample(wq, w.u, poses, poses_out, idx, stream)
+        mcl.resample(wq, w.seed, 0, poses, poses_out, idx, stream)
 
     for _ in range(args.warmup):
         step(False)
@@ -221,7 +221,7 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
     if workload_key == "small":
         # the same update as one graph-replayed tick (one call, one launch of
         # a captured chain): the latency a small filter sees on the batched path
-        f = mcl.Filter(m, pts, poses, w.sigma, w.u, want_w=False)
+        f = mcl.Filter(m, pts, poses, w.sigma, w.seed, want_w=False)
         side = torch.cuda.Stream()
         torch.cuda.synchronize()
         tl = []
@@ -376,7 +376,7 @@ def run_loop(args):
         timed("sensor", lambda: mcl.sensor_update(m, pts, poses, w.sigma, logw, stream))
         timed("normalize", lambda: mcl.normalize(logw, wt, wq, None, want_w=True, stream=stream))
         timed("estimate", lambda: mcl.pose_estimate(wt, poses, mean, bi, bp, stream))
-        timed("resample", lambda: mcl.resample(wq, int(it) * 0x9E3779B97F4A7C15, poses, spare, idx, stream))
+        timed("resample", lambda: mcl.resample(wq, w.seed, it, poses, spare, idx, stream))
         poses, spare = spare, poses
     torch.cuda.synchronize()
     ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v[-args.steps:] if True])) for k, v in ev.items()}
@@ -415,7 +415,7 @@ def run_batched(args):
         f"sum N {sum(f.N for f in specs)}")
     dev = torch.device("cuda:0")
     m = mcl.Map.from_tsdf(tmap)
-    filters = [mcl.Filter(m, torch.from_numpy(f.points).to(dev), torch.from_numpy(f.poses).to(dev), f.sigma, f.u,
+    filters = [mcl.Filter(m, torch.from_numpy(f.points).to(dev), torch.from_numpy(f.poses).to(dev), f.sigma, f.seed,
                           want_w=False) for f in specs]
     evals = sum(f.N * f.K for f in specs)
     big = max(range(len(filters)), key=lambda i: specs[i].N * specs[i].K)
@@ -427,7 +427,7 @@ def run_batched(args):
         for f in filters:
             mcl.sensor_update(m, f.points, f.poses, f.sigma, f.logw)
             mcl.normalize(f.logw, None, f.wq, f.log_z, want_w=False)
-            mcl.resample(f.wq, f.u, f.poses, f.poses_out, f.idx)
+            mcl.resample(f.wq, f.seed, f.tick, f.poses, f.poses_out, f.idx)
 
     def eager():
         mcl.tick(filters)
@@ -507,26 +507,25 @@ def run_precision(args):
 
 
 def served_setup(args, sw, torch, mcl, served):
-    dev = torch.device("cuda:0")
+    """Resident maps, robots whose requests carry pinned host scans, and the
+    library initialisers of their particle sets."""
+    from paper_2310_04172_amd.serve import LibraryInit, Robot
     maps = [mcl.Map.from_tsdf(t) for t in sw.tmaps]
-    vals = [torch.from_numpy(t.values).to(dev) for t in sw.tmaps]
-    scans = [[torch.from_numpy(p).to(dev) for p in lst] for lst in sw.scans]
+    host_scans = [[torch.from_numpy(p).pin_memory() for p in lst] for lst in sw.scans]
     specs = sw.robots
+    counts = {sp.rid: {"global": sp.n_global, "track": sp.n_track} for sp in specs}
+    means = {sp.rid: served.pose12(sp.gt) for sp in specs}
+    init = LibraryInit(counts, means, served.MAX_TILT, served.TRACK_SIGMA_T, served.TRACK_SIGMA_R, seed=11)
+    for m in maps:   # the free-voxel index of each map, built once before the trace
+        mcl.init_uniform(m, 1, served.MAX_TILT, 0)
+    torch.cuda.synchronize()
 
     def make_robots():
-        from paper_2310_04172_amd.serve import Robot
-        return [Robot(sp.rid, maps[sp.map_idx], scans[sp.map_idx][sp.scan_idx], served.sigma_for(sw.tmaps[sp.map_idx]),
-                      [(sw.global_updates, "global"), (None, "track")]) for sp in specs]
+        return [Robot(sp.rid, maps[sp.map_idx], host_scans[sp.map_idx][sp.scan_idx],
+                      served.sigma_for(sw.tmaps[sp.map_idx]), [(sw.global_updates, "global"), (None, "track")])
+                for sp in specs]
 
-    def init_particles(r, phase, probe=False):
-        sp = specs[r.rid]
-        n = sp.n_global if phase == "global" else sp.n_track
-        if probe:
-            return n
-        return served.device_particles(torch, sw.tmaps[sp.map_idx], vals[sp.map_idx], n, phase, sp.gt,
-                                       seed=(r.rid << 1) | (phase == "track"), device=dev)
-
-    return make_robots, init_particles
+    return make_robots, init
 
 
 def run_served(args):

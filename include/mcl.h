@@ -41,6 +41,7 @@ typedef int32_t mcl_status;
 #define MCL_ENOMEM (-2)  /* device allocation failed                          */
 #define MCL_EDEVICE (-3) /* HIP runtime / launch error                        */
 #define MCL_ERANGE (-4)  /* a size beyond the limits below                    */
+#define MCL_EBUSY (-5)   /* a resource is held by earlier work (MCL_TICK_NOWAIT) */
 
 #define MCL_MAX_PARTICLES (1 << 21) /* N per call                                */
 #define MCL_MAX_POINTS (1 << 20)    /* K per call                                */
@@ -96,7 +97,12 @@ mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_values, voi
 mcl_status mcl_map_upload_bricks(const mcl_map_desc *desc, int64_t nstored, const int32_t *brick_coords,
                                  const void *brick_values, void *stream, mcl_map *out);
 
-/* Release a map.  The caller must ensure no enqueued work still reads it. */
+/* Release a map.  Deferred: the call first waits for the work this library
+ * has enqueued on the map (every call that reads it records an event on its
+ * stream), then frees the device memory; the handle is invalid afterwards.
+ * Work captured into a graph by the caller is not tracked (the events are
+ * recorded only outside stream capture): keep such maps alive while the graph
+ * may run.  A NULL map returns MCL_EINVAL. */
 mcl_status mcl_map_free(mcl_map map);
 
 /* Device bytes a map holds: its values, coarse level and sentinels, plus the
@@ -157,15 +163,22 @@ mcl_status mcl_normalize(const float *logw, int32_t N, double *w, uint64_t *wq, 
 
 /* Low-variance (systematic) resampling (§III: a new particle set is drawn from
  * the weighted one).  With C_i = wq_0 + ... + wq_i and T = C_{N-1}, the offset
- * is r = floor(u * T / 2^64) for the caller's uniform 64-bit draw u, and output
- * slot m takes the particle i with N*C_{i-1} <= m*T + r < N*C_i.  Integer only:
- * the result is exact.  T = 0 is treated as equal weights (idx[m] = m).
+ * is r = floor(u * T / 2^64) for one uniform 64-bit draw u, and output slot m
+ * takes the particle i with N*C_{i-1} <= m*T + r < N*C_i.  Integer only: the
+ * result is exact.  T = 0 is treated as equal weights (idx[m] = m).
+ * The draw (the paper names no generator; reading): u = splitmix64(seed XOR
+ * splitmix64(tick)), splitmix64(x) being the output of SplitMix64 (Steele, Lea
+ * and Flood, OOPSLA 2014) from state x: z = x + 0x9E3779B97F4A7C15,
+ * z = (z ^ z >> 30) * 0xBF58476D1CE4E5B9, z = (z ^ z >> 27) * 0x94D049BB133111EB,
+ * z ^ z >> 31 (all modulo 2^64).  A filter keeps one seed and counts its updates
+ * in tick, so a resampling step is reproducible from (seed, tick) alone.
  * Precondition: N * T < 2^64 (true for the output of mcl_normalize).
  *   wq:        device, [N] uint64; N in [1, MCL_MAX_PARTICLES].
+ *   seed, tick: select the draw.
  *   idx:       device output [N] int32, non-decreasing ancestor indices.
  *   poses_in / poses_out: device [12][N] float32, both NULL (indices only) or
  *              both set; poses_out[:, m] = poses_in[:, idx[m]]; no overlap. */
-mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t u, int32_t *idx,
+mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t seed, uint64_t tick, int32_t *idx,
                         const float *poses_in, float *poses_out, void *stream);
 
 /* Pose estimate of a weighted particle set (§III: the weighted average of the
@@ -216,6 +229,18 @@ mcl_status mcl_pose_estimate(const double *w, const float *poses, int32_t N, dou
 mcl_status mcl_motion_update(const float *poses_in, float *poses_out, int32_t N, const float *delta,
                              float sigma_t, float sigma_r, uint64_t seed, uint64_t step, void *stream);
 
+/* Initialisation round a pose estimate (§III: with an initial estimate the
+ * particles are spread with a preset variance around it).  Exactly the motion
+ * update above applied to N copies of `mean` with the identity increment:
+ *     R = R_mean Exp(sigma_r (n3, n4, n5)),  t = t_mean + R_mean sigma_t (n0, n1, n2)
+ * (noise in the frame of the estimate), same random numbers and float32 steps
+ * as mcl_motion_update(copies of mean, identity, sigma_t, sigma_r, seed, step).
+ *   poses:   device output [12][N] float32.
+ *   mean:    HOST [12] float32, the estimate (R row-major, t), finite.
+ *   sigma_t, sigma_r: deviations (m, rad), >= 0. */
+mcl_status mcl_init_gaussian(float *poses, int32_t N, const float *mean, float sigma_t, float sigma_r,
+                             uint64_t seed, uint64_t step, void *stream);
+
 /* Uniform initialisation in free space (§III: without an initial pose estimate
  * the particles are distributed uniformly in free space).  Free voxels are
  * those with a stored value > 0, counted in x-fastest order; with F of them,
@@ -258,7 +283,7 @@ typedef struct {
     double *w;              /* device out [N], or NULL                            */
     uint64_t *wq;           /* device out [N]                                     */
     double *log_z;          /* device out [1], or NULL                            */
-    uint64_t u;             /* uniform 64-bit draw for the resampling offset      */
+    uint64_t seed, tick;    /* resampling draw, as for mcl_resample               */
     int32_t *idx;           /* device out [N] ancestor indices                    */
     float *poses_out;       /* device out [12][N] resampled poses, or NULL        */
     double *est_mean;       /* device out [12], or NULL: the pose estimate of the
@@ -278,6 +303,12 @@ typedef struct {
  * job tables are copied to the device before each replay.  Needs a
  * non-default stream. */
 #define MCL_TICK_GRAPH 1
+/* Flag for mcl_tick: do not wait for the stream's table staging buffer.  A tick
+ * copies its job tables from a pinned host buffer (one per stream); while the
+ * copy of the previous tick on that stream has not run yet (it runs in stream
+ * order, after the work enqueued before it), the call returns MCL_EBUSY and
+ * enqueues nothing, instead of blocking the calling thread. */
+#define MCL_TICK_NOWAIT 2
 
 /* Run one tick for n_jobs filters (1..MCL_MAX_JOBS) on `stream`.  The job array
  * is read during the call (it may be reused when the call returns).  Returns

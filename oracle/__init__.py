@@ -59,6 +59,10 @@ def lib():
         L.oracle_init_uniform.argtypes = [P, C.c_float, P, C.c_int32, P, C.c_int32, C.c_float, C.c_uint64, P, P]
         L.oracle_init_uniform.restype = C.c_int
         L.oracle_resample.argtypes = [P, C.c_int32, C.c_uint64, P]
+        L.oracle_splitmix64.argtypes = [C.c_uint64]
+        L.oracle_splitmix64.restype = C.c_uint64
+        L.oracle_resample_draw.argtypes = [C.c_uint64, C.c_uint64]
+        L.oracle_resample_draw.restype = C.c_uint64
         for f in (L.oracle_voxel_indices, L.oracle_sensor_update, L.oracle_sensor_update_trilinear,
                   L.oracle_normalize, L.oracle_resample):
             f.restype = C.c_int
@@ -188,8 +192,23 @@ def normalize(logw: np.ndarray):
     return w, wq, float(lz[0])
 
 
+def splitmix64(x: int) -> int:
+    """SplitMix64 output from state x."""
+    return int(lib().oracle_splitmix64(C.c_uint64(int(x) & (2**64 - 1))))
+
+
+def resample_draw(seed: int, tick: int) -> int:
+    """The uniform 64-bit draw of update `tick` of a filter seeded with `seed`."""
+    return int(lib().oracle_resample_draw(C.c_uint64(int(seed) & (2**64 - 1)), C.c_uint64(int(tick) & (2**64 - 1))))
+
+
+def resample_seeded(wq: np.ndarray, seed: int, tick: int) -> np.ndarray:
+    """Ancestor indices of update `tick` of a filter seeded with `seed`."""
+    return resample(wq, resample_draw(seed, tick))
+
+
 def resample(wq: np.ndarray, u: int) -> np.ndarray:
-    """int32 [N] ancestor indices (non-decreasing)."""
+    """int32 [N] ancestor indices (non-decreasing) for the draw u."""
     W = np.ascontiguousarray(wq, np.uint64)
     N = W.shape[0]
     idx = np.empty(N, np.int32)

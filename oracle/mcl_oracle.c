@@ -84,6 +84,13 @@
  *    particle i whose scaled cell [N C_{i-1}, N C_i) holds m T + r.  Written
  *    below as the familiar single sweep with a moving threshold.  T = 0 (every
  *    weight zero) is read as equal weights: slot m takes particle m.
+ *    The draw: the paper names no generator.  Reading: a filter keeps one
+ *    64-bit seed and counts its updates (tick); the update's draw is
+ *        u = splitmix64(seed XOR splitmix64(tick)),
+ *    splitmix64(x) being the output of SplitMix64 (Steele, Lea and Flood,
+ *    "Fast splittable pseudorandom number generators", OOPSLA 2014) from state
+ *    x: the state advances by the golden-ratio increment 0x9E3779B97F4A7C15,
+ *    then two xor-shift-multiply rounds and a final xor-shift mix it.
  */
 
 #include <math.h>
@@ -518,6 +525,19 @@ int oracle_normalize(const double *logw, int32_t N, double *w, uint64_t *wq, dou
 }
 
 /* -------------------------------------------------------------- resampling */
+
+/* SplitMix64 output from state x (see the header): advance, then mix. */
+uint64_t oracle_splitmix64(uint64_t x) {
+    uint64_t z = x + UINT64_C(0x9E3779B97F4A7C15);
+    z = (z ^ (z >> 30)) * UINT64_C(0xBF58476D1CE4E5B9);
+    z = (z ^ (z >> 27)) * UINT64_C(0x94D049BB133111EB);
+    return z ^ (z >> 31);
+}
+
+/* The resampling draw of update `tick` of a filter seeded with `seed`. */
+uint64_t oracle_resample_draw(uint64_t seed, uint64_t tick) {
+    return oracle_splitmix64(seed ^ oracle_splitmix64(tick));
+}
 
 int oracle_resample(const uint64_t *wq, int32_t N, uint64_t u, int32_t *idx) {
     if (N < 1) return -1;

@@ -4,7 +4,7 @@
 #include <unordered_map>
 #include <utility>
 
-#include "mcl_internal.h"
+#include "jobs.h"
 
 namespace mcl {
 
@@ -96,7 +96,8 @@ extern "C" mcl_status mcl_sensor_update(mcl_map map, const float *points, int32_
     float c = 0.0f;
     mcl_status st = sensor_args("sensor_update", map, points, K, poses, N, sigma, logw, &c);
     if (st != MCL_OK) return st;
-    return launch_sensor(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream));
+    st = launch_sensor(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream));
+    return st == MCL_OK ? note_map_use(map, static_cast<hipStream_t>(stream)) : st;
 }
 
 extern "C" mcl_status mcl_sensor_update_trilinear(mcl_map map, const float *points, int32_t K, const float *poses,
@@ -104,7 +105,8 @@ extern "C" mcl_status mcl_sensor_update_trilinear(mcl_map map, const float *poin
     float c = 0.0f;
     mcl_status st = sensor_args("sensor_update_trilinear", map, points, K, poses, N, sigma, logw, &c);
     if (st != MCL_OK) return st;
-    return launch_sensor_trilinear(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream));
+    st = launch_sensor_trilinear(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream));
+    return st == MCL_OK ? note_map_use(map, static_cast<hipStream_t>(stream)) : st;
 }
 
 extern "C" mcl_status mcl_normalize(const float *logw, int32_t N, double *w, uint64_t *wq, double *log_z,
@@ -118,8 +120,8 @@ extern "C" mcl_status mcl_normalize(const float *logw, int32_t N, double *w, uin
     return launch_normalize(logw, N, w, wq, log_z, static_cast<hipStream_t>(stream));
 }
 
-extern "C" mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t u, int32_t *idx, const float *poses_in,
-                                   float *poses_out, void *stream) {
+extern "C" mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t seed, uint64_t tick, int32_t *idx,
+                                   const float *poses_in, float *poses_out, void *stream) {
     if (!wq || !idx) return fail(MCL_EINVAL, "resample: NULL wq or idx");
     if (N < 1) return fail(MCL_EINVAL, "resample: need N >= 1");
     if (N > MCL_MAX_PARTICLES) return fail(MCL_ERANGE, "resample: N above the limit");
@@ -130,7 +132,8 @@ extern "C" mcl_status mcl_resample(const uint64_t *wq, int32_t N, uint64_t u, in
         overlaps(poses_out, pb, idx, (size_t)N * 4) || overlaps(idx, (size_t)N * 4, wq, (size_t)N * 8) ||
         overlaps(idx, (size_t)N * 4, poses_in, pb))
         return fail(MCL_EINVAL, "resample: overlapping buffers");
-    return launch_resample(wq, N, u, idx, poses_in, poses_out, static_cast<hipStream_t>(stream));
+    return launch_resample(wq, N, resample_draw(seed, tick), idx, poses_in, poses_out,
+                           static_cast<hipStream_t>(stream));
 }
 
 extern "C" mcl_status mcl_pose_estimate(const double *w, const float *poses, int32_t N, double *mean,
@@ -156,5 +159,6 @@ extern "C" mcl_status mcl_debug_voxel_indices(mcl_map map, const float *points, 
     if (K < 0 || N < 1) return fail(MCL_EINVAL, "debug_voxel_indices: need K >= 0 and N >= 1");
     if (K > 0 && !points) return fail(MCL_EINVAL, "debug_voxel_indices: NULL points with K > 0");
     if ((int64_t)N * K > ((int64_t)1 << 31)) return fail(MCL_ERANGE, "debug_voxel_indices: N*K above 2^31");
-    return launch_debug_indices(map, points, K, poses, N, lin_idx, static_cast<hipStream_t>(stream));
+    mcl_status st = launch_debug_indices(map, points, K, poses, N, lin_idx, static_cast<hipStream_t>(stream));
+    return st == MCL_OK ? note_map_use(map, static_cast<hipStream_t>(stream)) : st;
 }

@@ -53,6 +53,17 @@ struct SensorJob {
 constexpr int32_t kCoarseAuto = 0, kCoarseBytes = 1, kCoarseBits = 2;
 constexpr int kProbe = 2;  // probe particles per chunk; LDS when over 3/4 of their lookups read in place
 
+// The resampling draw of a filter's update: u = splitmix64(seed ^ splitmix64(tick)),
+// splitmix64(x) the output of SplitMix64 (Steele, Lea and Flood, 2014) from
+// state x.  Host code: the draw is computed when the work is enqueued.
+inline uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+inline uint64_t resample_draw(uint64_t seed, uint64_t tick) { return splitmix64(seed ^ splitmix64(tick)); }
+
 // Weight normalisation and resampling of one filter.
 constexpr int kWThreads = 256;
 constexpr int kWPer = 16;

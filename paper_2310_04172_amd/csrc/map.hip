@@ -448,9 +448,41 @@ extern "C" mcl_status mcl_map_upload(const mcl_map_desc *desc, const void *host_
 
 extern "C" size_t mcl_map_bytes(mcl_map map) { return map ? map->bytes + map->tri_bytes : 0; }
 
+namespace mcl {
+mcl_status note_map_use(mcl_map_s *map, hipStream_t stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return fail(MCL_EDEVICE, "map use: stream query failed");
+    if (cs != hipStreamCaptureStatusNone) return MCL_OK;
+    std::lock_guard<std::mutex> lk(map->uses_mu);
+    hipEvent_t ev = nullptr;
+    for (auto &u : map->uses)
+        if (u.first == stream) ev = u.second;
+    if (!ev) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return fail(MCL_EDEVICE, "map use: event creation failed");
+        map->uses.emplace_back(stream, ev);
+    }
+    if (hipEventRecord(ev, stream) != hipSuccess) return fail(MCL_EDEVICE, "map use: event record failed");
+    return MCL_OK;
+}
+}  // namespace mcl
+
 extern "C" mcl_status mcl_map_free(mcl_map map) {
     if (!map) return fail(MCL_EINVAL, "map_free: NULL map");
     hipError_t e = hipSuccess;
+    {
+        // deferred: the work enqueued on the map completes before its memory goes
+        std::lock_guard<std::mutex> lk(map->uses_mu);
+        for (auto &u : map->uses) {
+            if (hipEventSynchronize(u.second) != hipSuccess) e = hipErrorInvalidValue;
+            (void)hipEventDestroy(u.second);
+        }
+        map->uses.clear();
+    }
+    if (e != hipSuccess) {
+        delete map;
+        return fail(MCL_EDEVICE, "map_free: waiting for the map's work failed (its memory is kept)");
+    }
     if (map->dev) e = hipFree(map->dev);
     if (map->sp_table && hipFree(map->sp_table) != hipSuccess) e = hipErrorInvalidValue;
     if (map->sp_pool && hipFree(map->sp_pool) != hipSuccess) e = hipErrorInvalidValue;

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "mcl.h"
 
@@ -136,6 +139,10 @@ struct mcl_map_s {
     bool sparse;        // coarse table + brick pool (view.base and view.mask unused)
     mcl::SparseView sp;
     void *sp_table, *sp_pool;
+    // Work enqueued on the map: one event per stream that has read it, recorded
+    // after the last such work (mcl_map_free waits for all of them).
+    std::mutex uses_mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 namespace mcl {
@@ -153,6 +160,11 @@ mcl_status check_launch(const char *what);
 
 // Workspace per stream, grown on demand (never shrinks until unload).
 void *workspace(hipStream_t stream, size_t bytes);
+
+// Record that work reading `map` has been enqueued on `stream` (an event after
+// it, so that mcl_map_free can wait for it).  Nothing is recorded while the
+// stream is being captured into a graph.
+mcl_status note_map_use(mcl_map_s *map, hipStream_t stream);
 
 inline int elem_size(int32_t dtype) { return dtype == MCL_TSDF_I16 ? 2 : dtype == MCL_TSDF_I8 ? 1 : 4; }
 

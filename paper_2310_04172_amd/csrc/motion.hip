@@ -57,8 +57,11 @@ struct Delta {
 };
 
 // pin and pout may be the same array (each thread reads its particle before
-// writing it), so neither is declared restrict.
-__global__ __launch_bounds__(256) void motion_kernel(const float *pin, float *pout, int N, Delta d,
+// writing it), so neither is declared restrict.  kMean: every particle starts
+// from the same pose `mean` (pin unused) - the initialisation round a pose
+// estimate, which is the motion update of N copies of the estimate.
+template <bool kMean>
+__global__ __launch_bounds__(256) void motion_kernel(const float *pin, float *pout, int N, Delta d, Delta mean,
                                                      float sigma_t, float sigma_r, uint64_t seed, uint64_t step) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(256) void motion_kernel(const float *pin, float *po
     }
     float P[12];
 #pragma unroll
-    for (int j = 0; j < 12; ++j) P[j] = pin[(size_t)j * N + n];
+    for (int j = 0; j < 12; ++j) P[j] = kMean ? mean.m[j] : pin[(size_t)j * N + n];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
 #pragma unroll
@@ -267,14 +270,32 @@ extern "C" mcl_status mcl_motion_update(const float *poses_in, float *poses_out,
     const size_t pb = (size_t)12 * N * 4;
     const auto a = reinterpret_cast<uintptr_t>(poses_in), b = reinterpret_cast<uintptr_t>(poses_out);
     if (a != b && a < b + pb && b < a + pb) return fail(MCL_EINVAL, "motion_update: poses_out partly overlaps poses_in");
-    Delta d;
+    Delta d, none{};
     for (int i = 0; i < 12; ++i) {
         if (!std::isfinite(delta[i])) return fail(MCL_EINVAL, "motion_update: delta must be finite");
         d.m[i] = delta[i];
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    motion_kernel<<<(N + 255) / 256, 256, 0, s>>>(poses_in, poses_out, N, d, sigma_t, sigma_r, seed, step);
+    motion_kernel<false><<<(N + 255) / 256, 256, 0, s>>>(poses_in, poses_out, N, d, none, sigma_t, sigma_r, seed, step);
     return check_launch("motion_kernel");
+}
+
+extern "C" mcl_status mcl_init_gaussian(float *poses, int32_t N, const float *mean, float sigma_t, float sigma_r,
+                                        uint64_t seed, uint64_t step, void *stream) {
+    if (!poses || !mean) return fail(MCL_EINVAL, "init_gaussian: NULL poses or mean");
+    if (N < 1) return fail(MCL_EINVAL, "init_gaussian: need N >= 1");
+    if (N > MCL_MAX_PARTICLES) return fail(MCL_ERANGE, "init_gaussian: N above the limit");
+    if (!(std::isfinite(sigma_t) && sigma_t >= 0.0f && std::isfinite(sigma_r) && sigma_r >= 0.0f))
+        return fail(MCL_EINVAL, "init_gaussian: deviations must be finite and >= 0");
+    Delta id{}, m;
+    id.m[0] = id.m[4] = id.m[8] = 1.0f;
+    for (int i = 0; i < 12; ++i) {
+        if (!std::isfinite(mean[i])) return fail(MCL_EINVAL, "init_gaussian: mean must be finite");
+        m.m[i] = mean[i];
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    motion_kernel<true><<<(N + 255) / 256, 256, 0, s>>>(nullptr, poses, N, id, m, sigma_t, sigma_r, seed, step);
+    return check_launch("motion_kernel (initialisation round a pose)");
 }
 
 extern "C" mcl_status mcl_init_uniform(mcl_map map, float *poses, int32_t N, float max_tilt, uint64_t seed,
@@ -297,5 +318,6 @@ extern "C" mcl_status mcl_init_uniform(mcl_map map, float *poses, int32_t N, flo
         init_kernel<int8_t><<<blocks, 256, 0, s>>>(v, map->voxel, fi.prefix, fi.nchunks, fi.qx, fi.nfree, poses, N, max_tilt, seed);
     else
         init_kernel<float><<<blocks, 256, 0, s>>>(v, map->voxel, fi.prefix, fi.nchunks, fi.qx, fi.nfree, poses, N, max_tilt, seed);
-    return check_launch("init_kernel");
+    st = check_launch("init_kernel");
+    return st == MCL_OK ? note_map_use(map, s) : st;
 }

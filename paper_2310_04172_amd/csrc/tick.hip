@@ -194,6 +194,18 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         if (hipEventCreateWithFlags(&S.copied, hipEventDisableTiming) != hipSuccess)
             return fail(MCL_EDEVICE, "tick: event creation failed");
     }
+    // the previous tick's table copy must have left the staging buffer
+    if (S.pending) {
+        if (flags & MCL_TICK_NOWAIT) {
+            const hipError_t q = hipEventQuery(S.copied);
+            if (q == hipErrorNotReady)
+                return fail(MCL_EBUSY, "tick: the previous tick on this stream still holds the table staging buffer");
+            if (q != hipSuccess) return fail(MCL_EDEVICE, "tick: event query failed");
+        } else if (hipEventSynchronize(S.copied) != hipSuccess) {
+            return fail(MCL_EDEVICE, "tick: event wait failed");
+        }
+        S.pending = false;
+    }
     if (S.dev_bytes < need) {
         if (hipStreamSynchronize(stream) != hipSuccess) return fail(MCL_EDEVICE, "tick: synchronisation failed");
         drop_graphs(S);
@@ -204,9 +216,6 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         if (hipMalloc((void **)&S.dev, want) != hipSuccess) return fail(MCL_ENOMEM, "tick: workspace allocation failed");
         S.dev_bytes = want;
     }
-    // the previous tick's table copy must have left the staging buffer
-    if (S.pending && hipEventSynchronize(S.copied) != hipSuccess) return fail(MCL_EDEVICE, "tick: event wait failed");
-
     // launch shape and coarse-level mode: those tuned for the largest filter
     int big = 0;
     for (int j = 1; j < n_jobs; ++j)
@@ -263,7 +272,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             W.idx = F.idx;
             W.pin = F.poses_out ? F.poses : nullptr;
             W.pout = F.poses_out;
-            W.u = F.u;
+            W.u = resample_draw(F.seed, F.tick);
             W.elem0 = welem;
             W.blk0 = (int32_t)wblk;
             welem += F.N;
@@ -349,7 +358,22 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         }
         return launch_resample_src(wsrc, key.blocks, key.elems, stream);
     };
-    if (!use_graph) return chain();
+    // every map the tick reads: an event after its work (deferred mcl_map_free)
+    auto note_uses = [&]() -> mcl_status {
+        std::vector<mcl_map_s *> maps(n_jobs);
+        for (int j = 0; j < n_jobs; ++j) maps[j] = jobs[j].map;
+        std::sort(maps.begin(), maps.end());
+        maps.erase(std::unique(maps.begin(), maps.end()), maps.end());
+        for (mcl_map_s *m : maps) {
+            mcl_status st = note_map_use(m, stream);
+            if (st != MCL_OK) return st;
+        }
+        return MCL_OK;
+    };
+    if (!use_graph) {
+        mcl_status st = chain();
+        return st == MCL_OK ? note_uses() : st;
+    }
 
     auto it = S.graphs.find(key);
     if (it == S.graphs.end() && S.graphs.size() >= 32) drop_graphs(S);  // bound the cache
@@ -372,5 +396,5 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         it = S.graphs.emplace(key, exec).first;
     }
     if (hipGraphLaunch(it->second, stream) != hipSuccess) return fail(MCL_EDEVICE, "tick: graph launch failed");
-    return MCL_OK;
+    return note_uses();
 }

@@ -99,6 +99,7 @@ extern "C" mcl_status mcl_autotune(mcl_map map, const float *points, int32_t K, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != MCL_OK) return st;
+    if ((st = note_map_use(map, stream)) != MCL_OK) return st;
     {
         std::lock_guard<std::mutex> lk(g_tmu);
         g_tuned[{map->dtype, size_class(K), size_class(N)}] = bestc;

@@ -27,9 +27,9 @@ _lib = C.CDLL(LIB_PATH)
 _P = C.c_void_p
 _I = C.c_int32
 
-MCL_OK, MCL_EINVAL, MCL_ENOMEM, MCL_EDEVICE, MCL_ERANGE = 0, -1, -2, -3, -4
+MCL_OK, MCL_EINVAL, MCL_ENOMEM, MCL_EDEVICE, MCL_ERANGE, MCL_EBUSY = 0, -1, -2, -3, -4, -5
 MAX_JOBS = 4096
-TICK_GRAPH = 1
+TICK_GRAPH, TICK_NOWAIT = 1, 2
 LOOKUP_NEAREST, LOOKUP_TRILINEAR = 0, 1
 MAX_PARTICLES = 1 << 21
 MAX_POINTS = 1 << 20
@@ -44,7 +44,8 @@ class MapDesc(C.Structure):
 
 class FilterJob(C.Structure):
     _fields_ = [("map", _P), ("points", _P), ("K", C.c_int32), ("poses", _P), ("N", C.c_int32),
-                ("sigma", C.c_float), ("logw", _P), ("w", _P), ("wq", _P), ("log_z", _P), ("u", C.c_uint64),
+                ("sigma", C.c_float), ("logw", _P), ("w", _P), ("wq", _P), ("log_z", _P), ("seed", C.c_uint64),
+                ("tick", C.c_uint64),
                 ("idx", _P), ("poses_out", _P), ("est_mean", _P), ("est_idx", _P), ("est_pose", _P),
                 ("lookup", C.c_int32)]
 
@@ -59,11 +60,12 @@ _lib.mcl_map_upload_bricks.argtypes = [C.POINTER(MapDesc), C.c_int64, _P, _P, _P
 _lib.mcl_sensor_update.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_sensor_update_trilinear.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
-_lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, _P, _P, _P, _P]
+_lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, C.c_uint64, _P, _P, _P, _P]
 _lib.mcl_debug_voxel_indices.argtypes = [_P, _P, _I, _P, _I, _P, _P]
 _lib.mcl_pose_estimate.argtypes = [_P, _P, _I, _P, _P, _P, _P]
 _lib.mcl_motion_update.argtypes = [_P, _P, _I, _P, C.c_float, C.c_float, C.c_uint64, C.c_uint64, _P]
 _lib.mcl_init_uniform.argtypes = [_P, _P, _I, C.c_float, C.c_uint64, _P]
+_lib.mcl_init_gaussian.argtypes = [_P, _I, _P, C.c_float, C.c_float, C.c_uint64, C.c_uint64, _P]
 _lib.mcl_debug_philox.argtypes = [_P, _P]
 _lib.mcl_tick.argtypes = [C.POINTER(FilterJob), _I, _I, _P]
 _lib.mcl_job_bytes.argtypes = [_I, _I]
@@ -76,7 +78,7 @@ _lib.mcl_last_error.restype = C.c_char_p
 for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear", "mcl_normalize",
            "mcl_resample",
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_pose_estimate", "mcl_motion_update",
-           "mcl_init_uniform", "mcl_debug_philox"):
+           "mcl_init_uniform", "mcl_init_gaussian", "mcl_debug_philox"):
     getattr(_lib, _f).restype = C.c_int32
 
 
@@ -231,8 +233,8 @@ def normalize(logw, w=None, wq=None, log_z=None, want_w=True, stream=None):
     return w, wq, log_z
 
 
-def resample(wq, u: int, poses_in=None, poses_out=None, idx=None, stream=None):
-    """(idx int32 [N], poses_out [12, N] or None)."""
+def resample(wq, seed: int, tick: int, poses_in=None, poses_out=None, idx=None, stream=None):
+    """(idx int32 [N], poses_out [12, N] or None); the draw is selected by (seed, tick)."""
     import torch
     N = wq.shape[0]
     _dev(wq, torch.uint64, (N,), "wq")
@@ -240,8 +242,8 @@ def resample(wq, u: int, poses_in=None, poses_out=None, idx=None, stream=None):
         idx = torch.empty(N, dtype=torch.int32, device=wq.device)
     if poses_in is not None and poses_out is None:
         poses_out = torch.empty_like(poses_in)
-    _check(_lib.mcl_resample(_ptr(wq), N, C.c_uint64(int(u) & (2 ** 64 - 1)), _ptr(idx), _ptr(poses_in),
-                             _ptr(poses_out), _stream(stream)), "mcl_resample")
+    _check(_lib.mcl_resample(_ptr(wq), N, C.c_uint64(int(seed) & (2 ** 64 - 1)), C.c_uint64(int(tick) & (2 ** 64 - 1)),
+                             _ptr(idx), _ptr(poses_in), _ptr(poses_out), _stream(stream)), "mcl_resample")
     return idx, poses_out
 
 
@@ -289,6 +291,20 @@ def init_uniform(m: Map, N: int, max_tilt: float, seed: int, poses=None, device=
     return poses
 
 
+def init_gaussian(mean, N: int, sigma_t: float, sigma_r: float, seed: int, step: int = 0, poses=None, device=None,
+                  stream=None):
+    """[12, N] poses spread round the pose `mean` (12 floats: R row-major, t), see include/mcl.h."""
+    import torch
+    if poses is None:
+        poses = torch.empty((12, N), dtype=torch.float32, device=device or "cuda")
+    _dev(poses, torch.float32, (12, N), "poses")
+    mv = np.ascontiguousarray(np.asarray(mean, np.float32).reshape(12))
+    _check(_lib.mcl_init_gaussian(_ptr(poses), N, mv.ctypes.data_as(C.c_void_p), float(sigma_t), float(sigma_r),
+                                  C.c_uint64(int(seed) & (2 ** 64 - 1)), C.c_uint64(int(step) & (2 ** 64 - 1)),
+                                  _stream(stream)), "mcl_init_gaussian")
+    return poses
+
+
 def debug_philox(counter, key) -> np.ndarray:
     """Philox4x32-10 on the device (test support): 4 uint32 words."""
     ck = np.ascontiguousarray(list(counter) + list(key), np.uint32)
@@ -307,14 +323,6 @@ def debug_voxel_indices(m: Map, points, poses, out=None, stream=None):
     return out
 
 
-def score_const(m: Map, sigma: float) -> float:
-    """c = s^2 / (2 sigma^2) as the library computes it (float64, rounded to float32)."""
-    Q = {"i16": 32767, "i8": 127, "f32": 1}[m.dtype]
-    s = 1.0 if m.dtype == "f32" else float(np.float32(m.tau)) / Q
-    sg = float(np.float32(sigma))
-    return float(np.float32((s * s) / (2.0 * sg * sg)))
-
-
 class Filter:
     """Device buffers of one filter for a batched tick (see include/mcl.h, mcl_tick).
 
@@ -322,14 +330,15 @@ class Filter:
     buffers are allocated here unless given.
     """
 
-    def __init__(self, m: Map, points, poses, sigma: float, u: int, want_w: bool = True, resample_poses: bool = True,
-                 want_estimate: bool = False, trilinear: bool = False):
+    def __init__(self, m: Map, points, poses, sigma: float, seed: int, tick: int = 0, want_w: bool = True,
+                 resample_poses: bool = True, want_estimate: bool = False, trilinear: bool = False):
         import torch
         self.map = m
         self.points = points
         self.poses = poses
         self.sigma = float(sigma)
-        self.u = int(u)
+        self.seed = int(seed)        # resampling draw of this update: (seed, tick)
+        self.tick = int(tick)
         self.trilinear = bool(trilinear)   # the sensor update as mcl_sensor_update_trilinear
         N = poses.shape[1]
         dev = poses.device
@@ -360,14 +369,22 @@ class Filter:
             _dev(self.points, torch.float32, (3, self.K), "points")
         return FilterJob(self.map.handle, _ptr(self.points) if self.K else None, self.K, _ptr(self.poses), self.N,
                          self.sigma, _ptr(self.logw), _ptr(self.w), _ptr(self.wq), _ptr(self.log_z),
-                         self.u & (2 ** 64 - 1), _ptr(self.idx), _ptr(self.poses_out), _ptr(self.est_mean),
+                         self.seed & (2 ** 64 - 1), self.tick & (2 ** 64 - 1), _ptr(self.idx), _ptr(self.poses_out),
+                         _ptr(self.est_mean),
                          _ptr(self.est_idx), _ptr(self.est_pose), LOOKUP_TRILINEAR if self.trilinear else LOOKUP_NEAREST)
 
 
-def tick(filters, graph: bool = False, stream=None):
-    """One batched update (sensor, normalise, pose estimate if asked, resample) of every filter."""
+def tick(filters, graph: bool = False, stream=None, nowait: bool = False) -> bool:
+    """One batched update (sensor, normalise, pose estimate if asked, resample) of every filter.
+    nowait: return False (nothing enqueued) instead of blocking while the stream's
+    previous tick still holds the table staging buffer (MCL_EBUSY)."""
     arr = (FilterJob * len(filters))(*[f.job() for f in filters])
-    _check(_lib.mcl_tick(arr, len(filters), TICK_GRAPH if graph else 0, _stream(stream)), "mcl_tick")
+    flags = (TICK_GRAPH if graph else 0) | (TICK_NOWAIT if nowait else 0)
+    st = _lib.mcl_tick(arr, len(filters), flags, _stream(stream))
+    if st == MCL_EBUSY and nowait:
+        return False
+    _check(st, "mcl_tick")
+    return True
 
 
 def job_bytes(N: int, K: int) -> int:

@@ -7,9 +7,12 @@ already on the GPU into one batched tick (``mcl_tick``: sensor update,
 normalisation and resampling of every filter in one launch per stage).  Up to
 ``n_streams * depth`` ticks are in flight: with two streams a new tick runs
 beside the previous one on the device; with one stream and depth 2 the next
-tick is queued behind the running one, so the device never waits for the host
-between ticks and a tick never shares the device with another.
+tick is queued behind the running one.
 
+* Each request carries its scan in pinned host memory.  When the request is
+  taken, the scan is copied to the robot's device buffer on a copy stream and
+  the tick's stream waits for that copy (an event), so uploads overlap the
+  ticks already running; the latency includes the upload.
 * Latest wins: a robot keeps at most one waiting request; a newer scan replaces
   an older one that has not started (counted as dropped, as a localiser drops
   stale scans).  A robot has at most one update in flight.
@@ -18,12 +21,17 @@ between ticks and a tick never shares the device with another.
   every robot's pose is kept as fresh as the device allows; under overload the
   scan served is then one that arrived recently, not one that waited longest).
 * Admission: a robot becomes resident when its device state (``mcl_job_bytes``)
-  fits the memory budget; until then its request waits.
+  fits the memory budget; until then its request waits.  Its particle set is
+  made by the library's initialisation calls, on the stream of the tick that
+  first serves it, so the tick is ordered after it.
+* Resampling draws: robot r's n-th completed update uses seed
+  ``seed * 2^32 + r`` and tick n (the library's draw), so results do not depend
+  on batching or timing.
 * Latency is measured from a request's arrival to the GPU completion of its
   tick, read from device events against a reference event.
 
-The particle sets themselves (initial distributions, phase changes) come from a
-caller-supplied function: particle initialisation is not part of this path.
+The robots' initial particle sets (global or round a pose, per phase) come from
+a caller-supplied function of (robot, phase, stream) that calls the library.
 """
 
 from __future__ import annotations
@@ -37,29 +45,47 @@ import numpy as np
 from . import mcl
 
 
-def splitmix64(x: int) -> int:
-    """SplitMix64 (Steele, Lea, Flood 2014): one 64-bit output for a 64-bit state."""
-    x = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
-    z = x
-    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
-    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
-    return z ^ (z >> 31)
+def robot_seed(seed: int, rid: int) -> int:
+    """Resampling seed of robot `rid` in an engine seeded with `seed`."""
+    return ((int(seed) << 32) + int(rid)) & (2 ** 64 - 1)
 
 
-def update_draw(seed: int, robot: int, update: int) -> int:
-    """Resampling draw of a robot's n-th update: independent of batching and timing."""
-    return splitmix64(splitmix64(seed ^ (robot << 20)) ^ update)
+class LibraryInit:
+    """Initial particle sets made by the library, for Engine's init_particles:
+    a 'global' phase uniform over the map's free voxels (mcl_init_uniform,
+    roll and pitch within max_tilt), a 'track' phase round the robot's pose
+    estimate (mcl_init_gaussian).  counts[rid][phase] is the particle count,
+    means[rid] the estimate (12 floats, R row-major and t).  The random numbers
+    of robot r's phase p are fixed by (seed, r, p)."""
+
+    PHASES = ("global", "track")
+
+    def __init__(self, counts, means, max_tilt: float, sigma_t: float, sigma_r: float, seed: int = 0):
+        self.counts, self.means = counts, means
+        self.max_tilt, self.sigma_t, self.sigma_r = float(max_tilt), float(sigma_t), float(sigma_r)
+        self.seed = int(seed)
+
+    def __call__(self, r, phase: str, stream, probe: bool = False):
+        n = int(self.counts[r.rid][phase])
+        if probe:
+            return n
+        key = robot_seed(self.seed, r.rid)
+        step = self.PHASES.index(phase)
+        if phase == "global":
+            return mcl.init_uniform(r.map, n, self.max_tilt, key ^ (step << 62), stream=stream)
+        return mcl.init_gaussian(self.means[r.rid], n, self.sigma_t, self.sigma_r, key, step, stream=stream)
 
 
 @dataclass
 class Robot:
     rid: int
     map: "mcl.Map"
-    points: object              # device [3, K]
+    host_points: object         # pinned host [3, K] float32: the scan every request carries
     sigma: float
     phases: list                # [(n_updates or None for the rest, phase name)]
     completed: int = 0
     phase_i: int = 0
+    points: object = None       # device [3, K] upload target (while resident)
     poses: object = None        # device [12, N] current particle set
     spare: object = None        # device [12, N] resample target
     filt: object = None
@@ -71,7 +97,7 @@ class Robot:
 
     @property
     def K(self):
-        return self.points.shape[1]
+        return self.host_points.shape[1]
 
     @property
     def phase(self):
@@ -86,6 +112,8 @@ class ServeStats:
     arrived: int = 0
     evals: int = 0
     ticks: int = 0
+    busy: int = 0               # ticks refused by the library (MCL_EBUSY) and retried later
+    uploaded_bytes: int = 0
     max_resident_bytes: int = 0
     wall_s: float = 0.0
 
@@ -94,17 +122,25 @@ class ServeStats:
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "completed": self.completed, "arrived": self.arrived,
                 "dropped": self.dropped, "drop_rate": self.dropped / max(1, self.arrived),
-                "evals_per_s": self.evals / max(self.wall_s, 1e-9), "ticks": self.ticks,
+                "evals_per_s": self.evals / max(self.wall_s, 1e-9), "ticks": self.ticks, "busy": self.busy,
+                "uploaded_MB": self.uploaded_bytes / 1e6,
                 "max_resident_GiB": self.max_resident_bytes / 2 ** 30, "wall_s": self.wall_s}
 
 
 class Engine:
     """Continuous-batching server over mcl_tick (or, with plain=True, the same
-    trace served one request at a time with the single-filter calls)."""
+    trace served one request at a time with the single-filter calls).
+
+    init_particles(robot, phase, stream, probe=False): with probe, the particle
+    count of the robot's set for that phase; else the set itself, a device
+    [12, N] tensor made on `stream` by the library's initialisation calls.
+    on_complete(robot, filter): optional, called when an update has completed,
+    before the resampled set becomes the robot's particle set (tests read the
+    update's inputs and outputs there)."""
 
     def __init__(self, robots, init_particles, budget_bytes: int = 64 << 30, max_evals_per_tick: float = 1.2e11,
                  n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0, depth: int = 1,
-                 order: str = "fifo"):
+                 order: str = "fifo", on_complete=None):
         import torch
         self.torch = torch
         self.robots = robots
@@ -114,7 +150,9 @@ class Engine:
         self.plain = plain
         self.graph = graph and not plain
         self.seed = seed
+        self.on_complete = on_complete
         self.streams = [torch.cuda.Stream() for _ in range(1 if plain else n_streams)]
+        self.copy_stream = torch.cuda.Stream()
         self.depth = 1 if plain else max(1, int(depth))    # ticks in flight per stream
         if order not in ("fifo", "stale"):
             raise ValueError("order must be 'fifo' or 'stale'")
@@ -123,16 +161,20 @@ class Engine:
         self.stats = ServeStats()
 
     # -------------------------------------------------------------- state
-    def _admit(self, r: Robot) -> bool:
+    def _admit(self, r: Robot, stream) -> bool:
+        """Make r resident: its buffers and initial particle set, on `stream`."""
         if r.filt is not None:
             return True
-        N = self.init_particles(r, r.phase, probe=True)
+        torch = self.torch
+        N = self.init_particles(r, r.phase, stream, probe=True)
         need = mcl.job_bytes(N, r.K)
         if self.used + need > self.budget:
             return False
-        r.poses = self.init_particles(r, r.phase)
-        r.spare = self.torch.empty_like(r.poses)
-        r.filt = mcl.Filter(r.map, r.points, r.poses, r.sigma, 0, want_w=False)
+        with torch.cuda.stream(stream):
+            r.poses = self.init_particles(r, r.phase, stream)
+            r.spare = torch.empty_like(r.poses)
+            r.points = torch.empty((3, r.K), dtype=torch.float32, device=r.poses.device)
+            r.filt = mcl.Filter(r.map, r.points, r.poses, r.sigma, robot_seed(self.seed, r.rid), want_w=False)
         r.filt.poses_out = r.spare
         r.bytes = need
         self.used += need
@@ -141,11 +183,13 @@ class Engine:
 
     def _release(self, r: Robot):
         r.filt = None
-        r.poses = r.spare = None
+        r.poses = r.spare = r.points = None
         self.used -= r.bytes
         r.bytes = 0
 
     def _finish(self, r: Robot, t_done: float):
+        if self.on_complete is not None:
+            self.on_complete(r, r.filt)
         self.stats.latencies_ms.append((t_done - r.in_flight) * 1e3)
         self.stats.completed += 1
         n_evals = r.poses.shape[1] * r.K
@@ -171,6 +215,35 @@ class Engine:
             if i == r.phase_i:
                 return n
         return None
+
+    def _upload(self, batch, s):
+        """Copy the batch's scans from pinned host memory on the copy stream; the
+        tick's stream `s` waits for them."""
+        torch = self.torch
+        cs = self.copy_stream
+        cs.wait_stream(s)                # the device buffers were made on s (admission)
+        with torch.cuda.stream(cs):
+            for r in batch:
+                r.points.copy_(r.host_points, non_blocking=True)
+                self.stats.uploaded_bytes += r.host_points.numel() * 4
+        ev = torch.cuda.Event()
+        ev.record(cs)
+        s.wait_event(ev)
+
+    def _submit(self, batch, s) -> bool:
+        """Enqueue one update of every robot in `batch` on stream s; False if
+        the library reports the stream's staging buffer busy (nothing enqueued)."""
+        torch = self.torch
+        for r in batch:
+            r.filt.tick = r.completed
+        with torch.cuda.stream(s):
+            if self.plain:
+                f = batch[0].filt
+                mcl.sensor_update(f.map, f.points, f.poses, f.sigma, f.logw, s)
+                mcl.normalize(f.logw, None, f.wq, f.log_z, want_w=False, stream=s)
+                mcl.resample(f.wq, f.seed, f.tick, f.poses, f.poses_out, f.idx, s)
+                return True
+            return mcl.tick([r.filt for r in batch], graph=self.graph, stream=s, nowait=True)
 
     # ---------------------------------------------------------------- run
     def run(self, trace, drain: bool = True) -> ServeStats:
@@ -208,37 +281,33 @@ class Engine:
                     progressed = True
             free = [i for i, b in enumerate(busy) if b < self.depth]
             if free:
+                si = free[0]
+                s = self.streams[si]
                 key = (lambda r: r.pending) if self.order == "fifo" else (lambda r: (r.last_done, r.pending))
                 cands = sorted((r for r in self.robots if r.pending is not None and r.in_flight is None), key=key)
                 batch, evals = [], 0.0
                 for r in cands:
-                    if not self._admit(r):
-                        continue
-                    e = r.poses.shape[1] * r.K
+                    e = self.init_particles(r, r.phase, s, probe=True) * r.K if r.filt is None else \
+                        r.poses.shape[1] * r.K
                     if batch and (self.plain or evals + e > self.max_evals):
                         break
+                    if not self._admit(r, s):
+                        continue
                     batch.append(r)
                     evals += e
                 if batch:
-                    si = free[0]
-                    s = self.streams[si]
-                    for r in batch:
-                        r.in_flight, r.pending = r.pending, None
-                        r.filt.u = update_draw(self.seed, r.rid, r.completed)
-                    with torch.cuda.stream(s):
-                        if self.plain:
-                            f = batch[0].filt
-                            mcl.sensor_update(f.map, f.points, f.poses, f.sigma, f.logw, s)
-                            mcl.normalize(f.logw, None, f.wq, f.log_z, want_w=False, stream=s)
-                            mcl.resample(f.wq, f.u, f.poses, f.poses_out, f.idx, s)
-                        else:
-                            mcl.tick([r.filt for r in batch], graph=self.graph, stream=s)
+                    self._upload(batch, s)
+                    if self._submit(batch, s):
+                        for r in batch:
+                            r.in_flight, r.pending = r.pending, None
                         ev = torch.cuda.Event(enable_timing=True)
                         ev.record(s)
-                    inflight.append((ev, batch, si))
-                    busy[si] += 1
-                    st.ticks += 1
-                    progressed = True
+                        inflight.append((ev, batch, si))
+                        busy[si] += 1
+                        st.ticks += 1
+                        progressed = True
+                    else:
+                        st.busy += 1
             if ptr >= len(trace) and not inflight and (not drain or not any(
                     r.pending is not None for r in self.robots)):
                 break

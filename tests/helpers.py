@@ -37,3 +37,41 @@ def poses_from(R: np.ndarray, t: np.ndarray) -> np.ndarray:
     p[:9] = R.reshape(-1, 9).T
     p[9:] = np.asarray(t).T
     return p
+
+
+def score_const(dtype: str, tau: float, sigma: float) -> float:
+    """The library's c = s^2 / (2 sigma^2) (float64, rounded to float32), with
+    s = tau / Q metres per stored unit (1 for float32 maps), as its header
+    states: tests that need the exact float32 constant recompute it here."""
+    Q = {"i16": 32767, "i8": 127, "f32": 1}[dtype]
+    s = 1.0 if dtype == "f32" else float(np.float32(tau)) / Q
+    sg = float(np.float32(sigma))
+    return float(np.float32((s * s) / (2.0 * sg * sg)))
+
+
+_M64 = 2 ** 64 - 1
+
+
+def _unxorshift(y: int, s: int) -> int:
+    x = y
+    for _ in range(64 // s + 1):
+        x = y ^ (x >> s)
+    return x & _M64
+
+
+def splitmix64_state_for(u: int) -> int:
+    """The state whose SplitMix64 output is u (the output map is a bijection)."""
+    z = _unxorshift(u & _M64, 31)
+    z = (z * pow(0x94D049BB133111EB, -1, 2 ** 64)) & _M64
+    z = _unxorshift(z, 27)
+    z = (z * pow(0xBF58476D1CE4E5B9, -1, 2 ** 64)) & _M64
+    z = _unxorshift(z, 30)
+    return (z - 0x9E3779B97F4A7C15) & _M64
+
+
+def seed_for_draw(oracle, u: int, tick: int = 0) -> int:
+    """A filter seed whose resampling draw at `tick` is u (so that tests can pick
+    an edge-case offset); checked against the oracle's draw."""
+    seed = splitmix64_state_for(u) ^ oracle.splitmix64(tick)
+    assert oracle.resample_draw(seed, tick) == u & _M64
+    return seed

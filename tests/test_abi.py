@@ -50,8 +50,9 @@ def test_argument_errors_are_reported_on_the_host(mcl):
     assert lib.mcl_normalize(None, 10, None, fake, None, None) == mcl.MCL_EINVAL
     assert lib.mcl_normalize(fake, 0, None, P(0x9000), None, None) == mcl.MCL_EINVAL
     assert lib.mcl_normalize(fake, mcl.MAX_PARTICLES + 1, None, P(0x90000000), None, None) == mcl.MCL_ERANGE
-    assert lib.mcl_resample(fake, 10, 0, P(0x9000), fake, None, None) == mcl.MCL_EINVAL
-    assert lib.mcl_resample(fake, 0, 0, P(0x9000), None, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_resample(fake, 10, 0, 0, P(0x9000), fake, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_resample(fake, 0, 0, 0, P(0x9000), None, None, None) == mcl.MCL_EINVAL
+    assert lib.mcl_map_free(None) == mcl.MCL_EINVAL
     assert lib.mcl_pose_estimate(None, fake, 10, P(0x9000), None, None, None) == mcl.MCL_EINVAL
     assert lib.mcl_pose_estimate(fake, fake, 0, P(0x90000), None, None, None) == mcl.MCL_EINVAL
     assert lib.mcl_pose_estimate(fake, fake, mcl.MAX_PARTICLES + 1, P(0x9000000000), None, None,
@@ -97,9 +98,9 @@ def test_tick_and_tuning_argument_errors(mcl):
     P = C.c_void_p
     assert lib.mcl_tick(None, 1, 0, None) == mcl.MCL_EINVAL
     jobs = (mcl.FilterJob * 2)()
-    jobs[0] = mcl.FilterJob(P(0x1000), P(0x2000), 10, P(0x3000), 10, 0.1, P(0x4000), None, P(0x5000), None, 7,
+    jobs[0] = mcl.FilterJob(P(0x1000), P(0x2000), 10, P(0x3000), 10, 0.1, P(0x4000), None, P(0x5000), None, 7, 0,
                             P(0x6000), None)
-    jobs[1] = mcl.FilterJob(P(0x1000), P(0x2000), 10, P(0x3000), 10, -1.0, P(0x4000), None, P(0x5000), None, 7,
+    jobs[1] = mcl.FilterJob(P(0x1000), P(0x2000), 10, P(0x3000), 10, -1.0, P(0x4000), None, P(0x5000), None, 7, 0,
                             P(0x6000), None)
     assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL
     assert b"job 1" in lib.mcl_last_error()
@@ -121,6 +122,22 @@ def test_tick_and_tuning_argument_errors(mcl):
     assert lib.mcl_set_launch_config(0, 1000, 1000, C.byref(bad)) == mcl.MCL_EINVAL
     assert lib.mcl_set_launch_config(5, 1000, 1000, None) == mcl.MCL_EINVAL
     assert lib.mcl_autotune(None, None, 0, None, 0, 0.1, None, None, None) == mcl.MCL_EINVAL
+
+
+def test_binding_constants_match_the_header(mcl):
+    """Status codes, flags and limits the binding uses are the header's."""
+    text = open(HEADER).read()
+    want = {"MCL_OK": mcl.MCL_OK, "MCL_EINVAL": mcl.MCL_EINVAL, "MCL_ENOMEM": mcl.MCL_ENOMEM,
+            "MCL_EDEVICE": mcl.MCL_EDEVICE, "MCL_ERANGE": mcl.MCL_ERANGE, "MCL_EBUSY": mcl.MCL_EBUSY,
+            "MCL_TICK_GRAPH": mcl.TICK_GRAPH, "MCL_TICK_NOWAIT": mcl.TICK_NOWAIT, "MCL_MAX_JOBS": mcl.MAX_JOBS,
+            "MCL_LOOKUP_NEAREST": mcl.LOOKUP_NEAREST, "MCL_LOOKUP_TRILINEAR": mcl.LOOKUP_TRILINEAR,
+            "MCL_WQ_SHIFT": mcl.WQ_SHIFT}
+    for name, val in want.items():
+        m = re.search(r"#define\s+" + name + r"\s+\(?(-?\d+)\)?", text)
+        assert m and int(m.group(1)) == val, name
+    for name, val in (("MCL_MAX_PARTICLES", mcl.MAX_PARTICLES), ("MCL_MAX_POINTS", mcl.MAX_POINTS)):
+        m = re.search(r"#define\s+" + name + r"\s+\(1 << (\d+)\)", text)
+        assert m and 1 << int(m.group(1)) == val, name
 
 
 def test_binding_structs_match_the_header(mcl, tmp_path):

@@ -3,7 +3,8 @@
 The contract: every filter in a tick gets bit for bit the results of the
 single-filter calls (sensor update, normalisation, pose estimate for the
 filters that ask for one, resampling), eagerly or replayed from a captured
-graph, and no launch shape changes any result.
+graph, and no launch shape changes any result.  The batched workload itself
+(64 filters on the warehouse map) is checked against the CPU oracle directly.
 """
 
 import sys
@@ -11,6 +12,7 @@ import sys
 import numpy as np
 import pytest
 
+from tests import checks
 from tests.helpers import make_map, poses_from, random_rotations
 from workloads import configs
 from workloads.tsdf import f32, to_bricks
@@ -68,7 +70,7 @@ def job_set(torch, mcl, seed, maps, specs):
 def single(torch, mcl, f):
     lw = (mcl.sensor_update_trilinear if f.trilinear else mcl.sensor_update)(f.map, f.points, f.poses, f.sigma)
     w, wq, lz = mcl.normalize(lw)
-    idx, pout = mcl.resample(wq, f.u, f.poses)
+    idx, pout = mcl.resample(wq, f.seed, f.tick, f.poses)
     est = mcl.pose_estimate(w, f.poses) if f.est_mean is not None else ()
     torch.cuda.synchronize()
     return [x.cpu().numpy() for x in (lw, w, wq, lz, idx, pout, *est)]
@@ -251,3 +253,81 @@ def test_runs_do_not_change_bits(torch, mcl, maps):
     mcl.tick([small, big])
     assert_same(outputs(torch, small), alone, "small filter in a large tick")
     assert_same(outputs(torch, big), single(torch, mcl, big), "large filter")
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    return configs.config4()
+
+
+def test_config4_tick_matches_oracle(torch, mcl, oracle_lib, cfg4):
+    """The batched workload (64 filters on the 1024x1024x128 warehouse map,
+    N log-uniform in [2048, 524288], VLP-16 16x1800 and OS0-64 64x1024 scans) as
+    one graph-replayed tick, then the same graph replayed on the resampled sets
+    (tick 1).  Every filter against the oracle: 64 seeded particles'
+    log-weights within 1e-5, the whole normalisation within its float64 bound
+    and the whole resampling bit for bit (on the GPU's own weights), the pose
+    estimate of every eighth filter within its bound."""
+    tmap, specs = cfg4
+    say(f"case: config-4 tick vs oracle, {len(specs)} filters, sum N {sum(f.N for f in specs)}")
+    m = mcl.Map.from_tsdf(tmap)
+    filters = [mcl.Filter(m, dev(torch, sp.points), dev(torch, sp.poses), sp.sigma, sp.seed, want_w=True,
+                          want_estimate=i % 8 == 0) for i, sp in enumerate(specs)]
+    rng = np.random.default_rng(404)
+    s = torch.cuda.Stream()
+    Ns = [sp.N for sp in specs]
+    assert min(Ns) < 4096 and max(Ns) > 300000
+    for tick in (0, 1):
+        inputs = [f.poses.cpu().numpy() for f in filters]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            mcl.tick(filters, graph=True, stream=s)
+        s.synchronize()
+        for i, (f, sp, P) in enumerate(zip(filters, specs, inputs)):
+            what = f"tick {tick} filter {i} (N={f.N}, K={f.K})"
+            sub = np.sort(rng.choice(f.N, size=min(64, f.N), replace=False))
+            checks.check_update(oracle_lib, tmap, sp.points, P, sp.sigma, f.logw.cpu().numpy(),
+                                f.wq.cpu().numpy(), f.log_z.cpu().numpy()[0], f.idx.cpu().numpy(), f.seed,
+                                f.tick, sub, poses_out=f.poses_out.cpu().numpy(), w=f.w.cpu().numpy(), what=what)
+            if f.est_mean is not None:
+                checks.check_estimate(f.est_mean.cpu().numpy(), f.est_idx.cpu().numpy()[0],
+                                      f.est_pose.cpu().numpy(), f.w.cpu().numpy(), P, what)
+        say(f"tick {tick}: every filter matches the oracle")
+        for f in filters:    # the resampled set is the next tick's input
+            f.poses, f.poses_out = f.poses_out, f.poses
+            f.tick += 1
+
+
+def test_tick_nowait_and_deferred_map_free(torch, mcl, maps):
+    """A tick with MCL_TICK_NOWAIT returns MCL_EBUSY (enqueuing nothing) while
+    the stream's previous tick still holds the table staging buffer, and runs
+    once it is free; mcl_map_free waits for the work enqueued on the map, so a
+    map freed right after its update leaves the results intact."""
+    say("case: tick nowait (EBUSY) and deferred map free")
+    w = configs.config2(n_particles=262144)
+    m = mcl.Map.from_tsdf(w.tmap)
+    P, X = dev(torch, w.poses), dev(torch, w.points)
+    s = torch.cuda.Stream()
+    a, b = job_set(torch, mcl, 61, maps, [(0, 3000, 5000), (1, 2000, 4000)])
+    with torch.cuda.stream(s):
+        mcl.tick([a, b], stream=s)      # the stream's tick workspace, grown once (growth synchronises)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        lw = mcl.sensor_update(m, X, P, w.sigma, stream=s)     # ~5 ms of work ahead of the ticks
+        assert mcl.tick([a], stream=s, nowait=True)            # staging buffer free: enqueued
+        busy = not mcl.tick([b], stream=s, nowait=True)        # the first tick's table copy has not run yet
+        assert mcl.tick([b], stream=s)                         # waits for the buffer, then runs
+    assert busy, "expected MCL_EBUSY while the previous tick's table copy waits behind the sensor update"
+    ref = mcl.sensor_update(m, X, P, w.sigma, stream=s)
+    s.synchronize()
+    for f in (a, b):
+        assert_same(outputs(torch, f), single(torch, mcl, f), "tick after EBUSY")
+    # deferred free: update on the side stream, free at once, then reuse memory
+    with torch.cuda.stream(s):
+        out = mcl.sensor_update(m, X, P, w.sigma, stream=s)
+    m.close()
+    junk = torch.full((64 << 20,), -7, dtype=torch.int16, device="cuda")   # may take the freed memory
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref) and torch.equal(lw, ref)
+    del junk

@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 from oracle import estimate as E
+from tests import checks
 from tests.helpers import poses_from, random_rotations
 from workloads import configs
 
@@ -55,34 +56,7 @@ def run_gpu(torch, mcl, w, P):
 def check(torch, mcl, w, P, what):
     say(f"estimate {what}: N={P.shape[1]}")
     g_mean, g_b, g_bp = run_gpu(torch, mcl, w, P)
-    o_mean, o_b, o_bp = E.pose_estimate(w, P)
-    assert g_b == o_b, (what, g_b, o_b)
-    assert np.array_equal(g_bp.view(np.uint32), o_bp.view(np.uint32)), what
-
-    ws, S, _ = E.weighted_sums(w, P)
-    Pd = P.astype(np.float64)
-    wu = np.asarray(w, np.float64) if np.sum(w) > 0 else np.ones(P.shape[1])
-    absS = (np.abs(Pd[0:9]) * wu).sum(axis=1)
-    absT = (np.abs(Pd[9:12]) * wu).sum(axis=1)
-    dS = 64 * U * absS                                   # per element
-    s = np.linalg.svd(S, compute_uv=False)
-    s3 = s[2] if np.linalg.det(S) >= 0 else -s[2]
-    gap = s[1] + s3
-    tol_R = (2 * np.linalg.norm(dS) + 32 * U * 3 * s[0]) / gap if gap > 0 else np.inf
-    tol_t = 2 * 64 * U * absT / ws + 4 * U * np.abs(o_mean[9:12])
-    np.testing.assert_array_less(np.abs(g_mean[9:12] - o_mean[9:12]), tol_t + 1e-300, err_msg=what)
-
-    Rg = g_mean[:9].reshape(3, 3)
-    np.testing.assert_allclose(Rg @ Rg.T, np.eye(3), atol=1e-13, err_msg=what)
-    assert np.linalg.det(Rg) > 0, what
-    if tol_R < 1e-6:
-        err = np.abs(g_mean[:9] - o_mean[:9]).max()
-        assert err <= tol_R, (what, err, tol_R)
-    else:
-        f_o = np.trace(o_mean[:9].reshape(3, 3).T @ S)
-        f_g = np.trace(Rg.T @ S)
-        tol_f = 2 * math.sqrt(3) * np.linalg.norm(dS) + 64 * U * 3 * s[0]
-        assert f_g >= f_o - tol_f, (what, f_g, f_o, tol_f)
+    o_mean = checks.check_estimate(g_mean, g_b, g_bp, w, P, what)
     return g_mean, o_mean
 
 

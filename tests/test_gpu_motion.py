@@ -86,6 +86,29 @@ def test_motion_update(torch, mcl, oracle_lib, N, st, sr):
     check_motion(got, ref, P, delta, st, sr, f"N={N}")
 
 
+@pytest.mark.parametrize("N", [1, 1000, 65537])
+@pytest.mark.parametrize("st,sr", [(0.0, 0.0), (0.5, 0.087)])
+def test_init_gaussian(torch, mcl, oracle_lib, N, st, sr):
+    """Initialisation round a pose estimate: bit for bit the motion update of N
+    copies of the estimate by the identity increment, and within the motion
+    bounds of the oracle's motion update of those copies."""
+    say(f"case: init round a pose N={N} sigma=({st}, {sr})")
+    rng = np.random.default_rng(N)
+    mean = poses_from(random_rotations(rng, 1), rng.normal(0, 20, (1, 3)))[:, 0]
+    seed, step = 0x5EED, 1
+    got = mcl.init_gaussian(mean, N, st, sr, seed, step).cpu().numpy()
+    copies = np.ascontiguousarray(np.repeat(mean[:, None], N, axis=1))
+    ident = np.r_[np.eye(3).ravel(), 0.0, 0.0, 0.0].astype(np.float32)
+    moved = mcl.motion_update(dev(torch, copies), ident, st, sr, seed, step).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), moved.view(np.uint32))
+    ref = oracle_lib.motion_update(copies, ident, st, sr, seed, step)
+    check_motion(got, ref, copies, ident, st, sr, f"init N={N}")
+    if st > 0 and N > 1000:
+        # the spread is the requested one (0.5 m per axis, in the estimate's frame)
+        d = (mean[:9].reshape(3, 3).astype(np.float64).T @ (got[9:] - mean[9:, None]).astype(np.float64))
+        assert np.all(np.abs(d.std(axis=1) / st - 1.0) < 0.02), d.std(axis=1)
+
+
 def test_motion_in_place_and_determinism(torch, mcl):
     say("case: motion in place")
     P, delta = motion_case(3, 5000)
@@ -168,7 +191,7 @@ def test_full_loop_runs(torch, mcl):
         lw = mcl.sensor_update(m, X, P, w.sigma)
         wt, wq, _ = mcl.normalize(lw)
         mean, bi, _ = mcl.pose_estimate(wt, P)
-        _, P2 = mcl.resample(wq, 12345 + step, P)
+        _, P2 = mcl.resample(wq, 12345, step, P)
         P = mcl.motion_update(P2, np.r_[np.eye(3).ravel(), 0.1, 0, 0], 0.02, 0.01, 7, step)
     torch.cuda.synchronize()
     assert np.all(np.isfinite(P.cpu().numpy())) and np.all(np.isfinite(mean.cpu().numpy()))

@@ -11,13 +11,14 @@ import sys
 import numpy as np
 import pytest
 
-from tests.helpers import identity_poses, make_map, poses_from, random_rotations
+from tests import checks
+from tests.helpers import identity_poses, make_map, poses_from, random_rotations, score_const, seed_for_draw
 from workloads import configs
 from workloads.tsdf import f32
 
 pytestmark = pytest.mark.gpu
 
-RTOL_LOGW = 1e-5
+RTOL_LOGW = checks.RTOL_LOGW
 
 
 def say(*a):
@@ -48,11 +49,7 @@ def gpu_logw(torch, mcl, tmap, pts, poses, sigma):
     return lw.cpu().numpy()
 
 
-def assert_logw_close(gpu, ref, what=""):
-    ref = np.asarray(ref, np.float64)
-    err = np.abs(gpu.astype(np.float64) - ref)
-    bad = err > RTOL_LOGW * np.abs(ref)
-    assert not bad.any(), f"{what}: {bad.sum()} particles off, worst rel {np.max(err / np.maximum(np.abs(ref), 1e-300))}"
+assert_logw_close = checks.assert_logw_close
 
 
 # ------------------------------------------------------------- sensor update
@@ -71,8 +68,7 @@ def test_identity_pose_bit_exact(torch, mcl, oracle_lib):
     lw = gpu_logw(torch, mcl, tmap, pts, identity_poses(3), sigma)
     S = sum(int(q) ** 2 for q in vals[kk, jj, ii])
     assert S < 2 ** 24
-    m = mcl.Map.from_tsdf(tmap)
-    c = np.float32(mcl.score_const(m, sigma))
+    c = np.float32(score_const(tmap.dtype, tmap.tau, sigma))
     expect = -(np.float32(S) * c)
     assert np.all(lw == expect)
 
@@ -220,7 +216,7 @@ def full_chain(torch, mcl, w):
     P = dev(torch, w.poses)
     lw = mcl.sensor_update(m, dev(torch, w.points), P, w.sigma)
     wt, wq, lz = mcl.normalize(lw)
-    idx, pout = mcl.resample(wq, w.u, P)
+    idx, pout = mcl.resample(wq, w.seed, 0, P)
     torch.cuda.synchronize()
     return (lw.cpu().numpy(), wt.cpu().numpy(), wq.cpu().numpy(), float(lz.cpu().numpy()[0]),
             idx.cpu().numpy(), pout.cpu().numpy())
@@ -240,41 +236,17 @@ def check_chain_properties(lw, wq, idx, pout, poses):
     assert np.array_equal(pout, poses[:, idx])
 
 
-U64 = 2.0 ** -53     # unit roundoff of float64
-
-
-def check_weight_stages(torch, mcl, oracle_lib, lw32, poses, u):
+def check_weight_stages(torch, mcl, oracle_lib, lw32, poses, seed, tick=0):
     """Normalisation and resampling, each fed the same oracle-made input as the
-    oracle: log-sum-exp and weights within the bound below, fixed-point weights
-    within one unit plus that bound, resampled indices and gathered poses
-    bit-exact.
-
-    Bound on log Z.  The oracle's S is within 2u of the exact sum of its terms
-    (compensated sum), each term within 1 ulp of its exponential.  The GPU adds
-    each thread's 16 terms in order, then a tree of depth 8 per block of 4096,
-    then scales each block sum by exp(m_b - m) (2 roundings) and adds the block
-    sums, at most 2 per thread for N <= 2^21, in another tree of depth 8: at most
-    36 roundings on the way of any term, each term within 2 ulps.  All terms are
-    positive, so the two S differ by at most (36 + 2 + 2 + 1) u relative, and log S
-    by as much in absolute terms; the log and m + log S round once on each side.
-    Weights: the exponent l_n - log Z differs by the log Z bound plus one
-    rounding of the subtraction on each side, and exp adds 2 ulps per side."""
+    oracle: log-sum-exp and weights within the bound of
+    checks.normalize_bounds, fixed-point weights within one unit plus that
+    bound, resampled indices and gathered poses bit-exact."""
     lw32 = np.ascontiguousarray(lw32, np.float32)
     wt, wq, lz = mcl.normalize(dev(torch, lw32))
-    w_ref, wq_ref, lz_ref = oracle_lib.normalize(lw32.astype(np.float64))
-    wt, wq, lz = wt.cpu().numpy(), wq.cpu().numpy(), float(lz.cpu().numpy()[0])
-    log_s = lz_ref - float(lw32.max())
-    tol_lz = 41 * U64 + np.spacing(abs(log_s)) + np.spacing(abs(lz_ref))
-    assert abs(lz - lz_ref) <= tol_lz, (lz, lz_ref, tol_lz)
-    lw64 = lw32.astype(np.float64)
-    rtol_w = tol_lz + np.spacing(np.max(np.abs(lw64 - lz_ref))) + 4 * U64
-    np.testing.assert_allclose(wt, w_ref, rtol=rtol_w, atol=1e-300)
-    diff = np.abs(wq.astype(np.int64) - wq_ref.astype(np.int64))
-    assert np.all(diff <= 1 + rtol_w * wq_ref.astype(np.float64))
-    idx, pout = mcl.resample(dev(torch, wq_ref), u, dev(torch, poses))
-    idx_ref = oracle_lib.resample(wq_ref, u)
-    assert np.array_equal(idx.cpu().numpy(), idx_ref)
-    assert np.array_equal(pout.cpu().numpy(), poses[:, idx_ref])
+    wq_ref = checks.check_normalize(oracle_lib, lw32, wq.cpu().numpy(), float(lz.cpu().numpy()[0]),
+                                    wt.cpu().numpy(), "normalise")
+    idx, pout = mcl.resample(dev(torch, wq_ref), seed, tick, dev(torch, poses))
+    checks.check_resample(oracle_lib, wq_ref, seed, tick, idx.cpu().numpy(), poses, pout.cpu().numpy(), "resample")
 
 
 def test_config1_chain(torch, mcl, oracle_lib, cfg1):
@@ -284,7 +256,7 @@ def test_config1_chain(torch, mcl, oracle_lib, cfg1):
     ref = oracle_lib.sensor_update(w.tmap, w.points, w.poses, w.sigma)
     assert_logw_close(lw, ref, "config1 chain")
     check_chain_properties(lw, wq, idx, pout, w.poses)
-    check_weight_stages(torch, mcl, oracle_lib, ref.astype(np.float32), w.poses, w.u)
+    check_weight_stages(torch, mcl, oracle_lib, ref.astype(np.float32), w.poses, w.seed)
 
 
 @pytest.fixture(scope="module")
@@ -306,7 +278,7 @@ def test_config2_full_size_sampled(torch, mcl, oracle_lib, cfg2):
     # full-size normalise + resample on oracle-made log-weights: the subset's
     # oracle values drawn with replacement (seeded) to all N particles
     boot = ref[np.random.default_rng(22).integers(0, ref.shape[0], w.N)].astype(np.float32)
-    check_weight_stages(torch, mcl, oracle_lib, boot, w.poses, w.u)
+    check_weight_stages(torch, mcl, oracle_lib, boot, w.poses, w.seed)
     # voxel indices of 32 sampled particles, bit for bit
     m = mcl.Map.from_tsdf(w.tmap)
     ps = np.ascontiguousarray(w.poses[:, sub[:32]])
@@ -387,20 +359,21 @@ def test_normalize_resample_edges(torch, mcl, oracle_lib):
     for N in (1, 2, 4095, 4096, 4097, 70001):
         lw = (-np.abs(rng.normal(0, 300, N)) - 1e4).astype(np.float32)
         poses = rng.normal(size=(12, N)).astype(np.float32)
-        check_weight_stages(torch, mcl, oracle_lib, lw, poses, 0xDEADBEEF12345678)
+        check_weight_stages(torch, mcl, oracle_lib, lw, poses, 0xDEADBEEF12345678, N)
     # all-zero fixed-point weights: equal weights, identity
     N = 5000
-    idx, _ = mcl.resample(dev(torch, np.zeros(N, np.uint64)), 12345)
+    idx, _ = mcl.resample(dev(torch, np.zeros(N, np.uint64)), 12345, 0)
     assert np.array_equal(idx.cpu().numpy(), np.arange(N))
     # one dominating particle
     lw = np.full(N, -1e5, np.float32)
     lw[4321] = -10.0
     wt, wq, lz = mcl.normalize(dev(torch, lw))
     assert wq.cpu().numpy()[4321] == 2 ** 42 and int(wq.cpu().numpy().sum()) == 2 ** 42
-    idx, _ = mcl.resample(wq, 2 ** 64 - 1)
+    top = seed_for_draw(oracle_lib, 2 ** 64 - 1, 3)   # the largest offset r = T - 1
+    idx, _ = mcl.resample(wq, top, 3)
     assert np.all(idx.cpu().numpy() == 4321)
     # largest N
     N = mcl.MAX_PARTICLES
     wq = dev(torch, np.full(N, 2 ** 21, np.uint64))
-    idx, _ = mcl.resample(wq, 2 ** 64 - 1)
+    idx, _ = mcl.resample(wq, top, 3)
     assert np.array_equal(idx.cpu().numpy(), np.arange(N))

@@ -1,11 +1,19 @@
-"""The serving engine: every robot's result is the same served in the mix as
-replayed alone with the single-filter calls (bit for bit), under a memory
-budget small enough to make robots wait for admission."""
+"""The serving engine.
+
+* Every robot's result is the same served in the mix as replayed alone with the
+  single-filter calls (bit for bit), under a memory budget small enough to make
+  robots wait for admission, with two streams, one stream two ticks deep, and
+  both request orders.
+* On the served workload's four maps at their particle-count ranges, every
+  completed update is checked against the CPU oracle as it completes.
+"""
 
 import sys
 
 import numpy as np
 import pytest
+
+from tests import checks
 
 pytestmark = pytest.mark.gpu
 
@@ -14,11 +22,28 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def setup(torch, mcl, sw, n_global_updates, seed=11):
+    from paper_2310_04172_amd.serve import LibraryInit, Robot
+    from workloads import served
+    maps = [mcl.Map.from_tsdf(t) for t in sw.tmaps]
+    host = [[torch.from_numpy(p).pin_memory() for p in lst] for lst in sw.scans]
+    counts = {sp.rid: {"global": sp.n_global, "track": sp.n_track} for sp in sw.robots}
+    means = {sp.rid: served.pose12(sp.gt) for sp in sw.robots}
+    init = LibraryInit(counts, means, served.MAX_TILT, served.TRACK_SIGMA_T, served.TRACK_SIGMA_R, seed=seed)
+    phases = [(n_global_updates, "global"), (None, "track")]
+
+    def robots():
+        return [Robot(sp.rid, maps[sp.map_idx], host[sp.map_idx][sp.scan_idx], served.sigma_for(sw.tmaps[sp.map_idx]),
+                      list(phases)) for sp in sw.robots]
+
+    return maps, init, robots, phases
+
+
 @pytest.mark.parametrize("n_streams,depth,order", [(2, 1, "fifo"), (1, 2, "fifo"), (2, 1, "stale")])
 def test_served_equals_alone(n_streams, depth, order):
     import torch
     from paper_2310_04172_amd import mcl
-    from paper_2310_04172_amd.serve import Engine, Robot, update_draw
+    from paper_2310_04172_amd.serve import Engine, Robot, robot_seed
     from workloads import served
 
     say(f"case: served engine, small trace, {n_streams} streams x {depth} ticks, order {order}")
@@ -26,24 +51,8 @@ def test_served_equals_alone(n_streams, depth, order):
     for sp in sw.robots:          # keep the test small: scale particle counts down
         sp.n_global = 1 + sp.n_global // 64
         sp.n_track = 1 + sp.n_track // 16
-    dev = torch.device("cuda:0")
-    maps = [mcl.Map.from_tsdf(t) for t in sw.tmaps]
-    vals = [torch.from_numpy(t.values).to(dev) for t in sw.tmaps]
-    scans = [[torch.from_numpy(p).to(dev) for p in lst] for lst in sw.scans]
-
-    def robots():
-        return [Robot(sp.rid, maps[sp.map_idx], scans[sp.map_idx][sp.scan_idx], served.sigma_for(sw.tmaps[sp.map_idx]),
-                      [(3, "global"), (None, "track")]) for sp in sw.robots]
-
-    def init(r, phase, probe=False):
-        sp = sw.robots[r.rid]
-        n = sp.n_global if phase == "global" else sp.n_track
-        if probe:
-            return n
-        return served.device_particles(torch, sw.tmaps[sp.map_idx], vals[sp.map_idx], n, phase, sp.gt,
-                                       seed=(r.rid << 1) | (phase == "track"), device=dev)
-
-    big = max(mcl.job_bytes(sp.n_global, scans[sp.map_idx][sp.scan_idx].shape[1]) for sp in sw.robots)
+    maps, init, robots, phases = setup(torch, mcl, sw, 3)
+    big = max(mcl.job_bytes(sp.n_global, sw.scans[sp.map_idx][sp.scan_idx].shape[1]) for sp in sw.robots)
     eng = Engine(robots(), init, budget_bytes=3 * big, max_evals_per_tick=2e9, seed=9, n_streams=n_streams,
                  depth=depth, order=order)
     st = eng.run(sw.trace)
@@ -51,22 +60,67 @@ def test_served_equals_alone(n_streams, depth, order):
     say(f"served: {summ}")
     assert st.completed > 0 and st.completed + st.dropped <= st.arrived
     assert st.max_resident_bytes <= 3 * big
+    assert st.uploaded_bytes > 0
     # replay each robot alone, update by update, with the single-filter calls
+    dev = torch.device("cuda:0")
+    s = torch.cuda.current_stream()
     for r in eng.robots:
         if r.poses is None:
             continue
-        alone = Robot(r.rid, r.map, r.points, r.sigma, [(3, "global"), (None, "track")])
+        alone = Robot(r.rid, r.map, r.host_points, r.sigma, list(phases))
+        pts = r.host_points.to(dev)
         poses = None
         for n in range(r.completed):
             if poses is None:
-                poses = init(alone, alone.phase)
-            lw = mcl.sensor_update(alone.map, alone.points, poses, alone.sigma)
+                poses = init(alone, alone.phase, s)
+            lw = mcl.sensor_update(alone.map, pts, poses, alone.sigma)
             _, wq, _ = mcl.normalize(lw, want_w=False)
-            _, poses = mcl.resample(wq, update_draw(9, r.rid, n), poses)
+            _, poses = mcl.resample(wq, robot_seed(9, r.rid), n, poses)
             if n + 1 == 3:
                 alone.phase_i = 1
                 poses = None
         if poses is None:
-            poses = init(alone, alone.phase)
+            poses = init(alone, alone.phase, s)
         torch.cuda.synchronize()
         assert torch.equal(poses, r.poses), f"robot {r.rid} after {r.completed} updates"
+
+
+def test_served_matches_oracle(oracle_lib):
+    """The served workload's four int16 maps (512x512x64, 1024x1024x128 and
+    2048x2048x128 at 0.05 m; 1024x1024x256 at 0.1 m), 32 robots with their full
+    particle counts (global sets of 262,144 to 1,048,576 particles for the first
+    update, tracking sets of 4,096 to 32,768 after), VLP-16 and OS0-64
+    scans uploaded per request, continuous batching on two streams: every
+    completed update against the oracle (32 seeded particles' log-weights within
+    1e-5, the whole normalisation and the whole resampling)."""
+    import torch
+    from paper_2310_04172_amd import mcl
+    from paper_2310_04172_amd.serve import Engine
+    from workloads import served
+
+    say("case: served workload vs oracle, 4 maps, 32 robots")
+    sw = served.build(n_robots=32, trace_s=2.0, rate_hz=10.0, scans_per_map=2, stagger_s=0.4)
+    maps, init, robots, _ = setup(torch, mcl, sw, 1)
+    rng = np.random.default_rng(77)
+    seen = {"global": 0, "track": 0, "maps": set(), "N": []}
+
+    def on_complete(r, f):
+        sp = sw.robots[r.rid]
+        tmap = sw.tmaps[sp.map_idx]
+        P = f.poses.cpu().numpy()
+        sub = np.sort(rng.choice(f.N, size=min(32, f.N), replace=False))
+        what = f"robot {r.rid} update {r.completed} ({r.phase}, N={f.N}, K={f.K}, map {sp.map_idx})"
+        checks.check_update(oracle_lib, tmap, sw.scans[sp.map_idx][sp.scan_idx], P, r.sigma, f.logw.cpu().numpy(),
+                            f.wq.cpu().numpy(), f.log_z.cpu().numpy()[0], f.idx.cpu().numpy(), f.seed, f.tick, sub,
+                            poses_out=f.poses_out.cpu().numpy(), what=what)
+        seen[r.phase] += 1
+        seen["maps"].add(sp.map_idx)
+        seen["N"].append(f.N)
+
+    eng = Engine(robots(), init, max_evals_per_tick=5e9, seed=5, n_streams=2, order="stale",
+                 on_complete=on_complete)
+    st = eng.run(sw.trace)
+    say(f"served: {st.summary()}; checked {seen['global']} global and {seen['track']} tracking updates "
+        f"on maps {sorted(seen['maps'])}, N {min(seen['N'])}..{max(seen['N'])}")
+    assert seen["global"] > 0 and seen["track"] > 0 and len(seen["maps"]) == 4
+    assert max(seen["N"]) > 262144 and min(seen["N"]) < 32768

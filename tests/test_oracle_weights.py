@@ -6,6 +6,7 @@ resampling (the multiplicity bound, and the expectation over every offset).
 """
 
 import math
+import os
 from decimal import Decimal, getcontext
 
 import numpy as np
@@ -151,3 +152,46 @@ def test_resample_special_cases(oracle_lib):
     W = np.full(N, 2 ** 21, np.uint64)
     idx = oracle_lib.resample(W, 2 ** 64 - 1)
     assert np.array_equal(idx, np.arange(N))
+
+
+# ------------------------------------------------------------- resampling draw
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "splitmix64_kat.txt")
+GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+
+
+def _splitmix_kat():
+    state, outs = None, []
+    for line in open(GOLDEN):
+        line = line.strip()
+        if line.startswith("# state"):
+            state = int(line.split()[2])
+        elif line and not line.startswith("#"):
+            outs.append(int(line))
+    return state, outs
+
+
+def test_splitmix64_known_answers(oracle_lib):
+    """The published first outputs of the reference SplitMix64 from state 1234567:
+    output k comes from state 1234567 + k * gamma (the generator advances first)."""
+    state, outs = _splitmix_kat()
+    assert len(outs) == 5
+    for k, want in enumerate(outs):
+        assert oracle_lib.splitmix64((state + k * GOLDEN_GAMMA) % 2 ** 64) == want, k
+
+
+def test_resample_draw_properties(oracle_lib):
+    """Per filter seed, distinct ticks give distinct draws (the map tick -> u is a
+    bijection of 64-bit words), the draw depends on the seed, and the top bits
+    of u over consecutive ticks are uniform (chi-square over 64 cells)."""
+    seed = 0x0123456789ABCDEF
+    us = [oracle_lib.resample_draw(seed, t) for t in range(20000)]
+    assert len(set(us)) == len(us)
+    assert oracle_lib.resample_draw(seed ^ 1, 5) != oracle_lib.resample_draw(seed, 5)
+    # u(seed, tick) = splitmix64(seed XOR splitmix64(tick)): with seed 0 and the
+    # known answers, u(0, t) for the tick whose splitmix64 is the state 1234567
+    state, outs = _splitmix_kat()
+    assert oracle_lib.resample_draw(state ^ oracle_lib.splitmix64(7), 7) == outs[0]
+    cells = np.bincount(np.asarray([u >> 58 for u in us]), minlength=64)
+    exp = len(us) / 64
+    chi2 = float(((cells - exp) ** 2 / exp).sum())
+    assert chi2 < 120.0, chi2   # 63 degrees of freedom: P(chi2 > 120) < 1e-5

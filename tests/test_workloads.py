@@ -15,7 +15,7 @@ def _small_scene():
 def test_config1_is_deterministic():
     a, b = configs.config1(64), configs.config1(64)
     assert np.array_equal(a.points, b.points) and np.array_equal(a.poses, b.poses)
-    assert np.array_equal(a.tmap.values, b.tmap.values) and a.u == b.u
+    assert np.array_equal(a.tmap.values, b.tmap.values) and a.seed == b.seed
     assert a.points.dtype == np.float32 and a.poses.shape == (12, 64)
     assert 1000 < a.K < 16 * 360
 

@@ -5,8 +5,9 @@ VLP-16 and the HILTI drone arena recorded with an OS0-64 (§VI).  Beam geometry
 follows those sensors; scenes are procedural (floor, boxes, walls, cylinders).
 
 Seeds: numpy ``default_rng((cfg, component, index))`` with components
-0 scene, 1 ground-truth pose, 2 range noise, 3 particles, 4 subset choice,
-5 the resampling draw.
+0 scene, 1 ground-truth pose, 2 range noise, 3 particles, 4 subset choice; the
+resampling seed of filter f of config c is c * 2^32 + f (its first update is
+tick 0).
 
 Poses are handed to the library as 12 float32 rows (structure of arrays):
 r00 r01 r02 r10 r11 r12 r20 r21 r22 tx ty tz, the rotation row-major and the
@@ -163,7 +164,7 @@ class Workload:
     points: np.ndarray            # [3, K] float32
     poses: np.ndarray             # [12, N] float32
     sigma: float                  # Eq. (3) sigma, float32 value
-    u: int                        # 64-bit uniform draw for the resampling offset
+    seed: int                     # resampling seed (the draw of update `tick` is fixed by both)
     gt: tuple = field(default=None)
     extra: dict = field(default_factory=dict)
 
@@ -176,8 +177,8 @@ class Workload:
         return self.points.shape[1]
 
 
-def draw_u(cfg: int, index: int = 0) -> int:
-    return int(rng(cfg, 5, index).integers(0, 2**64, dtype=np.uint64))
+def resample_seed(cfg: int, index: int = 0) -> int:
+    return (cfg << 32) + index
 
 
 def config1(n_particles=1000) -> Workload:
@@ -188,7 +189,7 @@ def config1(n_particles=1000) -> Workload:
     pts = raycast_scan(sc, tmap, R, t, beam_dirs(azimuths=360, **VLP16), 30.0, 0.02, rng(1, 2))
     xyz, rpy = gaussian_particles(rng(1, 3), gxyz, grpy, n_particles)
     return Workload("plain-small: 128x128x64@0.1m int16, VLP-16 16x360, N=1000", tmap, pts,
-                    poses_soa(xyz, rpy), f32(tmap.tau / 2), draw_u(1), (gxyz, grpy))
+                    poses_soa(xyz, rpy), f32(tmap.tau / 2), resample_seed(1), (gxyz, grpy))
 
 
 _WAREHOUSE_CACHE = {}
@@ -210,7 +211,7 @@ def config2(n_particles=1_000_000) -> Workload:
     pts = raycast_scan(sc, tmap, R, t, beam_dirs(azimuths=1800, **VLP16), 100.0, 0.03, rng(2, 2))
     xyz, rpy = free_voxel_particles(rng(2, 3), tmap, n_particles)
     return Workload("plain-global: 1024x1024x128@0.05m int16 warehouse, VLP-16 16x1800, N=1e6",
-                    tmap, pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), draw_u(2), (gxyz, grpy))
+                    tmap, pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), resample_seed(2), (gxyz, grpy))
 
 
 def config2_converged(n_particles=1_000_000) -> Workload:
@@ -223,7 +224,7 @@ def config2_converged(n_particles=1_000_000) -> Workload:
     xyz, rpy = gaussian_particles(rng(2, 9), gxyz, grpy, n_particles, s_xyz=0.05, s_rpy_deg=1.0)
     return Workload("plain-converged: 1024x1024x128@0.05m int16 warehouse, VLP-16 16x1800, N=1e6 "
                     "Gaussian round the true pose (0.05 m, 1 deg)",
-                    tmap, pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), draw_u(2), (gxyz, grpy))
+                    tmap, pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), resample_seed(2), (gxyz, grpy))
 
 
 def config3(n_particles=262_144, dtype="i16") -> Workload:
@@ -238,7 +239,7 @@ def config3(n_particles=262_144, dtype="i16") -> Workload:
     xl, rl = gaussian_particles(rng(3, 3, 1), gxyz, grpy, n_particles - half)
     poses = poses_soa(np.vstack([xg, xl]), np.vstack([rg, rl]))
     return Workload(f"precision: warehouse {dtype}, OS0-64 64x1024, N=262144", tmap, pts, poses,
-                    f32(tmap.tau / 2), draw_u(3), (gxyz, grpy))
+                    f32(tmap.tau / 2), resample_seed(3), (gxyz, grpy))
 
 
 def subset_indices(cfg: int, n_total: int, n_sub: int = 4096) -> np.ndarray:
@@ -251,7 +252,7 @@ class FilterSpec:
     points: np.ndarray            # [3, K] float32
     poses: np.ndarray             # [12, N] float32
     sigma: float
-    u: int
+    seed: int
     gt: tuple
 
     @property
@@ -284,5 +285,5 @@ def config4(n_filters: int = 64, n_scale: float = 1.0):
             xyz, rpy = gaussian_particles(rng(4, 5, f), gxyz, grpy, N)
         else:
             xyz, rpy = free_voxel_particles(rng(4, 5, f), tmap, N)
-        out.append(FilterSpec(pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), draw_u(4, f), (gxyz, grpy)))
+        out.append(FilterSpec(pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), resample_seed(4, f), (gxyz, grpy)))
     return tmap, out

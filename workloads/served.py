@@ -7,10 +7,10 @@ OS0-64-shaped scan (a few distinct scans per map, shared by its robots);
 requests form a Poisson process at 10 Hz per robot, first arrivals staggered
 over 10 s; a robot's first five accepted updates use a global particle set
 (N log-uniform in [262144, 1048576], uniform over free voxels), later ones a
-tracking set (N log-uniform in [4096, 32768], Gaussian around the true pose).
-
-Particle sets are sampled on the device with torch's seeded generator (input
-generation only: none of the sensor model's arithmetic).
+tracking set (N log-uniform in [4096, 32768], spread round the true pose at
+0.5 m and 5 degrees).  Only the counts and the true poses are generated here:
+the particle sets themselves are made on the device by the library's
+initialisation calls.
 """
 
 from __future__ import annotations
@@ -53,7 +53,9 @@ class ServedWorkload:
 
 
 def build(n_robots: int = 256, trace_s: float = 30.0, rate_hz: float = 10.0, scans_per_map: int = 4,
-          map_subset=None) -> ServedWorkload:
+          map_subset=None, stagger_s: float = 10.0) -> ServedWorkload:
+    """The served workload; robots' first requests arrive uniformly within
+    stagger_s seconds, then at `rate_hz` (Poisson) until trace_s."""
     tmaps, scans, scenes = [], [], []
     specs = MAP_SPECS if map_subset is None else [MAP_SPECS[i] for i in map_subset]
     for mi, (dims, v, tau) in enumerate(specs):
@@ -85,7 +87,7 @@ def build(n_robots: int = 256, trace_s: float = 30.0, rate_hz: float = 10.0, sca
     tr = rng(CFG, 4)
     trace = []
     for rid in range(n_robots):
-        t = tr.uniform(0.0, 10.0)
+        t = tr.uniform(0.0, stagger_s)
         while t < trace_s:
             trace.append((t, rid))
             t += tr.exponential(1.0 / rate_hz)
@@ -93,46 +95,15 @@ def build(n_robots: int = 256, trace_s: float = 30.0, rate_hz: float = 10.0, sca
     return ServedWorkload(tmaps, scans, robots, trace)
 
 
-def device_particles(torch, tmap, map_values_dev, n: int, kind: str, gt, seed: int, device):
-    """[12, n] float32 poses on the device: 'global' uniform over free voxels (stored
-    value > 0) with jitter, yaw uniform, roll/pitch within 5 degrees; 'track'
-    Gaussian around gt (0.5 m, 5 degrees)."""
-    g = torch.Generator(device=device)
-    g.manual_seed(seed)
-    f64 = torch.float64
-    if kind == "global":
-        flat = map_values_dev.reshape(-1)
-        nx, ny, _ = tmap.dims
-        chunks, need = [], n
-        while need > 0:
-            lin = torch.randint(0, flat.numel(), (int(need * 1.4) + 64,), generator=g, device=device)
-            lin = lin[flat[lin] > 0][:need]
-            chunks.append(lin)
-            need -= lin.numel()
-        lin = torch.cat(chunks)
-        k = lin // (nx * ny)
-        rem = lin - k * (nx * ny)
-        j = rem // nx
-        i = rem - j * nx
-        ijk = torch.stack([i, j, k], 1).to(f64)
-        xyz = torch.tensor(tmap.origin, dtype=f64, device=device) + \
-            (ijk + torch.rand((n, 3), generator=g, device=device, dtype=f64)) * float(tmap.voxel)
-        u = torch.rand((n, 3), generator=g, device=device, dtype=f64)
-        roll = (u[:, 0] * 10 - 5) * DEG
-        pitch = (u[:, 1] * 10 - 5) * DEG
-        yaw = (u[:, 2] * 2 - 1) * math.pi
-    else:
-        gxyz, grpy = gt
-        xyz = torch.tensor(gxyz, dtype=f64, device=device) + 0.5 * torch.randn((n, 3), generator=g, device=device, dtype=f64)
-        e = torch.tensor(grpy, dtype=f64, device=device) + 5 * DEG * torch.randn((n, 3), generator=g, device=device, dtype=f64)
-        roll, pitch, yaw = e[:, 0], e[:, 1], e[:, 2]
-    cr, sr, cp, sp, cy, sy = (torch.cos(roll), torch.sin(roll), torch.cos(pitch), torch.sin(pitch),
-                              torch.cos(yaw), torch.sin(yaw))
-    rows = [cy * cp, cy * sp * sr - sy * cr, cy * sp * cr + sy * sr,
-            sy * cp, sy * sp * sr + cy * cr, sy * sp * cr - cy * sr,
-            -sp, cp * sr, cp * cr,
-            xyz[:, 0], xyz[:, 1], xyz[:, 2]]
-    return torch.stack(rows, 0).to(torch.float32).contiguous()
+def pose12(gt) -> np.ndarray:
+    """A ground-truth pose (xyz, roll/pitch/yaw) as 12 float32 values: R row-major, t."""
+    R, t = pose_matrix(gt[0], gt[1])
+    return np.concatenate([np.asarray(R, np.float64).ravel(), np.asarray(t, np.float64)]).astype(np.float32)
+
+
+TRACK_SIGMA_T = 0.5            # metres
+TRACK_SIGMA_R = 5.0 * DEG      # radians
+MAX_TILT = 5.0 * DEG           # global phase: |roll|, |pitch| bound
 
 
 def sigma_for(tmap) -> float:

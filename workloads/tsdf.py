@@ -13,6 +13,7 @@ The library converts this dense x-fastest array to its own device layout.
 
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -89,10 +90,9 @@ def voxelise(scene: Scene, dims, voxel: float, origin, tau: float, dtype: str = 
             sl.append((max(0, i0), min(n, i1)))
         if all(b > a for a, b in sl):
             prims.append((kind, prm, sl))
-    buf = np.empty((min(slab, nz), ny, nx), dtype=np.float64)
-    for zs in range(0, nz, slab):
+    def do_slab(zs):
         ze = min(nz, zs + slab)
-        d = buf[: ze - zs]
+        d = np.empty((ze - zs, ny, nx), dtype=np.float64)
         d.fill(tau)
         for kind, prm, sl in prims:
             if kind == "floor":
@@ -123,6 +123,13 @@ def voxelise(scene: Scene, dims, voxel: float, origin, tau: float, dtype: str = 
         else:
             _quantise_inplace(d, tau, dtype)
             out[zs:ze] = d
+
+    # slabs are independent (disjoint z ranges of the outputs); numpy releases
+    # the interpreter lock in its array loops, so threads share the work
+    from concurrent.futures import ThreadPoolExecutor
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 4))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(do_slab, range(0, nz, slab)))
     return out, d64
 
 
