@@ -43,19 +43,35 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-point evals/s (G/s) + p99 update latency, batched/served vs plain"
-FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_threads() -> int:
+BOX_CPU_SHARE = 16   # host threads a one-GPU machine gives a job, whatever the host has
+
+
+def cpu_info() -> dict:
+    """Host CPU: model name, logical CPUs of the host, CPUs this process may use."""
+    model = "unknown"
     try:
-        n = len(os.sched_getaffinity(0))
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(16, n))
+        affinity = os.cpu_count() or 1
+    return {"model": model, "nproc_host": os.cpu_count(), "affinity": affinity}
+
+
+def cpu_threads() -> int:
+    """The oracle's threads: every CPU this process may use, up to the box's share."""
+    return max(1, min(BOX_CPU_SHARE, cpu_info()["affinity"]))
 
 
 def cpu_baseline(w, target_s: float = 20.0) -> dict:
@@ -79,7 +95,9 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
     dt = time.perf_counter() - t0
     evals = n * w.K
     return {"value": evals / dt / 1e9, "unit": "G particle-point evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} of {w.N} particles x {w.K} points (sensor update + normalise + resample), {dt:.1f} s"}
+            "sample": f"{n} of {w.N} particles x {w.K} points (sensor update + normalise + resample), {dt:.1f} s",
+            "cpu": cpu_info(), "threads_note": f"one thread per CPU of this process's affinity set, at most the "
+                                               f"{BOX_CPU_SHARE} a one-GPU box allots"}
 
 
 # the sources that make up the sensor kernel, its map layout and its launch
@@ -116,6 +134,12 @@ def profiled_traffic(key="global"):
         if line.startswith("traffic_bytes_per_launch:"):
             return float(line.split(":")[1])
     return None
+
+
+def profiled_lines(key="global"):
+    """128-byte line fetches beyond L2 per sensor launch (counter summary), or None."""
+    t = profiled_traffic(key)
+    return None if t is None else t / 128.0
 
 
 def profiled_limiter(key="global"):
@@ -256,15 +280,102 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
     if sparse_info:
         out["config"]["sparse_map"] = sparse_info
     if with_roofline and not trilinear and not sparse:
-        flops = 20.0 * evals   # 9 fused multiply-adds (transform) + 1 (score), 2 flops each, per evaluation
-        achieved = flops / (sensor_ms * 1e-3) / 1e12
-        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / FP32_PEAK_TFLOPS,
+        achieved = evals / (sensor_ms * 1e-3) / 1e9
+        two = workload_key != "converged"   # global localisation reads the masks as bytes, converged from LDS
+        gr = gather_roofline(torch, mcl, m, pts, poses, two_gathers=two, stream=stream)
+        peak = gr["texture_ceiling_G_evals_per_s"]
+        tsdf_bytes = 2.0 * evals
+        out["roofline"] = {"bound": "gather", "achieved": achieved, "peak": peak, "unit": "G evals/s",
+                           "frac": achieved / peak,
                            "traffic": profiled_traffic(workload_key) if workload_key in ("global", "converged") else None,
-                           "kernel": "sensor_kernel", "algorithmic_flops_per_launch": flops,
-                           "algorithmic_tsdf_bytes_per_launch": 2.0 * evals}
+                           "kernel": "sensor_kernel",
+                           "algorithmic_tsdf_bytes_per_launch": tsdf_bytes,
+                           "bytes_frac_of_hbm_peak": tsdf_bytes / (sensor_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "gather_ceilings": gr}
+        lines = profiled_lines(workload_key)
+        if lines:
+            # the fabric ceiling: the launch's line fetches beyond L2 (counters) at the
+            # measured random-line rate of the Infinity Cache and of HBM
+            lpe = lines / evals
+            for where in ("MALL", "HBM"):
+                rate = gr["random_line_gathers"][f"{where}_64_lines_per_gather"]["G_lines_per_s"]
+                out["roofline"][f"fabric_ceiling_{where}_G_evals_per_s"] = rate / lpe
+            out["roofline"]["l2_miss_lines_per_eval"] = lpe
         if workload_key in ("global", "converged"):
             out["roofline"]["limiter"] = profiled_limiter(workload_key)
+        log(f"gather roofline: kernel {achieved:.0f} G evals/s, texture ceiling {peak:.0f} G evals/s "
+            f"(frac {achieved / peak:.3f}); {json.dumps(gr)}")
+    return out
+
+
+def _median_ms(torch, fn, stream, n=3):
+    ts = []
+    for _ in range(n):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def gather_roofline(torch, mcl, m, pts, poses, two_gathers=True, sample=65536, stream=None):
+    """The ceilings of the sensor kernel's gathers, measured on this GPU.
+
+    Texture path: the kernel's own gathers for a seeded sample of particles
+    (their byte offsets exported by the kernel's device code) replayed through a
+    load-and-sum kernel, each (particle, chunk) set issued r times in a row; the
+    time of one extra pass, (t(4) - t(2)) / 2, is the gathers' cost with their
+    lines in cache.  Memory system: random 128-byte line gathers within regions
+    that stay in L2 (2 MiB), in the Infinity Cache (128 MiB) and in HBM (8 GiB),
+    and a coalesced HBM read."""
+    stream = stream or torch.cuda.current_stream()
+    dev = poses.device
+    N, K = poses.shape[1], pts.shape[1]
+    S = min(sample, N) // 64 * 64
+    sel = torch.from_numpy(np.sort(np.random.default_rng(2024).choice(N, size=S, replace=False))).to(dev)
+    Ps = poses[:, sel].contiguous()
+    offs = mcl.bench_gather_offsets(m, pts, Ps, masked=not two_gathers, stream=stream)
+    npiece = (K + 4095) // 4096
+    blocks = (S // 64 * npiece + 3) // 4          # one wave per work item, 4 waves per workgroup
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    t = {}
+    for r in (1, 2, 4):
+        mcl.bench_gather_replay(m, offs, r, two_gathers, blocks, sink, stream)   # warm
+        t[r] = _median_ms(torch, lambda: mcl.bench_gather_replay(m, offs, r, two_gathers, blocks, sink, stream), stream)
+    evals = S * K
+    t_pass = (t[4] - t[2]) / 2.0
+    out = {"method": "the sensor kernel's own gathers replayed (offsets exported by its device code); one extra "
+                     "pass over each (particle, chunk) set = gathers with their lines in cache",
+           "sample_particles": S, "K": K, "gathers_per_eval": 2 if two_gathers else 1,
+           "replay_ms": {str(r): v for r, v in t.items()}, "pass_ms": t_pass,
+           "texture_ceiling_G_evals_per_s": evals / (t_pass * 1e-3) / 1e9,
+           "replay_cold_G_evals_per_s": evals / (t[1] * 1e-3) / 1e9}
+    del offs
+    # memory-system ceilings
+    region = torch.empty(8 << 30, dtype=torch.uint8, device=dev)
+    region.fill_(1)
+    gblocks, sblocks = 2048, 4096
+    gsink = torch.empty(max(gblocks, sblocks) * 256, dtype=torch.float32, device=dev)
+    lines_out = {}
+    for name, log2_lines in (("L2", 14), ("MALL", 20), ("HBM", 26)):
+        for lines in (64, 16):
+            steps = 64
+            fn = lambda: mcl.bench_line_gather(region, log2_lines, lines, steps, 7, gblocks, gsink, stream)
+            fn()
+            ms = _median_ms(torch, fn, stream)
+            nl = gblocks * 4 * steps * 16 * lines
+            lines_out[f"{name}_{lines}_lines_per_gather"] = {
+                "G_lines_per_s": nl / (ms * 1e-3) / 1e9, "GB_per_s": nl * 128 / (ms * 1e-3) / 1e9,
+                "region_MiB": (128 << log2_lines) >> 20}
+    out["random_line_gathers"] = lines_out
+    fn = lambda: mcl.bench_stream_read(region, sblocks, gsink, stream)
+    fn()
+    ms = _median_ms(torch, fn, stream)
+    out["hbm_stream_read_GB_per_s"] = region.numel() / (ms * 1e-3) / 1e9
+    del region
+    torch.cuda.empty_cache()
     return out
 
 
@@ -558,7 +669,8 @@ def run_served(args):
                       sv["evals_per_s"] / 1e9, sv["mean_ms"],
                       {"workload": "served: 4 resident int16 maps (512x512x64, 1024x1024x128, 2048x2048x128 at "
                                    "0.05 m; 1024x1024x256 at 0.1 m), 256 robots, Poisson 10 Hz, first 5 updates "
-                                   "global (N 262k-1M) then tracking (N 4k-32k), 16x1800 / 64x1024 scans",
+                                   "global (N 262k-1M) then tracking (N 4k-32k), 16x1800 / 64x1024 scans uploaded per request from pinned "
+                                   "host memory on a copy stream",
                        "trace_s": args.trace_seconds, "robots": len(sw.robots), "budget_GiB": args.budget_gib,
                        "graph": args.graph, "tick_evals_cap": args.tick_evals,
                        "streams": args.streams, "depth": args.depth, "order": args.order})
@@ -588,6 +700,8 @@ def main():
     ap.add_argument("--order", choices=("fifo", "stale"), default="stale",
                     help="served: oldest scan first, or the robot with the oldest last update first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="default workload: skip the batched and served comparisons")
     ap.add_argument("--autotune", action="store_true", help="tune the sensor kernel's launch shape first")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the batched workload's particle counts")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -622,7 +736,36 @@ def main():
                                       "converged": " [particles converged]"}[args.workload]
         if not args.no_cpu_baseline and args.workload not in ("trilinear", "sparse", "converged"):
             out["cpu_baseline"] = cpu_baseline(w)
+        if args.workload == "global" and not args.no_headline:
+            out.update(headline_comparisons(args))
     print(json.dumps(out), flush=True)
+
+
+def headline_comparisons(args) -> dict:
+    """The metric's comparison, batched and served against plain: the 64-filter
+    batched workload (one graph-replayed tick against the same filters through
+    the single-filter calls one after another) and the served workload (256
+    robots, continuous batching against one request at a time)."""
+    import torch
+    res = {}
+    for key, fn in (("batched", run_batched), ("served", run_served)):
+        t0 = time.perf_counter()
+        try:
+            r = fn(args)
+        except Exception as e:   # the main line is printed whatever happens here
+            res[key] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"{key} comparison failed: {e}")
+            continue
+        finally:
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+        keep = {k: r[k] for k in ("value", "ms_per_step", "latency_ms", "vs_plain", "served") if k in r}
+        keep["unit"] = r["unit"]
+        keep["workload"] = r["config"]["workload"]
+        keep["config"] = {k: v for k, v in r["config"].items() if k != "workload"}
+        keep["wall_s"] = time.perf_counter() - t0
+        res[key] = keep
+    return res
 
 
 if __name__ == "__main__":

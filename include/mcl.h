@@ -359,6 +359,43 @@ mcl_status mcl_debug_voxel_indices(mcl_map map, const float *points, int32_t K,
  * default stream. */
 mcl_status mcl_debug_philox(const uint32_t *counter_key, uint32_t *out);
 
+/* ------------------------------------------------------- measurement support
+ * The sensor update is bound by its map gathers (the TSDF look-ups, §VI-C).
+ * These calls measure the ceilings it is judged against; they compute nothing
+ * of the method.  Every kernel writes one float per thread to `sink` (device,
+ * at least blocks * 256 floats) so that no load can be dropped. */
+
+/* The byte offset, within the map's value allocation, that the nearest lookup
+ * of mcl_sensor_update reads for every (particle, point) pair, computed by the
+ * same device code: the voxel's offset or 0 outside the map; with masked != 0
+ * the brick's read mask applied (the offset actually read: 0, the +Q sentinel,
+ * for bricks wholly at +-Q).  offs: device output [N][K] uint32.  Dense maps. */
+mcl_status mcl_bench_gather_offsets(mcl_map map, const float *points, int32_t K, const float *poses, int32_t N,
+                                    int32_t masked, uint32_t *offs, void *stream);
+
+/* Replay of the sensor kernel's gathers for S particles (a multiple of 64)
+ * whose offsets mcl_bench_gather_offsets wrote (offs [S][K]): work items of 64
+ * particles x 4096 points, lanes holding points l, l + 64, ... of each 1024-point
+ * chunk as in the sensor kernel; per particle and chunk each lane loads its 16
+ * offsets, then issues `reps` times its 16 gathers: with two_gathers the read
+ * mask byte and the value at (offset AND mask) (offs unmasked), else the value
+ * at the offset (offs masked).  `blocks` workgroups of 4 waves. */
+mcl_status mcl_bench_gather_replay(mcl_map map, const uint32_t *offs, int32_t S, int32_t K, int32_t reps,
+                                   int32_t two_gathers, int32_t blocks, float *sink, size_t sink_floats,
+                                   void *stream);
+
+/* Random 128-byte line gathers: each 64-lane gather reads 4 bytes from each of
+ * `lines` (1..64, a power of two) lines chosen at random among the first
+ * 2^log2_lines lines of `region` (device, region_bytes >= 128 * 2^log2_lines),
+ * 16 gathers in flight per wave, `steps` x 16 gathers per wave. */
+mcl_status mcl_bench_line_gather(const void *region, size_t region_bytes, int32_t log2_lines, int32_t lines,
+                                 int32_t steps, uint32_t seed, int32_t blocks, float *sink, size_t sink_floats,
+                                 void *stream);
+
+/* Coalesced 16-byte loads over `bytes` (a multiple of 16) of device memory. */
+mcl_status mcl_bench_stream_read(const void *src, size_t bytes, int32_t blocks, float *sink, size_t sink_floats,
+                                 void *stream);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char *mcl_last_error(void);
 

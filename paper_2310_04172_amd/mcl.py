@@ -74,11 +74,16 @@ _lib.mcl_map_bytes.argtypes = [_P]
 _lib.mcl_map_bytes.restype = C.c_size_t
 _lib.mcl_autotune.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P, C.POINTER(LaunchConfig)]
 _lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
+_lib.mcl_bench_gather_offsets.argtypes = [_P, _P, _I, _P, _I, _I, _P, _P]
+_lib.mcl_bench_gather_replay.argtypes = [_P, _P, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]
+_lib.mcl_bench_line_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, C.c_uint32, _I, _P, C.c_size_t, _P]
+_lib.mcl_bench_stream_read.argtypes = [_P, C.c_size_t, _I, _P, C.c_size_t, _P]
 _lib.mcl_last_error.restype = C.c_char_p
 for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear", "mcl_normalize",
            "mcl_resample",
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_pose_estimate", "mcl_motion_update",
-           "mcl_init_uniform", "mcl_init_gaussian", "mcl_debug_philox"):
+           "mcl_init_uniform", "mcl_init_gaussian", "mcl_debug_philox", "mcl_bench_gather_offsets",
+           "mcl_bench_gather_replay", "mcl_bench_line_gather", "mcl_bench_stream_read"):
     getattr(_lib, _f).restype = C.c_int32
 
 
@@ -406,3 +411,32 @@ def set_launch_config(dtype: str, K: int, N: int, cfg=None):
     coarse: 0 auto, 1 global bytes, 2 LDS bits."""
     c = None if cfg is None else C.byref(LaunchConfig(*cfg))
     _check(_lib.mcl_set_launch_config(DTYPE_CODE[dtype], K, N, c), "mcl_set_launch_config")
+
+
+# ------------------------------------------------------------ measurement support
+def bench_gather_offsets(m: Map, points, poses, masked: bool, out=None, stream=None):
+    """[N, K] uint32 byte offsets the nearest lookup reads (see include/mcl.h)."""
+    import torch
+    K, N = points.shape[1], poses.shape[1]
+    if out is None:
+        out = torch.empty((N, K), dtype=torch.uint32, device=poses.device)
+    _check(_lib.mcl_bench_gather_offsets(m.handle, _ptr(points), K, _ptr(poses), N, int(masked), _ptr(out),
+                                         _stream(stream)), "mcl_bench_gather_offsets")
+    return out
+
+
+def bench_gather_replay(m: Map, offs, reps: int, two_gathers: bool, blocks: int, sink, stream=None):
+    S, K = offs.shape
+    _check(_lib.mcl_bench_gather_replay(m.handle, _ptr(offs), S, K, int(reps), int(two_gathers), int(blocks),
+                                        _ptr(sink), sink.numel(), _stream(stream)), "mcl_bench_gather_replay")
+
+
+def bench_line_gather(region, log2_lines: int, lines: int, steps: int, seed: int, blocks: int, sink, stream=None):
+    _check(_lib.mcl_bench_line_gather(_ptr(region), region.numel() * region.element_size(), int(log2_lines),
+                                      int(lines), int(steps), int(seed) & 0xFFFFFFFF, int(blocks), _ptr(sink),
+                                      sink.numel(), _stream(stream)), "mcl_bench_line_gather")
+
+
+def bench_stream_read(src, blocks: int, sink, stream=None):
+    _check(_lib.mcl_bench_stream_read(_ptr(src), src.numel() * src.element_size(), int(blocks), _ptr(sink),
+                                      sink.numel(), _stream(stream)), "mcl_bench_stream_read")
