@@ -205,8 +205,10 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
     idx = torch.empty(N, dtype=torch.int32, device=dev)
     poses_out = torch.empty_like(poses)
     stream = torch.cuda.current_stream()
-    if args.autotune:
-        log(f"autotuned launch shape: {mcl.autotune(m, pts, poses, w.sigma)}")
+    if args.autotune and not trilinear and not sparse:
+        log(f"autotuned launch settings: {mcl.autotune(m, pts, poses, w.sigma)}")
+    launch = dict(zip(("waves_per_block", "blocks_per_cu", "coarse", "runs", "lds_threshold"),
+                      mcl.get_launch_config(w.tmap.dtype, K, N)))
     ev = []
 
     def step(timed: bool):
@@ -272,7 +274,8 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
                       {"workload": w.name, "N": N, "K": K, "map_dtype": w.tmap.dtype,
                        "step": ("sensor update (trilinear lookup)" if trilinear else "sensor update") +
                                " + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
-                       "workload_key": workload_key, "sensor_update_ms": sensor_ms})
+                       "workload_key": workload_key, "sensor_update_ms": sensor_ms,
+                       "launch": launch, "launch_autotuned": bool(args.autotune and not trilinear and not sparse)})
     out["latency_ms"] = {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}
     if tick_lat:
         out["tick_graph_latency_ms"] = tick_lat
@@ -362,7 +365,8 @@ def gather_roofline(torch, mcl, m, pts, poses, two_gathers=True, sample=65536, s
     for name, log2_lines in (("L2", 14), ("MALL", 20), ("HBM", 26)):
         for lines in (64, 16):
             steps = 64
-            fn = lambda: mcl.bench_line_gather(region, log2_lines, lines, steps, 7, gblocks, gsink, stream)
+            fn = lambda: mcl.bench_line_gather(region, log2_lines, lines, steps, 7, gblocks, gsink, stream,
+                                               bytes_per_lane=4)
             fn()
             ms = _median_ms(torch, fn, stream)
             nl = gblocks * 4 * steps * 16 * lines
@@ -370,6 +374,19 @@ def gather_roofline(torch, mcl, m, pts, poses, two_gathers=True, sample=65536, s
                 "G_lines_per_s": nl / (ms * 1e-3) / 1e9, "GB_per_s": nl * 128 / (ms * 1e-3) / 1e9,
                 "region_MiB": (128 << log2_lines) >> 20}
     out["random_line_gathers"] = lines_out
+    # texture-path cost of one 64-lane gather against the lines it touches, data
+    # in L1 (64 lines, 8 KiB): compute-unit cycles per gather instruction
+    cost = {}
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    for width in (2, 4):
+        for lines in (1, 2, 4, 8, 16, 32, 64):
+            steps = 64
+            fn = lambda: mcl.bench_line_gather(region, 6, lines, steps, 7, gblocks, gsink, stream, bytes_per_lane=width)
+            fn()
+            ms = _median_ms(torch, fn, stream)
+            ng = gblocks * 4 * steps * 16
+            cost[f"{width}B_{lines}_lines"] = ms * 1e-3 * 2.4e9 * cus / ng
+    out["l1_gather_cycles_per_instruction_per_cu"] = cost
     fn = lambda: mcl.bench_stream_read(region, sblocks, gsink, stream)
     fn()
     ms = _median_ms(torch, fn, stream)
@@ -529,9 +546,14 @@ def run_batched(args):
     filters = [mcl.Filter(m, torch.from_numpy(f.points).to(dev), torch.from_numpy(f.poses).to(dev), f.sigma, f.seed,
                           want_w=False) for f in specs]
     evals = sum(f.N * f.K for f in specs)
-    big = max(range(len(filters)), key=lambda i: specs[i].N * specs[i].K)
-    if args.autotune:
-        log(f"autotuned launch shape: {mcl.autotune(m, filters[big].points, filters[big].poses, specs[big].sigma)}")
+    launch = {}
+    for parity in (0, 1):    # the largest filter of each scan type sets that size class's launch
+        idx = [i for i in range(len(specs)) if i % 2 == parity]
+        b = max(idx, key=lambda i: specs[i].N * specs[i].K)
+        if args.autotune:
+            mcl.autotune(m, filters[b].points, filters[b].poses, specs[b].sigma)
+        launch[f"N={specs[b].N},K={specs[b].K}"] = mcl.get_launch_config("i16", specs[b].K, specs[b].N)
+    log(f"launch settings: {launch}")
     side = torch.cuda.Stream()
 
     def plain():
@@ -568,7 +590,8 @@ def run_batched(args):
                       evals / (ms_graph * 1e-3) / 1e9, ms_graph,
                       {"workload": "batched: 64 filters on the 1024x1024x128@0.05m int16 warehouse, N log-uniform "
                                    "[2048, 524288], scans alternating 16x1800 / 64x1024",
-                       "filters": len(specs), "sum_N": int(sum(f.N for f in specs)), "evals_per_tick": int(evals)})
+                       "filters": len(specs), "sum_N": int(sum(f.N for f in specs)), "evals_per_tick": int(evals),
+                       "launch": launch, "launch_autotuned": bool(args.autotune)})
     out["latency_ms"] = {"p50": percentile(lat_graph, 50), "p99": percentile(lat_graph, 99)}
     out["vs_plain"] = {"plain_sequential": {"value": evals / (ms_plain * 1e-3) / 1e9, "ms": ms_plain,
                                             "p50_ms": percentile(lat_plain, 50), "p99_ms": percentile(lat_plain, 99)},
@@ -702,7 +725,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-headline", action="store_true",
                     help="default workload: skip the batched and served comparisons")
-    ap.add_argument("--autotune", action="store_true", help="tune the sensor kernel's launch shape first")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip tuning the sensor kernel's launch settings before timing")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the batched workload's particle counts")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")

@@ -321,30 +321,52 @@ mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32_t flags, v
 size_t mcl_job_bytes(int32_t N, int32_t K);
 
 /* --------------------------------------------------------------- tuning
- * Launch shape of the sensor kernel: waves per workgroup (2, 4, 8) and, for a
- * persistent grid, workgroups per compute unit (0 = one wave per work item);
- * where the nearest lookup reads the map's coarse level: 0 = chosen per wave
- * and chunk (default), 1 = bytes in global memory, 2 = bits copied into LDS
- * (only for maps whose bit table fits 64 KiB, and in mcl_tick only for a
- * storage type whose filters all share one map; otherwise 1).  Sparse maps
- * use a fixed shape.  No setting changes results (the summation order depends
- * only on K). */
+ * Launch settings of the sensor kernel; none changes a result (the summation
+ * order depends only on K):
+ *   waves_per_block: 2, 4 or 8;
+ *   blocks_per_cu:   0 = one wave per work item, else a persistent grid of that
+ *                    many workgroups per compute unit;
+ *   coarse:          where the nearest lookup reads the coarse level: 0 = chosen
+ *                    per wave and chunk (default), 1 = bytes in global memory,
+ *                    2 = bits copied into LDS (only for maps whose bit table fits
+ *                    64 KiB, and in mcl_tick only for a storage type whose filters
+ *                    all share one map; otherwise 1);
+ *   runs:            runs per 64-particle group (work items per group and
+ *                    4096-point piece): 0 = from the launch's size (more runs for
+ *                    small launches, so they spread over the chip), else 1, 2, 4,
+ *                    .., 64;
+ *   lds_threshold:   with coarse = 0, a wave reads the bits in LDS when more than
+ *                    lds_threshold / 8 of its probe lookups read in place (1..8;
+ *                    0 = the default 6).
+ * Sparse maps use a fixed shape.  mcl_tick uses, per storage type, the setting
+ * stored for the largest filter of that type. */
 typedef struct {
     int32_t waves_per_block;
     int32_t blocks_per_cu;
     int32_t coarse;
+    int32_t runs;
+    int32_t lds_threshold;
 } mcl_launch_config;
 
-/* Time every launch shape on the given filter (synchronises `stream`), keep
- * the fastest for its storage type and size class (K and N rounded to powers
- * of two) for later mcl_sensor_update / mcl_tick calls, and return it in *best
- * (may be NULL).  logw_scratch: device [N] float32 the trials write. */
+/* Time launch settings on the given filter by coordinate descent (the launch
+ * shape, then runs, then the coarse level; each the median of three timed
+ * launches; synchronises `stream`), keep the fastest for its storage type and
+ * size class (K and N rounded up to powers of two) for later mcl_sensor_update
+ * / mcl_tick calls, and return it in *best (may be NULL).  With the environment
+ * variable MCL_TUNE_CACHE naming a file, results are appended to it and read
+ * back by later processes on the same kind of GPU.  logw_scratch: device [N]
+ * float32 the trials write. */
 mcl_status mcl_autotune(mcl_map map, const float *points, int32_t K, const float *poses, int32_t N, float sigma,
                         float *logw_scratch, void *stream, mcl_launch_config *best);
 
-/* Set (or with NULL clear) the shape used for a storage type and size class,
- * as mcl_autotune would. */
+/* Set (or with NULL clear) the setting used for a storage type and size class,
+ * as mcl_autotune would (in this process only). */
 mcl_status mcl_set_launch_config(int32_t dtype, int32_t K, int32_t N, const mcl_launch_config *cfg);
+
+/* The setting mcl_sensor_update would use for a storage type and sizes: the
+ * stored one for their size class (set, tuned, or read from MCL_TUNE_CACHE),
+ * else the default {4, 0, 0, 0, 0}. */
+mcl_status mcl_get_launch_config(int32_t dtype, int32_t K, int32_t N, mcl_launch_config *out);
 
 /* Test support: the voxel each (particle, point) pair reads, by the same
  * device code as mcl_sensor_update.  lin_idx: device output [N][K] int64,
@@ -384,13 +406,14 @@ mcl_status mcl_bench_gather_replay(mcl_map map, const uint32_t *offs, int32_t S,
                                    int32_t two_gathers, int32_t blocks, float *sink, size_t sink_floats,
                                    void *stream);
 
-/* Random 128-byte line gathers: each 64-lane gather reads 4 bytes from each of
- * `lines` (1..64, a power of two) lines chosen at random among the first
- * 2^log2_lines lines of `region` (device, region_bytes >= 128 * 2^log2_lines),
+/* Random 128-byte line gathers: each 64-lane gather reads bytes_per_lane (1, 2
+ * or 4) bytes per lane from `lines` (1..64, a power of two) lines chosen at
+ * random among the first 2^log2_lines lines of `region` (device, region_bytes
+ * >= 128 * 2^log2_lines), the lanes sharing a line at consecutive addresses;
  * 16 gathers in flight per wave, `steps` x 16 gathers per wave. */
 mcl_status mcl_bench_line_gather(const void *region, size_t region_bytes, int32_t log2_lines, int32_t lines,
-                                 int32_t steps, uint32_t seed, int32_t blocks, float *sink, size_t sink_floats,
-                                 void *stream);
+                                 int32_t bytes_per_lane, int32_t steps, uint32_t seed, int32_t blocks, float *sink,
+                                 size_t sink_floats, void *stream);
 
 /* Coalesced 16-byte loads over `bytes` (a multiple of 16) of device memory. */
 mcl_status mcl_bench_stream_read(const void *src, size_t bytes, int32_t blocks, float *sink, size_t sink_floats,

@@ -8,7 +8,8 @@
 
 namespace mcl {
 
-mcl_status launch_sensor(const mcl_map_s *, const float *, int, const float *, int, float, float *, hipStream_t);
+mcl_status launch_sensor(const mcl_map_s *, const float *, int, const float *, int, float, float *, hipStream_t,
+                         float *);
 mcl_status launch_sensor_trilinear(mcl_map_s *, const float *, int, const float *, int, float, float *,
                                    hipStream_t);
 mcl_status launch_debug_indices(const mcl_map_s *, const float *, int, const float *, int, int64_t *, hipStream_t);
@@ -75,7 +76,7 @@ using namespace mcl;
 
 extern "C" const char *mcl_last_error(void) { return g_last_error.c_str(); }
 
-static mcl_status sensor_args(const char *what, mcl_map map, const float *points, int32_t K, const float *poses,
+mcl_status sensor_args(const char *what, mcl_map map, const float *points, int32_t K, const float *poses,
                               int32_t N, float sigma, float *logw, float *c) {
     const std::string w(what);
     if (!map) return fail(MCL_EINVAL, w + ": NULL map");
@@ -96,7 +97,7 @@ extern "C" mcl_status mcl_sensor_update(mcl_map map, const float *points, int32_
     float c = 0.0f;
     mcl_status st = sensor_args("sensor_update", map, points, K, poses, N, sigma, logw, &c);
     if (st != MCL_OK) return st;
-    st = launch_sensor(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream));
+    st = launch_sensor(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream), nullptr);
     return st == MCL_OK ? note_map_use(map, static_cast<hipStream_t>(stream)) : st;
 }
 

@@ -45,13 +45,16 @@ struct SensorJob {
     int32_t K, N, npiece, ngroups;
     int32_t coarse;       // where the nearest lookup reads the coarse level (kCoarse*)
     int32_t nsub;         // runs per group (work items per (group, piece) pair)
+    int32_t lds8;         // auto coarse level: LDS when over lds8 / 8 of the probe lookups read in place
+    int32_t pad_;
 };
 
 // Coarse level of the nearest lookup: chosen per wave and chunk (auto), or
 // forced to the mask bytes in global memory or the bits in LDS.  Results are
 // the same bits in every mode.
 constexpr int32_t kCoarseAuto = 0, kCoarseBytes = 1, kCoarseBits = 2;
-constexpr int kProbe = 2;  // probe particles per chunk; LDS when over 3/4 of their lookups read in place
+constexpr int kProbe = 2;      // probe particles per chunk
+constexpr int kLdsEighths = 6;  // default: LDS when over 6/8 of the probe lookups read in place
 
 // The resampling draw of a filter's update: u = splitmix64(seed ^ splitmix64(tick)),
 // splitmix64(x) the output of SplitMix64 (Steele, Lea and Flood, 2014) from
@@ -196,7 +199,10 @@ struct LaunchCfg {
     int waves_per_block;  // 2, 4 or 8
     int blocks_per_cu;    // 0: one wave per work item; else a persistent grid
     int coarse;           // kCoarseAuto, kCoarseBytes or kCoarseBits
+    int runs;             // runs per 64-particle group: 0 = from the launch's size, else 1, 2, 4, .., 64
+    int lds8;             // auto coarse level threshold in eighths (1..8); 0 = kLdsEighths
 };
+constexpr LaunchCfg kDefaultCfg{4, 0, kCoarseAuto, 0, 0};
 
 LaunchCfg tuned_config(int32_t dtype, int K, int N);
 int device_cus();

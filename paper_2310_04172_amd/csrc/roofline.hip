@@ -114,15 +114,23 @@ __global__ __launch_bounds__(256) void gather_replay_kernel(MapView m, const uin
 }
 
 // Random 128-byte lines of a region of 2^log2_lines lines: lane l of a wave
-// reads 4 bytes of line x_(l / (64 / lines)), dword l mod (64 / lines) of it,
-// x a per-lane-group 32-bit LCG, 16 loads in flight per step.
-__global__ __launch_bounds__(256) void line_gather_kernel(const uint32_t *__restrict__ base, int log2_lines, int lines,
+// reads W bytes of line x_(l / (64 / lines)), at byte W (l mod (64 / lines))
+// of it (modulo 128), x a per-lane-group 32-bit LCG, 16 loads in flight per step.
+template <int W>
+__device__ inline uint32_t load_w(const char *p) {
+    if constexpr (W == 1) return (uint32_t)(int)*gp(reinterpret_cast<const int8_t *>(p));
+    else if constexpr (W == 2) return (uint32_t)(int)*gp(reinterpret_cast<const int16_t *>(p));
+    else return *gp(reinterpret_cast<const uint32_t *>(p));
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void line_gather_kernel(const char *__restrict__ base, int log2_lines, int lines,
                                                           int steps, uint32_t seed, float *__restrict__ sink) {
     const int lane = threadIdx.x & (kWave - 1);
     const int per = kWave / lines;                    // lanes per line
     const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     uint32_t x = (seed ^ (wave * 0x9E3779B9u)) + (uint32_t)(lane / per) * 0x85EBCA6Bu;
-    const uint32_t word = (uint32_t)(lane % per) & 31u;   // a 128-byte line holds 32 dwords
+    const uint32_t byte = ((uint32_t)(lane % per) * W) & 127u;   // within the 128-byte line
     const int sh = 32 - log2_lines;
     uint32_t acc = 0;
     for (int s = 0; s < steps; ++s) {
@@ -131,7 +139,7 @@ __global__ __launch_bounds__(256) void line_gather_kernel(const uint32_t *__rest
         for (int u = 0; u < 16; ++u) {
             x = x * 1664525u + 1013904223u;
             const uint32_t line = sh >= 32 ? 0u : (x >> sh);
-            v[u] = gp(base)[(size_t)line * 32 + word];
+            v[u] = load_w<W>(base + (size_t)line * 128 + byte);
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) acc += v[u];
@@ -198,17 +206,22 @@ extern "C" mcl_status mcl_bench_gather_replay(mcl_map map, const uint32_t *offs,
 }
 
 extern "C" mcl_status mcl_bench_line_gather(const void *region, size_t region_bytes, int32_t log2_lines, int32_t lines,
-                                            int32_t steps, uint32_t seed, int32_t blocks, float *sink,
-                                            size_t sink_floats, void *stream) {
+                                            int32_t bytes_per_lane, int32_t steps, uint32_t seed, int32_t blocks,
+                                            float *sink, size_t sink_floats, void *stream) {
     if (!region || !sink) return fail(MCL_EINVAL, "bench_line_gather: NULL argument");
     if (sink_floats < (size_t)blocks * 256) return fail(MCL_EINVAL, "bench_line_gather: sink shorter than blocks * 256");
-    if (log2_lines >= 0 && log2_lines <= 31 && ((size_t)128 << log2_lines) > region_bytes)
-        return fail(MCL_EINVAL, "bench_line_gather: 2^log2_lines lines of 128 bytes exceed the region");
     if (log2_lines < 0 || log2_lines > 31 || !(lines == 1 || lines == 2 || lines == 4 || lines == 8 || lines == 16 ||
-                                                lines == 32 || lines == 64) || steps < 1 || blocks < 1)
-        return fail(MCL_EINVAL, "bench_line_gather: need 0 <= log2_lines <= 31, lines a power of two <= 64");
-    line_gather_kernel<<<(unsigned)blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(
-        static_cast<const uint32_t *>(region), log2_lines, lines, steps, seed, sink);
+                                                lines == 32 || lines == 64) || steps < 1 || blocks < 1 ||
+        !(bytes_per_lane == 1 || bytes_per_lane == 2 || bytes_per_lane == 4))
+        return fail(MCL_EINVAL, "bench_line_gather: need 0 <= log2_lines <= 31, lines a power of two <= 64, "
+                                "1, 2 or 4 bytes per lane");
+    if (((size_t)128 << log2_lines) > region_bytes)
+        return fail(MCL_EINVAL, "bench_line_gather: 2^log2_lines lines of 128 bytes exceed the region");
+    const char *b = static_cast<const char *>(region);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (bytes_per_lane == 1) line_gather_kernel<1><<<(unsigned)blocks, 256, 0, s>>>(b, log2_lines, lines, steps, seed, sink);
+    else if (bytes_per_lane == 2) line_gather_kernel<2><<<(unsigned)blocks, 256, 0, s>>>(b, log2_lines, lines, steps, seed, sink);
+    else line_gather_kernel<4><<<(unsigned)blocks, 256, 0, s>>>(b, log2_lines, lines, steps, seed, sink);
     return check_launch("line_gather_kernel");
 }
 

@@ -389,7 +389,7 @@ __device__ __attribute__((always_inline)) inline void chunk_group(const SensorJo
             int nmixed = 0;
             q0 = min(p0 + kProbe, p1);
             chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, p0, q0, acc, sbits, true, &nmixed);
-            lds = 4 * nmixed > 3 * kChunk * (q0 - p0);
+            lds = nmixed * 8 > J.lds8 * kChunk * (q0 - p0);
         }
         if (lds)
             chunk_range<T, TAIL, kLookNearestLds>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
@@ -661,23 +661,35 @@ SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const f
     J.npiece = sensor_pieces(K);
     J.ngroups = (N + kGroup - 1) / kGroup;
     J.nsub = sensor_runs((int64_t)J.ngroups * J.npiece);
+    J.lds8 = kLdsEighths;
     return J;
 }
 
+// The launch shape's settings of a job: runs per group and the coarse-level
+// threshold (neither changes a result).
+void apply_cfg(SensorJob &J, const LaunchCfg &cfg) {
+    if (cfg.runs > 0) J.nsub = cfg.runs;
+    J.lds8 = cfg.lds8 > 0 ? cfg.lds8 : kLdsEighths;
+}
+
+// part: the piece partials [npiece][N] (npiece > 1), or null for the stream's
+// workspace.
 mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
-                             float *logw, LaunchCfg cfg, hipStream_t stream) {
+                             float *logw, LaunchCfg cfg, hipStream_t stream, float *part) {
     if (K == 0) {
         fill_kernel<<<(N + 255) / 256, 256, 0, stream>>>(logw, N, -(0.0f * c));
         return check_launch("fill_kernel");
     }
     const int npiece = sensor_pieces(K);
-    float *part = nullptr;
-    if (npiece > 1) {
+    if (npiece == 1) {
+        part = nullptr;
+    } else if (!part) {
         part = static_cast<float *>(workspace(stream, (size_t)npiece * N * sizeof(float)));
         if (!part) return fail(MCL_ENOMEM, "sensor_update: workspace allocation failed");
     }
     using Src = OneJob<SensorJob>;
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
+    if (!map->sparse) apply_cfg(src.job, cfg);
     const int64_t nitems = (int64_t)src.job.ngroups * npiece * src.job.nsub;
     src.n = Counts{1, nitems, N, 0};
     const size_t lds_bytes = (((size_t)map->view.nrwords + 3) & ~(size_t)3) * 4;  // 16-byte pieces
@@ -737,8 +749,8 @@ mcl_status launch_sensor_trilinear(mcl_map_s *map, const float *pts, int K, cons
 }
 
 mcl_status launch_sensor(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
-                         float *logw, hipStream_t stream) {
-    return launch_sensor_cfg(map, pts, K, poses, N, c, logw, tuned_config(map->dtype, K, N), stream);
+                         float *logw, hipStream_t stream, float *part) {
+    return launch_sensor_cfg(map, pts, K, poses, N, c, logw, tuned_config(map->dtype, K, N), stream, part);
 }
 
 mcl_status launch_debug_indices(const mcl_map_s *map, const float *pts, int K, const float *poses, int N,

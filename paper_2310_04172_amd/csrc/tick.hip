@@ -17,6 +17,7 @@
 namespace mcl {
 
 SensorJob make_sensor_job(const mcl_map_s *, const float *, int, const float *, int, float, float *, float *);
+void apply_cfg(SensorJob &, const LaunchCfg &);
 template <typename Src>
 mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t, size_t);
 template <typename Src>
@@ -65,7 +66,7 @@ namespace {
 // A captured chain serves every tick whose totals fit its power-of-two buckets.
 struct GraphKey {
     int mask;
-    int wpb, bpc;
+    std::array<int, kGroups> wpb, bpc;  // launch shape per sensor group
     std::array<int64_t, kGroups> items;
     int64_t elems, blocks, eblocks, ejobs;
     std::array<int64_t, kGroups> lds;  // LDS bytes for the read bits of a group's shared map, or 0
@@ -216,12 +217,22 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         if (hipMalloc((void **)&S.dev, want) != hipSuccess) return fail(MCL_ENOMEM, "tick: workspace allocation failed");
         S.dev_bytes = want;
     }
-    // launch shape and coarse-level mode: those tuned for the largest filter
-    int big = 0;
-    for (int j = 1; j < n_jobs; ++j)
-        if ((int64_t)jobs[j].N * jobs[j].K > (int64_t)jobs[big].N * jobs[big].K) big = j;
-    const LaunchCfg cfg = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
-    // runs per group, one value for the whole tick, from its total (group, piece) pairs
+    // launch shape, runs and coarse-level mode per sensor group: those tuned
+    // for the group's largest filter (dense nearest lookups; the sparse and
+    // trilinear launches have a fixed shape)
+    LaunchCfg cfgs[kGroups];
+    for (int g = 0; g < kGroups; ++g) {
+        cfgs[g] = kDefaultCfg;
+        if (g / kTypes != kKindDense || g_begin[g + 1] == g_begin[g]) continue;
+        int big = order[g_begin[g]];
+        for (int t = g_begin[g] + 1; t < g_begin[g + 1]; ++t) {
+            const int j = order[t];
+            if ((int64_t)jobs[j].N * jobs[j].K > (int64_t)jobs[big].N * jobs[big].K) big = j;
+        }
+        cfgs[g] = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
+    }
+    // runs per group where not tuned: one value for the whole tick, from its
+    // total (group, piece) pairs
     int64_t pairs = 0;
     for (int j = 0; j < n_jobs; ++j)
         pairs += (int64_t)((jobs[j].N + kGroup - 1) / kGroup) * sensor_pieces(jobs[j].K);
@@ -259,10 +270,11 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             SensorJob &J = stbl[s];
             J = make_sensor_job(m, F.points, F.K, F.poses, F.N, c, F.logw, part);
             if (job_kind(F) == kKindTri) J.tri = m->tri;
-            J.coarse = cfg.coarse;
+            J.coarse = cfgs[g].coarse;
             J.item0 = items;
             J.elem0 = elems;
             J.nsub = nsub;
+            apply_cfg(J, cfgs[g]);
             items += (int64_t)J.ngroups * J.npiece * J.nsub;
             elems += F.N;
             W.logw = F.logw;
@@ -317,12 +329,16 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     // replay serves any tick that fits; surplus waves exit at once).
     const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
     const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
-    GraphKey key{mask, cfg.waves_per_block, cfg.blocks_per_cu, {}, 0, 0, 0, 0, {}};
+    GraphKey key{mask, {}, {}, {}, 0, 0, 0, 0, {}};
+    for (int g = 0; g < kGroups; ++g) {
+        key.wpb[g] = cfgs[g].waves_per_block;
+        key.bpc[g] = cfgs[g].blocks_per_cu;
+    }
     // A dense group whose jobs all read one map with a small enough bit table
     // gets the kernel that holds those bits in LDS (a power of two bytes, so a
     // graph serves any such map up to that size).
-    for (int g = 0; g < kTypes && cfg.coarse != kCoarseBytes; ++g) {
-        if (g_begin[g + 1] == g_begin[g]) continue;
+    for (int g = 0; g < kTypes; ++g) {
+        if (g_begin[g + 1] == g_begin[g] || cfgs[g].coarse == kCoarseBytes) continue;
         const mcl_map_s *m0 = jobs[order[g_begin[g]]].map;
         bool shared = true;
         for (int s = g_begin[g] + 1; s < g_begin[g + 1] && shared; ++s) shared = jobs[order[s]].map == m0;
@@ -343,7 +359,8 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             const int type = g % kTypes, kind = g / kTypes;
             const bool comb = use_graph || combine[g];
             mcl_status st =
-                kind == kKindDense  ? launch_sensor_src(type, src, key.items[g], key.elems, comb, cfg, stream, (size_t)key.lds[g])
+                kind == kKindDense  ? launch_sensor_src(type, src, key.items[g], key.elems, comb, cfgs[g], stream,
+                                                        (size_t)key.lds[g])
                 : kind == kKindSparse ? launch_sensor_sparse_src(type, src, key.items[g], key.elems, comb, stream)
                                       : launch_sensor_tri_src(type, src, key.items[g], key.elems, comb, stream);
             if (st != MCL_OK) return st;

@@ -51,7 +51,8 @@ class FilterJob(C.Structure):
 
 
 class LaunchConfig(C.Structure):
-    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("coarse", C.c_int32)]
+    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("coarse", C.c_int32),
+                ("runs", C.c_int32), ("lds_threshold", C.c_int32)]
 
 
 _lib.mcl_map_upload.argtypes = [C.POINTER(MapDesc), _P, _P, C.POINTER(_P)]
@@ -74,14 +75,17 @@ _lib.mcl_map_bytes.argtypes = [_P]
 _lib.mcl_map_bytes.restype = C.c_size_t
 _lib.mcl_autotune.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P, C.POINTER(LaunchConfig)]
 _lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
+_lib.mcl_get_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_bench_gather_offsets.argtypes = [_P, _P, _I, _P, _I, _I, _P, _P]
 _lib.mcl_bench_gather_replay.argtypes = [_P, _P, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]
-_lib.mcl_bench_line_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, C.c_uint32, _I, _P, C.c_size_t, _P]
+_lib.mcl_bench_line_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, _I, C.c_uint32, _I, _P, C.c_size_t, _P]
 _lib.mcl_bench_stream_read.argtypes = [_P, C.c_size_t, _I, _P, C.c_size_t, _P]
 _lib.mcl_last_error.restype = C.c_char_p
-for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear", "mcl_normalize",
+for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear",
+           "mcl_normalize",
            "mcl_resample",
-           "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_pose_estimate", "mcl_motion_update",
+           "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_get_launch_config",
+           "mcl_pose_estimate", "mcl_motion_update",
            "mcl_init_uniform", "mcl_init_gaussian", "mcl_debug_philox", "mcl_bench_gather_offsets",
            "mcl_bench_gather_replay", "mcl_bench_line_gather", "mcl_bench_stream_read"):
     getattr(_lib, _f).restype = C.c_int32
@@ -397,18 +401,27 @@ def job_bytes(N: int, K: int) -> int:
 
 
 def autotune(m: Map, points, poses, sigma: float, stream=None):
+    """Tune the sensor kernel's launch settings on this filter; returns
+    (waves_per_block, blocks_per_cu, coarse, runs, lds_threshold)."""
     import torch
     N, K = poses.shape[1], points.shape[1]
     scratch = torch.empty(N, dtype=torch.float32, device=poses.device)
     best = LaunchConfig()
     _check(_lib.mcl_autotune(m.handle, _ptr(points), K, _ptr(poses), N, float(sigma), _ptr(scratch),
                              _stream(stream), C.byref(best)), "mcl_autotune")
-    return best.waves_per_block, best.blocks_per_cu, best.coarse
+    return best.waves_per_block, best.blocks_per_cu, best.coarse, best.runs, best.lds_threshold
+
+
+def get_launch_config(dtype: str, K: int, N: int):
+    """(waves_per_block, blocks_per_cu, coarse, runs, lds_threshold) the sensor update would use."""
+    c = LaunchConfig()
+    _check(_lib.mcl_get_launch_config(DTYPE_CODE[dtype], K, N, C.byref(c)), "mcl_get_launch_config")
+    return c.waves_per_block, c.blocks_per_cu, c.coarse, c.runs, c.lds_threshold
 
 
 def set_launch_config(dtype: str, K: int, N: int, cfg=None):
-    """cfg = (waves_per_block, blocks_per_cu[, coarse]), or None to clear;
-    coarse: 0 auto, 1 global bytes, 2 LDS bits."""
+    """cfg = (waves_per_block, blocks_per_cu[, coarse[, runs[, lds_threshold]]]), or None to clear;
+    coarse: 0 auto, 1 global bytes, 2 LDS bits; runs: 0 automatic or a power of two <= 64."""
     c = None if cfg is None else C.byref(LaunchConfig(*cfg))
     _check(_lib.mcl_set_launch_config(DTYPE_CODE[dtype], K, N, c), "mcl_set_launch_config")
 
@@ -431,10 +444,11 @@ def bench_gather_replay(m: Map, offs, reps: int, two_gathers: bool, blocks: int,
                                         _ptr(sink), sink.numel(), _stream(stream)), "mcl_bench_gather_replay")
 
 
-def bench_line_gather(region, log2_lines: int, lines: int, steps: int, seed: int, blocks: int, sink, stream=None):
+def bench_line_gather(region, log2_lines: int, lines: int, steps: int, seed: int, blocks: int, sink, stream=None,
+                      bytes_per_lane: int = 4):
     _check(_lib.mcl_bench_line_gather(_ptr(region), region.numel() * region.element_size(), int(log2_lines),
-                                      int(lines), int(steps), int(seed) & 0xFFFFFFFF, int(blocks), _ptr(sink),
-                                      sink.numel(), _stream(stream)), "mcl_bench_line_gather")
+                                      int(lines), int(bytes_per_lane), int(steps), int(seed) & 0xFFFFFFFF, int(blocks),
+                                      _ptr(sink), sink.numel(), _stream(stream)), "mcl_bench_line_gather")
 
 
 def bench_stream_read(src, blocks: int, sink, stream=None):

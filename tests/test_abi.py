@@ -164,3 +164,26 @@ def test_binding_structs_match_the_header(mcl, tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_tune_cache_is_read_back(tmp_path):
+    """Launch settings persisted by the tuner (MCL_TUNE_CACHE) are read back by a
+    new process on the same kind of GPU and ignored for another; later lines
+    win.  Run in a child process (the cache is read at the first lookup); with
+    no GPU the library tags the device "unknown"."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    cache.write_text("unknown 0 15 20 2 8 1 4 5\n"        # int16, K class 2^15, N class 2^20
+                     "gfx000/1 0 15 20 8 16 2 64 3\n"     # another GPU: ignored
+                     "unknown 1 10 10 8 0 0 2 0\n"
+                     "unknown 1 10 10 2 4 0 1 7\n")       # later line wins
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2310_04172_amd import mcl\n"
+            "print(mcl.get_launch_config('i16', 28660, 1000000))\n"
+            "print(mcl.get_launch_config('i8', 1000, 600))\n"
+            "print(mcl.get_launch_config('f32', 1000, 600))\n") % ROOT
+    env = dict(os.environ, MCL_TUNE_CACHE=str(cache), HIP_VISIBLE_DEVICES="")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True).stdout
+    lines = out.strip().splitlines()
+    assert lines == ["(2, 8, 1, 4, 5)", "(2, 4, 0, 1, 7)", "(4, 0, 0, 0, 0)"], out

@@ -133,8 +133,10 @@ def test_tick_graph_replay(torch, mcl, maps):
             assert_same(got[i], single(torch, mcl, f), f"replay {rep} job {i}")
 
 
-def test_launch_shapes_are_bit_identical(torch, mcl):
+def test_launch_shapes_are_bit_identical(torch, mcl, tmp_path, monkeypatch):
     say("case: launch shapes")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("MCL_TUNE_CACHE", str(cache))   # the tuner appends its result here
     w = configs.config1()
     m = mcl.Map.from_tsdf(w.tmap)
     P, X = dev(torch, w.poses), dev(torch, w.points)
@@ -145,8 +147,18 @@ def test_launch_shapes_are_bit_identical(torch, mcl):
                 mcl.set_launch_config("i16", w.K, w.N, (wpb, bpc))
                 got = mcl.sensor_update(m, X, P, w.sigma).cpu().numpy()
                 assert np.array_equal(got, ref), (wpb, bpc)
+        for runs in (1, 2, 8, 64):
+            for coarse, l8 in ((0, 1), (0, 8), (1, 0), (2, 0)):
+                mcl.set_launch_config("i16", w.K, w.N, (4, 0, coarse, runs, l8))
+                got = mcl.sensor_update(m, X, P, w.sigma).cpu().numpy()
+                assert np.array_equal(got, ref), (runs, coarse, l8)
         best = mcl.autotune(m, X, P, w.sigma)
-        assert best[0] in (2, 4, 8) and best[1] in (0, 2, 4, 8, 16) and best[2] == 0
+        assert best[0] in (2, 4, 8) and best[1] in (0, 2, 4, 8, 16) and best[2] in (0, 1, 2)
+        assert best[3] in (0, 1, 2, 4, 8, 16, 64) and 0 <= best[4] <= 8
+        assert mcl.get_launch_config("i16", w.K, w.N) == best
+        last = cache.read_text().strip().splitlines()[-1].split()
+        kc, nc = int(np.ceil(np.log2(w.K))), int(np.ceil(np.log2(w.N)))
+        assert [int(x) for x in last[1:]] == [0, kc, nc, *best], last
         assert np.array_equal(mcl.sensor_update(m, X, P, w.sigma).cpu().numpy(), ref)
     finally:
         mcl.set_launch_config("i16", w.K, w.N, None)
