@@ -132,6 +132,23 @@ size_t mcl_map_bytes(mcl_map map);
 mcl_status mcl_sensor_update(mcl_map map, const float *points, int32_t K, const float *poses,
                              int32_t N, float sigma, float *logw, void *stream);
 
+/* The sensor update for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Results are bit for bit those of mcl_sensor_update (same kernels).  Instead
+ * of the stream's workspace, the piece partials (N * ceil(K / 4096) floats when
+ * K > 4096; none otherwise) live in a fixed device array of
+ * MCL_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on until
+ * the process ends.  The call allocates nothing and records no map-use event
+ * (so mcl_map_free does not wait for this work: keep the map alive until the
+ * stream has run it).  Every call on one GPU shares that GPU's array: calls
+ * that may overlap on one GPU race and must be ordered by the caller (one
+ * stream, or events).  MCL_ERANGE if the partials exceed the array (for
+ * example N = 10^6 needs K <= 16 * 4096).  Other arguments and errors as for
+ * mcl_sensor_update. */
+#define MCL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mcl_status mcl_sensor_update_noalloc(mcl_map map, const float *points, int32_t K, const float *poses,
+                                     int32_t N, float sigma, float *logw, void *stream);
+
 /* Sensor update with a trilinear lookup (§III: a pseudo-continuous map value by
  * interpolation).  As mcl_sensor_update, except that m(x_n, z_k) is the
  * trilinear interpolation of the 8 voxel centres around the transformed point

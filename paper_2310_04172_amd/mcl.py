@@ -33,6 +33,7 @@ TICK_GRAPH, TICK_NOWAIT = 1, 2
 LOOKUP_NEAREST, LOOKUP_TRILINEAR = 0, 1
 MAX_PARTICLES = 1 << 21
 MAX_POINTS = 1 << 20
+NOALLOC_SCRATCH_BYTES = 64 << 20
 WQ_SHIFT = 42
 DTYPE_CODE = {"i16": 0, "i8": 1, "f32": 2}
 
@@ -60,6 +61,7 @@ _lib.mcl_map_free.argtypes = [_P]
 _lib.mcl_map_upload_bricks.argtypes = [C.POINTER(MapDesc), C.c_int64, _P, _P, _P, C.POINTER(_P)]
 _lib.mcl_sensor_update.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_sensor_update_trilinear.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
+_lib.mcl_sensor_update_noalloc.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
 _lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, C.c_uint64, _P, _P, _P, _P]
 _lib.mcl_debug_voxel_indices.argtypes = [_P, _P, _I, _P, _I, _P, _P]
@@ -82,7 +84,7 @@ _lib.mcl_bench_line_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, _I, C.c_uint3
 _lib.mcl_bench_stream_read.argtypes = [_P, C.c_size_t, _I, _P, C.c_size_t, _P]
 _lib.mcl_last_error.restype = C.c_char_p
 for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear",
-           "mcl_normalize",
+           "mcl_sensor_update_noalloc", "mcl_normalize",
            "mcl_resample",
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_get_launch_config",
            "mcl_pose_estimate", "mcl_motion_update",
