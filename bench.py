@@ -295,15 +295,24 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
                            "algorithmic_tsdf_bytes_per_launch": tsdf_bytes,
                            "bytes_frac_of_hbm_peak": tsdf_bytes / (sensor_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                            "gather_ceilings": gr}
+        out["roofline"]["ceiling"] = "texture path (the kernel's own gathers replayed, lines in cache)"
         lines = profiled_lines(workload_key)
         if lines:
-            # the fabric ceiling: the launch's line fetches beyond L2 (counters) at the
-            # measured random-line rate of the Infinity Cache and of HBM
+            # the fabric ceiling: the launch's 128-byte line fetches beyond L2 (counter
+            # profile of these sources) at the measured random-line rate of the
+            # Infinity Cache (the upper one; HBM's is reported beside it)
             lpe = lines / evals
             for where in ("MALL", "HBM"):
                 rate = gr["random_line_gathers"][f"{where}_64_lines_per_gather"]["G_lines_per_s"]
                 out["roofline"][f"fabric_ceiling_{where}_G_evals_per_s"] = rate / lpe
             out["roofline"]["l2_miss_lines_per_eval"] = lpe
+            fabric = out["roofline"]["fabric_ceiling_MALL_G_evals_per_s"]
+            if fabric < peak:
+                out["roofline"]["peak"] = fabric
+                out["roofline"]["frac"] = achieved / fabric
+                out["roofline"]["ceiling"] = ("fabric line rate: the launch's L2-miss lines (counters) at the "
+                                              "measured random 128-byte line rate of the Infinity Cache")
+            out["roofline"]["texture_frac"] = achieved / peak
         if workload_key in ("global", "converged"):
             out["roofline"]["limiter"] = profiled_limiter(workload_key)
         log(f"gather roofline: kernel {achieved:.0f} G evals/s, texture ceiling {peak:.0f} G evals/s "
@@ -381,7 +390,7 @@ def gather_roofline(torch, mcl, m, pts, poses, two_gathers=True, sample=65536, s
     for width in (2, 4):
         for lines in (1, 2, 4, 8, 16, 32, 64):
             steps = 64
-            fn = lambda: mcl.bench_line_gather(region, 6, lines, steps, 7, gblocks, gsink, stream, bytes_per_lane=width)
+            fn = lambda: mcl.bench_l1_gather(region, lines, width, steps, gblocks, gsink, stream)
             fn()
             ms = _median_ms(torch, fn, stream)
             ng = gblocks * 4 * steps * 16

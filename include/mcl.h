@@ -432,6 +432,14 @@ mcl_status mcl_bench_line_gather(const void *region, size_t region_bytes, int32_
                                  int32_t bytes_per_lane, int32_t steps, uint32_t seed, int32_t blocks, float *sink,
                                  size_t sink_floats, void *stream);
 
+/* Texture-path cost of a gather: each 64-lane gather reads bytes_per_lane (1, 2
+ * or 4) bytes per lane from exactly `lines` (1..64, a power of two) 128-byte
+ * lines of one 8 KiB block (block_bytes >= 8192), which stays in the L1 cache;
+ * the address is a scalar base plus a fixed lane offset, so no vector
+ * arithmetic competes with the loads; `steps` x 16 gathers per wave. */
+mcl_status mcl_bench_l1_gather(const void *block, size_t block_bytes, int32_t lines, int32_t bytes_per_lane,
+                               int32_t steps, int32_t blocks, float *sink, size_t sink_floats, void *stream);
+
 /* Coalesced 16-byte loads over `bytes` (a multiple of 16) of device memory. */
 mcl_status mcl_bench_stream_read(const void *src, size_t bytes, int32_t blocks, float *sink, size_t sink_floats,
                                  void *stream);

@@ -147,6 +147,35 @@ __global__ __launch_bounds__(256) void line_gather_kernel(const char *__restrict
     sink[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = (float)acc;
 }
 
+// Texture-path cost of a gather against the lines it touches, data resident
+// in L1: lane l reads W bytes at byte offset 128 (l / (64 / lines)) + W (l mod
+// (64 / lines)) (mod 128) of an 8 KiB block, so a gather touches exactly
+// `lines` lines; the block's base is a scalar and the lane offsets fixed, so a
+// load costs no vector instruction besides the sum.
+template <int W>
+__global__ __launch_bounds__(256) void l1_gather_kernel(const char *base, int lines, int steps, float *__restrict__ sink) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int per = kWave / lines;
+    const uint32_t lo = (uint32_t)(lane / per) * 128u + (((uint32_t)(lane % per) * W) & 127u);
+    uint32_t acc = 0;
+    for (int s = 0; s < steps; ++s) {
+        uint32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            // the same lane offset every time, opaque to the compiler, so that
+            // no load is merged with another or hoisted out of the loop; the
+            // address is the scalar base plus this 32-bit offset, as in the
+            // sensor kernel's gathers
+            uint32_t o = lo;
+            asm volatile("" : "+v"(o));
+            v[u] = load_w<W>(base + o);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    sink[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = (float)acc;
+}
+
 typedef uint32_t u32x4r __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void stream_read_kernel(const u32x4r *__restrict__ src, size_t n16,
@@ -223,6 +252,23 @@ extern "C" mcl_status mcl_bench_line_gather(const void *region, size_t region_by
     else if (bytes_per_lane == 2) line_gather_kernel<2><<<(unsigned)blocks, 256, 0, s>>>(b, log2_lines, lines, steps, seed, sink);
     else line_gather_kernel<4><<<(unsigned)blocks, 256, 0, s>>>(b, log2_lines, lines, steps, seed, sink);
     return check_launch("line_gather_kernel");
+}
+
+extern "C" mcl_status mcl_bench_l1_gather(const void *block, size_t block_bytes, int32_t lines, int32_t bytes_per_lane,
+                                          int32_t steps, int32_t blocks, float *sink, size_t sink_floats,
+                                          void *stream) {
+    if (!block || !sink) return fail(MCL_EINVAL, "bench_l1_gather: NULL argument");
+    if (block_bytes < 8192) return fail(MCL_EINVAL, "bench_l1_gather: the block must hold 8 KiB");
+    if (sink_floats < (size_t)blocks * 256) return fail(MCL_EINVAL, "bench_l1_gather: sink shorter than blocks * 256");
+    if (!(lines == 1 || lines == 2 || lines == 4 || lines == 8 || lines == 16 || lines == 32 || lines == 64) ||
+        steps < 1 || blocks < 1 || !(bytes_per_lane == 1 || bytes_per_lane == 2 || bytes_per_lane == 4))
+        return fail(MCL_EINVAL, "bench_l1_gather: lines a power of two <= 64, 1, 2 or 4 bytes per lane");
+    const char *b = static_cast<const char *>(block);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (bytes_per_lane == 1) l1_gather_kernel<1><<<(unsigned)blocks, 256, 0, s>>>(b, lines, steps, sink);
+    else if (bytes_per_lane == 2) l1_gather_kernel<2><<<(unsigned)blocks, 256, 0, s>>>(b, lines, steps, sink);
+    else l1_gather_kernel<4><<<(unsigned)blocks, 256, 0, s>>>(b, lines, steps, sink);
+    return check_launch("l1_gather_kernel");
 }
 
 extern "C" mcl_status mcl_bench_stream_read(const void *src, size_t bytes, int32_t blocks, float *sink,

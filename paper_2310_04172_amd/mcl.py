@@ -82,6 +82,7 @@ _lib.mcl_bench_gather_offsets.argtypes = [_P, _P, _I, _P, _I, _I, _P, _P]
 _lib.mcl_bench_gather_replay.argtypes = [_P, _P, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]
 _lib.mcl_bench_line_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, _I, C.c_uint32, _I, _P, C.c_size_t, _P]
 _lib.mcl_bench_stream_read.argtypes = [_P, C.c_size_t, _I, _P, C.c_size_t, _P]
+_lib.mcl_bench_l1_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, _I, _P, C.c_size_t, _P]
 _lib.mcl_last_error.restype = C.c_char_p
 for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear",
            "mcl_sensor_update_noalloc", "mcl_normalize",
@@ -89,7 +90,7 @@ for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_senso
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_get_launch_config",
            "mcl_pose_estimate", "mcl_motion_update",
            "mcl_init_uniform", "mcl_init_gaussian", "mcl_debug_philox", "mcl_bench_gather_offsets",
-           "mcl_bench_gather_replay", "mcl_bench_line_gather", "mcl_bench_stream_read"):
+           "mcl_bench_gather_replay", "mcl_bench_line_gather", "mcl_bench_stream_read", "mcl_bench_l1_gather"):
     getattr(_lib, _f).restype = C.c_int32
 
 
@@ -451,6 +452,12 @@ def bench_line_gather(region, log2_lines: int, lines: int, steps: int, seed: int
     _check(_lib.mcl_bench_line_gather(_ptr(region), region.numel() * region.element_size(), int(log2_lines),
                                       int(lines), int(bytes_per_lane), int(steps), int(seed) & 0xFFFFFFFF, int(blocks),
                                       _ptr(sink), sink.numel(), _stream(stream)), "mcl_bench_line_gather")
+
+
+def bench_l1_gather(block, lines: int, bytes_per_lane: int, steps: int, blocks: int, sink, stream=None):
+    _check(_lib.mcl_bench_l1_gather(_ptr(block), block.numel() * block.element_size(), int(lines), int(bytes_per_lane),
+                                    int(steps), int(blocks), _ptr(sink), sink.numel(), _stream(stream)),
+           "mcl_bench_l1_gather")
 
 
 def bench_stream_read(src, blocks: int, sink, stream=None):
