@@ -201,9 +201,9 @@ using namespace mcl;
 extern "C" mcl_status mcl_bench_gather_offsets(mcl_map map, const float *points, int32_t K, const float *poses,
                                                int32_t N, int32_t masked, uint32_t *offs, void *stream) {
     if (!map || !points || !poses || !offs) return fail(MCL_EINVAL, "bench_gather_offsets: NULL argument");
-    if (map->sparse) return fail(MCL_EINVAL, "bench_gather_offsets: dense maps only");
     if (K < 1 || N < 1 || K > MCL_MAX_POINTS || N > MCL_MAX_PARTICLES)
         return fail(MCL_EINVAL, "bench_gather_offsets: need 1 <= K <= MCL_MAX_POINTS and 1 <= N <= MCL_MAX_PARTICLES");
+    if (map->sparse) return fail(MCL_EINVAL, "bench_gather_offsets: dense maps only");
     const int64_t total = (int64_t)N * K;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const unsigned blocks = (unsigned)((total + 255) / 256);
@@ -219,10 +219,10 @@ extern "C" mcl_status mcl_bench_gather_replay(mcl_map map, const uint32_t *offs,
                                               int32_t two_gathers, int32_t blocks, float *sink, size_t sink_floats,
                                               void *stream) {
     if (!map || !offs || !sink) return fail(MCL_EINVAL, "bench_gather_replay: NULL argument");
-    if (sink_floats < (size_t)blocks * 256) return fail(MCL_EINVAL, "bench_gather_replay: sink shorter than blocks * 256");
-    if (map->sparse) return fail(MCL_EINVAL, "bench_gather_replay: dense maps only");
     if (S < kGroup || S % kGroup || K < 1 || K > MCL_MAX_POINTS || reps < 1 || blocks < 1)
         return fail(MCL_EINVAL, "bench_gather_replay: need S a positive multiple of 64, 1 <= K, reps >= 1, blocks >= 1");
+    if (sink_floats < (size_t)blocks * 256) return fail(MCL_EINVAL, "bench_gather_replay: sink shorter than blocks * 256");
+    if (map->sparse) return fail(MCL_EINVAL, "bench_gather_replay: dense maps only");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (map->dtype == MCL_TSDF_I16)
         gather_replay_kernel<int16_t><<<(unsigned)blocks, 256, 0, s>>>(map->view, offs, S, K, reps, two_gathers, sink);

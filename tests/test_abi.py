@@ -122,6 +122,15 @@ def test_tick_and_tuning_argument_errors(mcl):
     assert lib.mcl_set_launch_config(0, 1000, 1000, C.byref(bad)) == mcl.MCL_EINVAL
     assert lib.mcl_set_launch_config(5, 1000, 1000, None) == mcl.MCL_EINVAL
     assert lib.mcl_autotune(None, None, 0, None, 0, 0.1, None, None, None) == mcl.MCL_EINVAL
+    # measurement calls: NULL arguments, sizes, sinks shorter than the grid
+    assert lib.mcl_bench_gather_offsets(None, P(0x1000), 10, P(0x2000), 10, 0, P(0x3000), None) == mcl.MCL_EINVAL
+    assert lib.mcl_bench_gather_replay(P(0x1000), P(0x2000), 100, 10, 1, 1, 1, P(0x3000), 256, None) == mcl.MCL_EINVAL
+    assert lib.mcl_bench_line_gather(P(0x1000), 1 << 20, 14, 64, 4, 1, 1, 8, P(0x2000), 8 * 256, None) == mcl.MCL_EINVAL
+    assert b"exceed the region" in lib.mcl_last_error()
+    assert lib.mcl_bench_line_gather(P(0x1000), 1 << 30, 14, 3, 4, 1, 1, 8, P(0x2000), 8 * 256, None) == mcl.MCL_EINVAL
+    assert lib.mcl_bench_l1_gather(P(0x1000), 4096, 4, 2, 1, 8, P(0x2000), 8 * 256, None) == mcl.MCL_EINVAL
+    assert lib.mcl_bench_l1_gather(P(0x1000), 8192, 4, 2, 1, 8, P(0x2000), 100, None) == mcl.MCL_EINVAL
+    assert lib.mcl_bench_stream_read(P(0x1000), 17, 8, P(0x2000), 8 * 256, None) == mcl.MCL_EINVAL
 
 
 def test_binding_constants_match_the_header(mcl):
