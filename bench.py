@@ -100,11 +100,11 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
                                                f"{BOX_CPU_SHARE} a one-GPU box allots"}
 
 
-# the sources that make up the sensor kernel, its map layout and its launch
+# the sources that make up the sensor kernel's device code and its map layout
+# (the launch settings a profile ran with are recorded in the profile itself)
 SENSOR_SOURCES = ("paper_2310_04172_amd/csrc/sensor.hip", "paper_2310_04172_amd/csrc/voxel.h",
                   "paper_2310_04172_amd/csrc/jobs.h", "paper_2310_04172_amd/csrc/mcl_internal.h",
-                  "paper_2310_04172_amd/csrc/map.hip", "paper_2310_04172_amd/csrc/tune.hip",
-                  "paper_2310_04172_amd/build.py")
+                  "paper_2310_04172_amd/csrc/map.hip", "paper_2310_04172_amd/build.py")
 
 
 def kernel_source_hash() -> str:
@@ -282,7 +282,13 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
     out["pose_estimate"] = est
     if sparse_info:
         out["config"]["sparse_map"] = sparse_info
-    if with_roofline and not trilinear and not sparse:
+    # a gather roofline needs a launch that fills the chip (the replay uses one wave per
+    # 64 particles x 4096 points); small launches are bound by latency, not gathers
+    fills_chip = (min(N, 65536) // 64) * ((K + 4095) // 4096) >= 4096
+    if with_roofline and not trilinear and not sparse and not fills_chip:
+        out["roofline_note"] = (f"no gather roofline: N x K = {evals:.3g} evaluations is a latency-bound launch "
+                                f"({N // 64 + 1} groups of 64 particles x {(K + 4095) // 4096} pieces)")
+    if with_roofline and not trilinear and not sparse and fills_chip:
         achieved = evals / (sensor_ms * 1e-3) / 1e9
         two = workload_key != "converged"   # global localisation reads the masks as bytes, converged from LDS
         gr = gather_roofline(torch, mcl, m, pts, poses, two_gathers=two, stream=stream)

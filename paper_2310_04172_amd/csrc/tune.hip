@@ -6,7 +6,9 @@
 // every setting gives the same bits and the tuner only ever changes speed.
 //
 // Choices are kept per storage type and size class (K and N rounded up to
-// powers of two).  With the environment variable MCL_TUNE_CACHE naming a file,
+// powers of two), whatever the spread of the particles they were timed on; so
+// the tuner keeps the per-wave coarse-level choice, which adapts to the spread,
+// unless a forced mode is more than 1 % faster.  With the environment variable MCL_TUNE_CACHE naming a file,
 // they persist across processes: the file is read at the first lookup and a
 // line is appended per tuning result (later lines win), tagged with the GPU's
 // architecture and compute-unit count so that another GPU ignores them.
@@ -159,14 +161,23 @@ extern "C" mcl_status mcl_autotune(mcl_map map, const float *points, int32_t K, 
         }
         return r;
     };
-    LaunchCfg bestc = kDefaultCfg;
-    float best_ms = INFINITY;
+    LaunchCfg bestc = kDefaultCfg, best_auto = kDefaultCfg;
+    float best_ms = INFINITY, best_auto_ms = INFINITY;
+    // auto: the coarse level chosen per wave with a threshold below 8/8 - the
+    // settings that adapt to the particle spread of whatever workload later
+    // runs in this size class
+    auto adaptive = [](const LaunchCfg &c) { return c.coarse == kCoarseAuto && c.lds8 < 8; };
     auto try_cfg = [&](const LaunchCfg &cfg) {
         float ms = INFINITY;
         if (st == MCL_OK) st = time_cfg(cfg, ms);
-        if (st == MCL_OK && ms < best_ms) {
+        if (st != MCL_OK) return;
+        if (ms < best_ms) {
             best_ms = ms;
             bestc = cfg;
+        }
+        if (adaptive(cfg) && ms < best_auto_ms) {
+            best_auto_ms = ms;
+            best_auto = cfg;
         }
     };
     // coordinate descent: launch shape, then runs per group, then the coarse level
@@ -183,6 +194,11 @@ extern "C" mcl_status mcl_autotune(mcl_map map, const float *points, int32_t K, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != MCL_OK) return st;
+    // a forced coarse mode suits the spread of the particles it was timed on
+    // (mask bytes for particles spread over the map, LDS bits for converged
+    // ones); the per-wave choice serves both, so it is kept when it is within
+    // 1 % of the fastest
+    if (!adaptive(bestc) && best_auto_ms <= 1.01f * best_ms) bestc = best_auto;
     if ((st = note_map_use(map, stream)) != MCL_OK) return st;
     {
         std::lock_guard<std::mutex> lk(g_tmu);
