@@ -136,13 +136,16 @@ class Engine:
     [12, N] tensor made on `stream` by the library's initialisation calls.
     on_complete(robot, filter): optional, called when an update has completed,
     before the resampled set becomes the robot's particle set (tests read the
-    update's inputs and outputs there)."""
+    update's inputs and outputs there).
+    torch_module: the torch module the engine takes streams, events and buffers
+    from (default: torch itself; tests of the host logic pass a stand-in)."""
 
     def __init__(self, robots, init_particles, budget_bytes: int = 64 << 30, max_evals_per_tick: float = 1.2e11,
                  n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0, depth: int = 1,
-                 order: str = "fifo", on_complete=None):
-        import torch
-        self.torch = torch
+                 order: str = "fifo", on_complete=None, torch_module=None):
+        if torch_module is None:
+            import torch as torch_module
+        torch = self.torch = torch_module
         self.robots = robots
         self.init_particles = init_particles
         self.budget = int(budget_bytes)

@@ -1,0 +1,264 @@
+"""The serving engine's host logic, on the CPU: streams, events and buffers are
+stand-ins and the library calls are replaced by recorders, so the tests see
+what the engine asks for and in which stream context.
+
+Checked: latest wins (a superseded scan is dropped and counted) and one update
+per robot in flight; the memory budget; a robot's particle set and buffers are
+made inside the context of the stream its tick then runs on; uploads run on
+the copy stream after it waited for the tick's stream, and the tick's stream
+waits for them through an event; a tick refused as busy is retried; the two
+request orders; the resampling draw (seed, tick) of each update.
+"""
+
+import time
+
+import pytest
+
+from paper_2310_04172_amd import serve
+
+
+class FakeTensor:
+    def __init__(self, shape, tag=""):
+        self.shape = tuple(shape)
+        self.tag = tag
+        self.copies = []
+
+    def numel(self):
+        n = 1
+        for d in self.shape:
+            n *= d
+        return n
+
+    @property
+    def device(self):
+        return "fake"
+
+    def copy_(self, src, non_blocking=False):
+        self.copies.append((src, FakeTorch.current[-1], non_blocking))
+        return self
+
+
+class FakeStream:
+    count = 0
+
+    def __init__(self):
+        FakeStream.count += 1
+        self.name = f"s{FakeStream.count}"
+        self.log = []
+
+    def wait_stream(self, other):
+        self.log.append(("wait_stream", other.name))
+
+    def wait_event(self, ev):
+        self.log.append(("wait_event", ev.stream.name if ev.stream else None, ev.serial))
+
+    def __repr__(self):
+        return self.name
+
+
+class FakeEvent:
+    serials = 0
+
+    def __init__(self, enable_timing=False):
+        self.stream = None
+        self.t = None
+        FakeEvent.serials += 1
+        self.serial = FakeEvent.serials
+
+    def record(self, stream=None):
+        self.stream = stream if stream is not None else FakeTorch.current[-1]
+        self.t = time.perf_counter()
+        if self.stream is not None:
+            self.stream.log.append(("record", self.serial))
+
+    def query(self):
+        return True
+
+    def synchronize(self):
+        pass
+
+    def elapsed_time(self, other):
+        return (other.t - self.t) * 1e3
+
+
+class _StreamCtx:
+    def __init__(self, s):
+        self.s = s
+
+    def __enter__(self):
+        FakeTorch.current.append(self.s)
+
+    def __exit__(self, *a):
+        FakeTorch.current.pop()
+
+
+class FakeCuda:
+    Stream = FakeStream
+    Event = FakeEvent
+
+    @staticmethod
+    def synchronize():
+        pass
+
+    @staticmethod
+    def stream(s):
+        return _StreamCtx(s)
+
+
+class FakeTorch:
+    cuda = FakeCuda
+    float32 = "float32"
+    current = [None]            # stream contexts entered (None: the default stream)
+
+    @staticmethod
+    def empty_like(t):
+        return FakeTensor(t.shape, "empty_like@" + str(FakeTorch.current[-1]))
+
+    @staticmethod
+    def empty(shape, dtype=None, device=None):
+        return FakeTensor(shape, "empty@" + str(FakeTorch.current[-1]))
+
+
+class FakeFilter:
+    def __init__(self, m, points, poses, sigma, seed, tick=0, want_w=True, **kw):
+        self.map, self.points, self.poses, self.sigma, self.seed, self.tick = m, points, poses, sigma, seed, tick
+        self.made_in = FakeTorch.current[-1]
+        self.poses_out = None
+        self.logw = self.wq = self.log_z = self.idx = None
+
+    @property
+    def N(self):
+        return self.poses.shape[1]
+
+
+class Recorder:
+    """Stands in for the library calls the engine makes."""
+
+    def __init__(self, busy_first=0):
+        self.ticks = []         # (stream, [(rid, seed, tick)])
+        self.plain = []
+        self.busy_left = busy_first
+
+    def tick(self, filters, graph=False, stream=None, nowait=False):
+        assert FakeTorch.current[-1] is stream, "tick enqueued outside its stream's context"
+        if self.busy_left:
+            self.busy_left -= 1
+            return False
+        # a robot's resampling seed is engine seed * 2^32 + robot id
+        self.ticks.append((stream, [(f.seed & 0xFFFFFFFF, f.seed, f.tick) for f in filters]))
+        return True
+
+    def sensor_update(self, m, points, poses, sigma, logw, stream):
+        self.plain.append(stream)
+
+    def normalize(self, *a, **k):
+        pass
+
+    def resample(self, *a, **k):
+        pass
+
+
+@pytest.fixture
+def lib(monkeypatch):
+    rec = Recorder()
+    monkeypatch.setattr(serve.mcl, "Filter", FakeFilter)
+    monkeypatch.setattr(serve.mcl, "tick", rec.tick)
+    monkeypatch.setattr(serve.mcl, "sensor_update", rec.sensor_update)
+    monkeypatch.setattr(serve.mcl, "normalize", rec.normalize)
+    monkeypatch.setattr(serve.mcl, "resample", rec.resample)
+    monkeypatch.setattr(serve.mcl, "job_bytes", lambda N, K: 1000 * N + K)
+    FakeTorch.current = [None]
+    return rec
+
+
+def make(n_robots, lib, phases=((None, "track"),), N=10, K=5):
+    made = []
+
+    def init(r, phase, stream, probe=False):
+        if probe:
+            return N
+        made.append((r.rid, phase, stream, FakeTorch.current[-1]))
+        return FakeTensor((12, N), "init")
+
+    robots = [serve.Robot(i, "map", FakeTensor((3, K), "host"), 0.1, list(phases)) for i in range(n_robots)]
+    return robots, init, made
+
+
+def run(engine, trace):
+    return engine.run(trace)
+
+
+def test_latest_wins_and_one_update_in_flight(lib):
+    robots, init, made = make(1, lib)
+    eng = serve.Engine(robots, init, n_streams=1, torch_module=FakeTorch, seed=3)
+    st = run(eng, [(0.0, 0), (0.0, 0), (0.0, 0)])
+    assert st.arrived == 3 and st.dropped == 2 and st.completed == 1
+    assert len(lib.ticks) == 1 and lib.ticks[0][1] == [(0, serve.robot_seed(3, 0), 0)]
+
+
+def test_budget_admission_and_phase_release(lib):
+    robots, init, made = make(3, lib, phases=((1, "global"), (None, "track")))
+    budget = 1000 * 10 + 5          # one robot's job bytes
+    eng = serve.Engine(robots, init, budget_bytes=budget, n_streams=1, torch_module=FakeTorch)
+    st = run(eng, [(0.0, 0), (0.0, 1), (0.0, 2)])
+    assert st.completed == 3 and st.max_resident_bytes <= budget
+    assert [t[1][0][0] for t in lib.ticks] == [0, 1, 2]     # one at a time, as the budget frees
+    assert all(r.phase == "track" and r.filt is None for r in robots)
+
+
+def test_particles_and_buffers_made_on_the_ticks_stream(lib):
+    """The advisor's race: a robot's particle set, its buffers and its filter are
+    made inside the context of the stream its tick runs on."""
+    robots, init, made = make(4, lib)
+    eng = serve.Engine(robots, init, n_streams=2, max_evals_per_tick=2 * 10 * 5, torch_module=FakeTorch)
+    st = run(eng, [(0.0, i) for i in range(4)])
+    assert st.completed == 4
+    tick_stream = {}
+    for s, jobs in lib.ticks:
+        for rid, _, _ in jobs:
+            tick_stream[rid] = s
+    for rid, phase, stream_arg, ctx in made:
+        assert stream_arg is tick_stream[rid] and ctx is tick_stream[rid], (rid, stream_arg, ctx)
+    for r in robots:
+        assert r.filt.made_in is tick_stream[r.rid]
+        assert r.poses.tag == "init" or r.poses.tag.startswith("empty_like@" + tick_stream[r.rid].name)
+
+
+def test_uploads_are_ordered_around_the_tick(lib):
+    robots, init, made = make(2, lib)
+    eng = serve.Engine(robots, init, n_streams=1, torch_module=FakeTorch)
+    run(eng, [(0.0, 0), (0.0, 1)])
+    s, cs = eng.streams[0], eng.copy_stream
+    # the copy stream waited for the tick's stream, copied, recorded an event; the
+    # tick's stream waited for that event
+    assert ("wait_stream", s.name) in cs.log
+    rec = [e for e in cs.log if e[0] == "record"]
+    assert rec and ("wait_event", cs.name, rec[0][1]) in s.log
+    for r in robots:
+        assert r.points is None or all(c[1] is cs and c[2] for c in r.points.copies)
+    assert eng.stats.uploaded_bytes == 2 * 3 * 5 * 4
+
+
+def test_busy_tick_is_retried(lib):
+    lib.busy_left = 2
+    robots, init, made = make(2, lib)
+    eng = serve.Engine(robots, init, n_streams=1, torch_module=FakeTorch)
+    st = run(eng, [(0.0, 0), (0.0, 1)])
+    assert st.busy == 2 and st.completed == 2 and st.dropped == 0
+
+
+@pytest.mark.parametrize("order", ["fifo", "stale"])
+def test_request_order(lib, order):
+    """Robot 0 completes an update first; then both robots wait, robot 0's scan
+    the older one: fifo serves robot 0 first, stale serves robot 1 (never
+    updated) first."""
+    robots, init, made = make(2, lib)
+    eng = serve.Engine(robots, init, plain=True, torch_module=FakeTorch, order=order)
+    robots[0].last_done = 0.5              # robot 0 was updated recently
+    robots[0].pending, robots[1].pending = 0.01, 0.02
+    robots[0].in_flight = robots[1].in_flight = None
+    eng.stats.arrived = 2
+    st = run(eng, [])
+    assert st.completed == 2
+    # one request at a time: the robot whose particle set was made first went first
+    assert made[0][0] == (0 if order == "fifo" else 1)
