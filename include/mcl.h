@@ -366,8 +366,8 @@ typedef struct {
 } mcl_launch_config;
 
 /* Time launch settings on the given filter by coordinate descent (the launch
- * shape, then runs, then the coarse level; each the median of three timed
- * launches; synchronises `stream`), keep the fastest for its storage type and
+ * shape, then runs, then the coarse level; each the median of three batches of
+ * back-to-back launches, a batch lasting about 2 ms; synchronises `stream`), keep the fastest for its storage type and
  * size class (K and N rounded up to powers of two) for later mcl_sensor_update
  * / mcl_tick calls, and return it in *best (may be NULL).  With the environment
  * variable MCL_TUNE_CACHE naming a file, results are appended to it and read

@@ -144,23 +144,37 @@ extern "C" mcl_status mcl_autotune(mcl_map map, const float *points, int32_t K, 
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(MCL_EDEVICE, "autotune: event creation failed");
     mcl_status st = MCL_OK;
-    // median of three timed launches after one untimed
+    // Median over three batches of `reps` back-to-back launches (after one
+    // untimed launch), per launch: a batch lasts at least about 2 ms, so short
+    // launches are timed without the events' own resolution and jitter.
+    int reps = 1;
+    auto batch = [&](const LaunchCfg &cfg, int n, float &ms) -> mcl_status {
+        mcl_status r = MCL_OK;
+        if (hipEventRecord(e0, stream) != hipSuccess) return fail(MCL_EDEVICE, "autotune: event record failed");
+        for (int i = 0; i < n && r == MCL_OK; ++i)
+            r = launch_sensor_cfg(map, points, K, poses, N, c, logw, cfg, stream, nullptr);
+        if (r == MCL_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            r = fail(MCL_EDEVICE, "autotune: timing failed");
+        ms /= (float)n;
+        return r;
+    };
     auto time_cfg = [&](const LaunchCfg &cfg, float &ms) -> mcl_status {
         mcl_status r = launch_sensor_cfg(map, points, K, poses, N, c, logw, cfg, stream, nullptr);
         float t[3];
-        for (int i = 0; i < 3 && r == MCL_OK; ++i) {
-            if (hipEventRecord(e0, stream) != hipSuccess) r = fail(MCL_EDEVICE, "autotune: event record failed");
-            if (r == MCL_OK) r = launch_sensor_cfg(map, points, K, poses, N, c, logw, cfg, stream, nullptr);
-            if (r == MCL_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                                hipEventElapsedTime(&t[i], e0, e1) != hipSuccess))
-                r = fail(MCL_EDEVICE, "autotune: timing failed");
-        }
+        for (int i = 0; i < 3 && r == MCL_OK; ++i) r = batch(cfg, reps, t[i]);
         if (r == MCL_OK) {
             std::sort(t, t + 3);
             ms = t[1];
         }
         return r;
     };
+    {   // the batch length, from the default setting's time
+        float once = 0.0f;
+        if ((st = launch_sensor_cfg(map, points, K, poses, N, c, logw, kDefaultCfg, stream, nullptr)) == MCL_OK)
+            st = batch(kDefaultCfg, 1, once);
+        if (st == MCL_OK) reps = std::max(1, std::min(64, (int)std::ceil(2.0f / std::max(once, 1e-3f))));
+    }
     LaunchCfg bestc = kDefaultCfg, best_auto = kDefaultCfg;
     float best_ms = INFINITY, best_auto_ms = INFINITY;
     // auto: the coarse level chosen per wave with a threshold below 8/8 - the
