@@ -22,8 +22,10 @@ tick is queued behind the running one.
   scan served is then one that arrived recently, not one that waited longest).
 * Admission: a robot becomes resident when its device state (``mcl_job_bytes``)
   fits the memory budget; until then its request waits.  Its particle set is
-  made by the library's initialisation calls, on the stream of the tick that
-  first serves it, so the tick is ordered after it.
+  made by the library's initialisation calls on the stream of the tick being
+  built, and an event recorded there after them orders the robot's first
+  upload (and so its first tick) after them, also when that tick is refused
+  as busy and the robot is then served on another stream.
 * Resampling draws: robot r's n-th completed update uses seed
   ``seed * 2^32 + r`` and tick n (the library's draw), so results do not depend
   on batching or timing.
@@ -94,6 +96,7 @@ class Robot:
     in_flight: float | None = None
     evals_done: int = 0
     last_done: float = -1.0     # completion time of the last update (-1: none yet)
+    ready: object = None        # event after the initialisation, until the first update is enqueued
 
     @property
     def K(self):
@@ -178,6 +181,8 @@ class Engine:
             r.spare = torch.empty_like(r.poses)
             r.points = torch.empty((3, r.K), dtype=torch.float32, device=r.poses.device)
             r.filt = mcl.Filter(r.map, r.points, r.poses, r.sigma, robot_seed(self.seed, r.rid), want_w=False)
+        r.ready = torch.cuda.Event()
+        r.ready.record(stream)
         r.filt.poses_out = r.spare
         r.bytes = need
         self.used += need
@@ -185,7 +190,7 @@ class Engine:
         return True
 
     def _release(self, r: Robot):
-        r.filt = None
+        r.filt = r.ready = None
         r.poses = r.spare = r.points = None
         self.used -= r.bytes
         r.bytes = 0
@@ -221,10 +226,14 @@ class Engine:
 
     def _upload(self, batch, s):
         """Copy the batch's scans from pinned host memory on the copy stream; the
-        tick's stream `s` waits for them."""
+        tick's stream `s` waits for them.  The copies wait for s and for the
+        initialisation of robots admitted on any stream and not yet served."""
         torch = self.torch
         cs = self.copy_stream
-        cs.wait_stream(s)                # the device buffers were made on s (admission)
+        cs.wait_stream(s)
+        for r in batch:
+            if r.ready is not None:
+                cs.wait_event(r.ready)
         with torch.cuda.stream(cs):
             for r in batch:
                 r.points.copy_(r.host_points, non_blocking=True)
@@ -302,7 +311,7 @@ class Engine:
                     self._upload(batch, s)
                     if self._submit(batch, s):
                         for r in batch:
-                            r.in_flight, r.pending = r.pending, None
+                            r.in_flight, r.pending, r.ready = r.pending, None, None
                         ev = torch.cuda.Event(enable_timing=True)
                         ev.record(s)
                         inflight.append((ev, batch, si))

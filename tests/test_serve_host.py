@@ -6,8 +6,9 @@ Checked: latest wins (a superseded scan is dropped and counted) and one update
 per robot in flight; the memory budget; a robot's particle set and buffers are
 made inside the context of the stream its tick then runs on; uploads run on
 the copy stream after it waited for the tick's stream, and the tick's stream
-waits for them through an event; a tick refused as busy is retried; the two
-request orders; the resampling draw (seed, tick) of each update.
+waits for them through an event; a tick refused as busy is retried, on
+another stream only after the admission's initialisation; the two request
+orders; the resampling draw (seed, tick) of each update.
 """
 
 import time
@@ -58,12 +59,14 @@ class FakeStream:
 
 class FakeEvent:
     serials = 0
+    lag = 0                     # queries an event answers "not yet" before it completes
 
     def __init__(self, enable_timing=False):
         self.stream = None
         self.t = None
         FakeEvent.serials += 1
         self.serial = FakeEvent.serials
+        self.queries_left = FakeEvent.lag
 
     def record(self, stream=None):
         self.stream = stream if stream is not None else FakeTorch.current[-1]
@@ -72,6 +75,9 @@ class FakeEvent:
             self.stream.log.append(("record", self.serial))
 
     def query(self):
+        if self.queries_left:
+            self.queries_left -= 1
+            return False
         return True
 
     def synchronize(self):
@@ -138,11 +144,14 @@ class Recorder:
         self.ticks = []         # (stream, [(rid, seed, tick)])
         self.plain = []
         self.busy_left = busy_first
+        self.busy_calls = set()  # indices of tick calls to refuse (0 = the first call)
+        self.calls = 0
 
     def tick(self, filters, graph=False, stream=None, nowait=False):
         assert FakeTorch.current[-1] is stream, "tick enqueued outside its stream's context"
-        if self.busy_left:
-            self.busy_left -= 1
+        call, self.calls = self.calls, self.calls + 1
+        if self.busy_left or call in self.busy_calls:
+            self.busy_left = max(0, self.busy_left - 1)
             return False
         # a robot's resampling seed is engine seed * 2^32 + robot id
         self.ticks.append((stream, [(f.seed & 0xFFFFFFFF, f.seed, f.tick) for f in filters]))
@@ -168,6 +177,7 @@ def lib(monkeypatch):
     monkeypatch.setattr(serve.mcl, "resample", rec.resample)
     monkeypatch.setattr(serve.mcl, "job_bytes", lambda N, K: 1000 * N + K)
     FakeTorch.current = [None]
+    FakeEvent.lag = 0
     return rec
 
 
@@ -245,6 +255,32 @@ def test_busy_tick_is_retried(lib):
     eng = serve.Engine(robots, init, n_streams=1, torch_module=FakeTorch)
     st = run(eng, [(0.0, 0), (0.0, 1)])
     assert st.busy == 2 and st.completed == 2 and st.dropped == 0
+
+
+def test_busy_retry_on_another_stream_waits_for_the_initialisation(lib):
+    """Robot 0's tick runs on stream 1; robot 1 is admitted while its tick is
+    built for stream 2, that tick is refused as busy, and once robot 0's tick
+    has completed the retry runs on stream 1: the copy stream must have waited
+    for the event recorded on stream 2 after robot 1's particle set was made,
+    and stream 1 for the copy."""
+    lib.busy_calls = {1}
+    FakeEvent.lag = 1
+    robots, init, made = make(2, lib)
+    eng = serve.Engine(robots, init, n_streams=2, max_evals_per_tick=10 * 5, torch_module=FakeTorch)
+    st = run(eng, [(0.0, 0), (0.0, 1)])
+    s1, s2, cs = eng.streams[0], eng.streams[1], eng.copy_stream
+    assert st.busy == 1 and st.completed == 2
+    assert [(t[0], t[1][0][0]) for t in lib.ticks] == [(s1, 0), (s1, 1)]
+    (rid, phase, stream_arg, ctx), = [m for m in made if m[0] == 1]
+    assert stream_arg is s2 and ctx is s2
+    ready = [e for e in s2.log if e[0] == "record"]
+    assert ready, s2.log
+    ready_serial = ready[0][1]
+    i_wait = cs.log.index(("wait_event", s2.name, ready_serial))
+    # the copy event recorded after that wait is one stream 1 waited for
+    later = [e[1] for e in cs.log[i_wait:] if e[0] == "record"]
+    assert any(("wait_event", cs.name, serial) in s1.log for serial in later)
+    assert all(r.ready is None for r in robots)
 
 
 @pytest.mark.parametrize("order", ["fifo", "stale"])
