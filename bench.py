@@ -167,6 +167,11 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
 
+def spread(xs):
+    """p10 / p50 / p90 / p99 of a list of latencies (ms)."""
+    return {f"p{q}": percentile(xs, q) for q in (10, 50, 90, 99)}
+
+
 def base_record(args, metric, value, ms_step, config, dtype="f32"):
     return {"metric": metric, "value": value, "unit": "G particle-point evals/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -276,7 +281,7 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
                                " + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
                        "workload_key": workload_key, "sensor_update_ms": sensor_ms,
                        "launch": launch, "launch_autotuned": bool(args.autotune and not trilinear and not sparse)})
-    out["latency_ms"] = {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}
+    out["latency_ms"] = spread(lat)
     if tick_lat:
         out["tick_graph_latency_ms"] = tick_lat
     out["pose_estimate"] = est
@@ -607,7 +612,7 @@ def run_batched(args):
                                    "[2048, 524288], scans alternating 16x1800 / 64x1024",
                        "filters": len(specs), "sum_N": int(sum(f.N for f in specs)), "evals_per_tick": int(evals),
                        "launch": launch, "launch_autotuned": bool(args.autotune)})
-    out["latency_ms"] = {"p50": percentile(lat_graph, 50), "p99": percentile(lat_graph, 99)}
+    out["latency_ms"] = spread(lat_graph)
     out["vs_plain"] = {"plain_sequential": {"value": evals / (ms_plain * 1e-3) / 1e9, "ms": ms_plain,
                                             "p50_ms": percentile(lat_plain, 50), "p99_ms": percentile(lat_plain, 99)},
                        "tick_eager": {"value": evals / (ms_eager * 1e-3) / 1e9, "ms": ms_eager},
@@ -714,7 +719,7 @@ def run_served(args):
                        "streams": args.streams, "depth": args.depth, "order": args.order})
     out["steps"] = sv["completed"]
     out["warmup"] = 0
-    out["latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"]}
+    out["latency_ms"] = {f"p{q}": sv[f"p{q}_ms"] for q in (10, 50, 90, 99)}
     out["served"] = sv
     out["vs_plain"] = {"plain_sequential": pl, "throughput_gain_vs_plain": sv["evals_per_s"] / max(pl["evals_per_s"], 1e-9),
                        "p99_ratio_vs_plain": sv["p99_ms"] / max(pl["p99_ms"], 1e-9)}

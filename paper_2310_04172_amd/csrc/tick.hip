@@ -393,7 +393,10 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     }
 
     auto it = S.graphs.find(key);
-    if (it == S.graphs.end() && S.graphs.size() >= 32) drop_graphs(S);  // bound the cache
+    if (it == S.graphs.end() && S.graphs.size() >= 32) {  // bound the cache, once earlier replays have ended
+        if (hipStreamSynchronize(stream) != hipSuccess) return fail(MCL_EDEVICE, "tick: synchronisation failed");
+        drop_graphs(S);
+    }
     if (it == S.graphs.end()) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;

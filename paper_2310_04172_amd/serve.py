@@ -122,7 +122,8 @@ class ServeStats:
 
     def summary(self) -> dict:
         lat = np.asarray(self.latencies_ms) if self.latencies_ms else np.zeros(1)
-        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        return {"p10_ms": float(np.percentile(lat, 10)), "p50_ms": float(np.percentile(lat, 50)),
+                "p90_ms": float(np.percentile(lat, 90)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "completed": self.completed, "arrived": self.arrived,
                 "dropped": self.dropped, "drop_rate": self.dropped / max(1, self.arrived),
                 "evals_per_s": self.evals / max(self.wall_s, 1e-9), "ticks": self.ticks, "busy": self.busy,
