@@ -48,6 +48,8 @@ def lib():
                                            P, C.c_int32, C.c_float, P, P, C.c_int32]
         L.oracle_sensor_update_trilinear.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, P, P, C.c_int32,
                                                      P, C.c_int32, C.c_float, P, P, P, C.c_int32]
+        L.oracle_sensor_update_sum.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, P, P, C.c_int32,
+                                               P, C.c_int32, C.c_float, P, P, C.c_int32]
         L.oracle_normalize.argtypes = [P, C.c_int32, P, P, P]
         L.oracle_sensor_update_bricks.argtypes = [P, C.c_float, P, C.c_float, C.c_int32, C.c_int64, P, P, P, C.c_int32,
                                                   P, C.c_int32, C.c_float, P, P, C.c_int32]
@@ -64,7 +66,7 @@ def lib():
         L.oracle_resample_draw.argtypes = [C.c_uint64, C.c_uint64]
         L.oracle_resample_draw.restype = C.c_uint64
         for f in (L.oracle_voxel_indices, L.oracle_sensor_update, L.oracle_sensor_update_trilinear,
-                  L.oracle_normalize, L.oracle_resample):
+                  L.oracle_sensor_update_sum, L.oracle_normalize, L.oracle_resample):
             f.restype = C.c_int
         _lib = L
     return _lib
@@ -106,6 +108,22 @@ def sensor_update(tmap, points: np.ndarray, poses: np.ndarray, sigma: float, nth
     ssum = np.empty(N, np.float64)
     rc = lib().oracle_sensor_update(_p(dims), tmap.voxel, _p(origin), tmap.tau, DTYPE_CODE[tmap.dtype],
                                     _p(vals), _p(pts), K, _p(ps), N, sigma, _p(logw), _p(ssum), nthreads)
+    assert rc == 0
+    return (logw, ssum) if return_sum else logw
+
+
+def sensor_update_sum(tmap, points: np.ndarray, poses: np.ndarray, sigma: float, nthreads: int = 1,
+                      return_sum: bool = False):
+    """float64 log-weights under the sum reading, l_n = log sum_k exp(-c q_k^2)
+    (and optionally the sums themselves)."""
+    dims, origin, vals = _map_args(tmap)
+    pts = np.ascontiguousarray(points, np.float32)
+    ps = np.ascontiguousarray(poses, np.float32)
+    K, N = pts.shape[1], ps.shape[1]
+    logw = np.empty(N, np.float64)
+    ssum = np.empty(N, np.float64)
+    rc = lib().oracle_sensor_update_sum(_p(dims), tmap.voxel, _p(origin), tmap.tau, DTYPE_CODE[tmap.dtype],
+                                        _p(vals), _p(pts), K, _p(ps), N, sigma, _p(logw), _p(ssum), nthreads)
     assert rc == 0
     return (logw, ssum) if return_sum else logw
 

@@ -47,6 +47,12 @@
  *    float32 maps (each square is exact in float64).  A float64 map (the
  *    unquantised distances) serves as the precision reference of the storage
  *    types.
+ *    The other reading (a mode of its own): the weight is the sum of the
+ *    points' likelihoods instead of their product, again without the constant
+ *    factor,
+ *        l_n = log sum_k exp(-(s^2 / (2 sigma^2)) q_k^2),
+ *    float64 terms added in point order; an empty scan gives l_n = 0 (no
+ *    evidence: equal weights, as the product reading gives).
  *
  *  Sparse coarse/fine map (§III, after Akai et al.: fine data only where the
  *    coarse grid holds distances inside the truncation band).  A storage form
@@ -303,6 +309,88 @@ int oracle_sensor_update(const int32_t dims[3], float voxel, const float origin[
         jobs[t].n0 = (int64_t)N * t / nthreads;
         jobs[t].n1 = (int64_t)N * (t + 1) / nthreads;
         pthread_create(&th[t], NULL, su_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(jobs);
+    free(th);
+    return 0;
+}
+
+/* ------------------------------------------- sensor update, sum reading */
+
+/* Stored value read for point k under the particle constants (a, b): the
+ * voxel's value as an exact double, or Q (tau) outside the map. */
+static double point_value(const su_job_t *J, const float a[9], const float b[3], int64_t k) {
+    const float *px = J->points, *py = J->points + J->K, *pz = J->points + 2 * J->K;
+    const int64_t v = voxel_index(a, b, px[k], py[k], pz[k], &J->g);
+    if (v < 0) return J->dtype >= ORACLE_F32 ? (double)(float)J->tau : (double)J->Q;
+    switch (J->dtype) {
+    case ORACLE_I16: return ((const int16_t *)J->values)[v];
+    case ORACLE_I8: return ((const int8_t *)J->values)[v];
+    case ORACLE_F32: return ((const float *)J->values)[v];
+    default: return ((const double *)J->values)[v];
+    }
+}
+
+static void *su_sum_worker(void *arg) {
+    su_job_t *J = (su_job_t *)arg;
+    for (int64_t n = J->n0; n < J->n1; ++n) {
+        float a[9], b[3];
+        particle_consts(J->poses, J->N, n, &J->g, a, b);
+        double S = 0.0;
+        for (int64_t k = 0; k < J->K; ++k) {
+            const double d = point_value(J, a, b, k);
+            S += exp(-J->c * (d * d));
+        }
+        if (J->ssum) J->ssum[n] = S;
+        J->logw[n] = J->K == 0 ? 0.0 : log(S);
+    }
+    return NULL;
+}
+
+/*
+ * l_n under the sum reading (see the header comment) on a dense map.  ssum
+ * may be NULL; else it receives sum_k exp(-c q_k^2).  nthreads as for
+ * oracle_sensor_update.
+ */
+int oracle_sensor_update_sum(const int32_t dims[3], float voxel, const float origin[3], float tau, int32_t dtype,
+                             const void *values, const float *points, int32_t K, const float *poses, int32_t N,
+                             float sigma, double *logw, double *ssum, int32_t nthreads) {
+    if (K < 0 || N < 0 || dtype < 0 || dtype > 3 || !(sigma > 0.0f)) return -1;
+    su_job_t base;
+    memset(&base, 0, sizeof base);
+    base.g = make_grid(dims, voxel, origin);
+    base.dtype = dtype;
+    base.values = values;
+    base.tau = (double)tau;
+    base.Q = dtype == ORACLE_I16 ? 32767 : dtype == ORACLE_I8 ? 127 : 1;
+    base.points = points;
+    base.K = K;
+    base.poses = poses;
+    base.N = N;
+    const double sc = dtype >= ORACLE_F32 ? 1.0 : (double)tau / (double)base.Q, sg = (double)sigma;
+    base.c = (sc * sc) / (2.0 * sg * sg);
+    base.logw = logw;
+    base.ssum = ssum;
+    if (nthreads > N) nthreads = (int32_t)N;
+    if (nthreads <= 1) {
+        base.n0 = 0;
+        base.n1 = N;
+        su_sum_worker(&base);
+        return 0;
+    }
+    su_job_t *jobs = (su_job_t *)malloc(sizeof(su_job_t) * (size_t)nthreads);
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    if (!jobs || !th) {
+        free(jobs);
+        free(th);
+        return -2;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = base;
+        jobs[t].n0 = (int64_t)N * t / nthreads;
+        jobs[t].n1 = (int64_t)N * (t + 1) / nthreads;
+        pthread_create(&th[t], NULL, su_sum_worker, &jobs[t]);
     }
     for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
     free(jobs);
