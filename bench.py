@@ -180,10 +180,11 @@ def base_record(args, metric, value, ms_step, config, dtype="f32"):
             "config": config}
 
 
-def run_single(args, w, workload_key, with_roofline=True, trilinear=False, sparse=False):
+def run_single(args, w, workload_key, with_roofline=True, trilinear=False, sparse=False, score_sum=False):
     """A plain single-filter update: sensor update + normalise + resample, timed.
     trilinear: the sensor update reads the map by trilinear interpolation;
-    sparse: the map is held as a coarse table + pool of band bricks."""
+    sparse: the map is held as a coarse table + pool of band bricks;
+    score_sum: the sum reading of the sensor model (mcl_sensor_update_sum)."""
     import torch
     from paper_2310_04172_amd import mcl
 
@@ -222,6 +223,8 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
             a.record(stream)
         if trilinear:
             mcl.sensor_update_trilinear(m, pts, poses, w.sigma, logw, stream)
+        elif score_sum:
+            mcl.sensor_update_sum(m, pts, poses, w.sigma, logw, stream)
         else:
             mcl.sensor_update(m, pts, poses, w.sigma, logw, stream)
         if timed:
@@ -277,7 +280,8 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
     out = base_record(args, METRIC,
                       evals / (ms_step * 1e-3) / 1e9, ms_step,
                       {"workload": w.name, "N": N, "K": K, "map_dtype": w.tmap.dtype,
-                       "step": ("sensor update (trilinear lookup)" if trilinear else "sensor update") +
+                       "step": ("sensor update (trilinear lookup)" if trilinear else
+                                "sensor update (sum reading)" if score_sum else "sensor update") +
                                " + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
                        "workload_key": workload_key, "sensor_update_ms": sensor_ms,
                        "launch": launch, "launch_autotuned": bool(args.autotune and not trilinear and not sparse)})
@@ -732,7 +736,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="global", choices=["global", "converged", "small", "batched", "served", "precision", "estimate", "trilinear", "loop",
-                                                    "sparse"])
+                                                    "sparse", "sum"])
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -774,11 +778,12 @@ def main():
              configs.config2_converged() if args.workload == "converged" else configs.config2())
         log(f"workload built in {time.perf_counter() - t0:.1f} s: N={w.N} K={w.K}")
         out = run_single(args, w, args.workload, trilinear=args.workload == "trilinear",
-                         sparse=args.workload == "sparse")
-        if args.workload in ("trilinear", "sparse", "converged"):
+                         sparse=args.workload == "sparse", score_sum=args.workload == "sum")
+        if args.workload in ("trilinear", "sparse", "converged", "sum"):
             out["metric"] = METRIC + {"trilinear": " [trilinear lookup]", "sparse": " [sparse map]",
-                                      "converged": " [particles converged]"}[args.workload]
-        if not args.no_cpu_baseline and args.workload not in ("trilinear", "sparse", "converged"):
+                                      "converged": " [particles converged]",
+                                      "sum": " [sum reading of the sensor model]"}[args.workload]
+        if not args.no_cpu_baseline and args.workload not in ("trilinear", "sparse", "converged", "sum"):
             out["cpu_baseline"] = cpu_baseline(w)
         if args.workload == "global" and not args.no_headline:
             out.update(headline_comparisons(args))

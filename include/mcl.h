@@ -132,6 +132,23 @@ size_t mcl_map_bytes(mcl_map map);
 mcl_status mcl_sensor_update(mcl_map map, const float *points, int32_t K, const float *poses,
                              int32_t N, float sigma, float *logw, void *stream);
 
+/* Sensor update with the sum reading of the same model (§III, Eq. 3: the
+ * paper does not say how the points' likelihoods combine; this entry point
+ * takes their sum instead of their product).  For every particle n:
+ *     logw[n] = log sum_k exp(-(1 / (2 sigma^2)) * m(x_n, z_k)^2),
+ * the log of the sum of Eq. (3) over the scan without its constant factor;
+ * logw[n] = 0 when K = 0 (no evidence: equal weights, as mcl_sensor_update
+ * gives).  Lookup and voxel recipe as for mcl_sensor_update.  Each likelihood
+ * is computed in float32 as 2^(k2 q^2) with k2 = -c log2(e) (c the score
+ * constant of mcl_sensor_update) by the hardware base-2 exponential, and the
+ * likelihoods are summed in float32 in the order of mcl_sensor_update; the
+ * absolute error of logw[n] stays below
+ *     2.2e-6 + 1.8e-7 * tau^2 / (2 sigma^2) + 1.8e-7 * |logw[n]|.
+ * Dense maps only, and sigma >= tau / 8, so that no likelihood underflows
+ * (MCL_EINVAL otherwise).  Other arguments and errors as for mcl_sensor_update. */
+mcl_status mcl_sensor_update_sum(mcl_map map, const float *points, int32_t K, const float *poses,
+                                 int32_t N, float sigma, float *logw, void *stream);
+
 /* The sensor update for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Results are bit for bit those of mcl_sensor_update (same kernels).  Instead
@@ -281,7 +298,8 @@ mcl_status mcl_init_uniform(mcl_map map, float *poses, int32_t N, float max_tilt
  * mcl_pose_estimate on the normalised weights and the input poses, then
  * mcl_resample: each stage is one launch over all filters together (the
  * sensor update one launch per storage type and lookup: nearest on dense
- * maps, nearest on sparse maps, trilinear on dense maps), and every filter's
+ * maps, nearest on sparse maps, trilinear on dense maps, nearest on dense maps
+ * with the sum reading), and every filter's
  * results are bit for bit those of the single-filter calls (the trilinear
  * lookup's corner cells are built on the map's first trilinear use, as by
  * mcl_sensor_update_trilinear).  Sparse maps are accepted when their blocks
@@ -310,10 +328,15 @@ typedef struct {
     int32_t lookup;         /* MCL_LOOKUP_NEAREST (as mcl_sensor_update) or
                                MCL_LOOKUP_TRILINEAR (as mcl_sensor_update_trilinear,
                                dense maps only)                                   */
+    int32_t score;          /* MCL_SCORE_PRODUCT (0: as mcl_sensor_update) or
+                               MCL_SCORE_SUM (as mcl_sensor_update_sum: dense maps,
+                               nearest lookup, sigma >= tau / 8)                  */
 } mcl_filter_job;
 
 #define MCL_LOOKUP_NEAREST 0
 #define MCL_LOOKUP_TRILINEAR 1
+#define MCL_SCORE_PRODUCT 0
+#define MCL_SCORE_SUM 1
 
 /* Flag for mcl_tick: the launch chain is captured into a HIP graph the first
  * time (per stream and per mix of storage types and lookups) and replayed afterwards;

@@ -12,6 +12,7 @@ mcl_status launch_sensor(const mcl_map_s *, const float *, int, const float *, i
                          float *);
 mcl_status launch_sensor_trilinear(mcl_map_s *, const float *, int, const float *, int, float, float *,
                                    hipStream_t);
+mcl_status launch_sensor_sum(const mcl_map_s *, const float *, int, const float *, int, float, float *, hipStream_t);
 mcl_status launch_debug_indices(const mcl_map_s *, const float *, int, const float *, int, int64_t *, hipStream_t);
 mcl_status launch_normalize(const float *, int, double *, uint64_t *, double *, hipStream_t);
 mcl_status launch_resample(const uint64_t *, int, uint64_t, int32_t *, const float *, float *, hipStream_t);
@@ -107,6 +108,17 @@ extern "C" mcl_status mcl_sensor_update_trilinear(mcl_map map, const float *poin
     mcl_status st = sensor_args("sensor_update_trilinear", map, points, K, poses, N, sigma, logw, &c);
     if (st != MCL_OK) return st;
     st = launch_sensor_trilinear(map, points, K, poses, N, c, logw, static_cast<hipStream_t>(stream));
+    return st == MCL_OK ? note_map_use(map, static_cast<hipStream_t>(stream)) : st;
+}
+
+extern "C" mcl_status mcl_sensor_update_sum(mcl_map map, const float *points, int32_t K, const float *poses,
+                                            int32_t N, float sigma, float *logw, void *stream) {
+    float c = 0.0f;
+    mcl_status st = sensor_args("sensor_update_sum", map, points, K, poses, N, sigma, logw, &c);
+    if (st != MCL_OK) return st;
+    if (map->sparse) return fail(MCL_EINVAL, "sensor_update_sum: the sum reading needs a dense map");
+    if (!sum_sigma_ok(map, sigma)) return fail(MCL_EINVAL, "sensor_update_sum: the sum reading needs sigma >= tau / 8");
+    st = launch_sensor_sum(map, points, K, poses, N, sum_k2(map, sigma), logw, static_cast<hipStream_t>(stream));
     return st == MCL_OK ? note_map_use(map, static_cast<hipStream_t>(stream)) : st;
 }
 

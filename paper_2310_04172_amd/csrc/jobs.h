@@ -46,8 +46,25 @@ struct SensorJob {
     int32_t coarse;       // where the nearest lookup reads the coarse level (kCoarse*)
     int32_t nsub;         // runs per group (work items per (group, piece) pair)
     int32_t lds8;         // auto coarse level: LDS when over lds8 / 8 of the probe lookups read in place
+    int32_t score;        // kScoreProduct or kScoreSum (how the points' likelihoods combine)
+    float k2;             // sum reading: -c log2(e), so a point's likelihood is 2^(k2 q^2)
     int32_t pad_;
 };
+
+// How a particle's points combine: the product of their likelihoods (l = -c sum q^2)
+// or their sum (l = log sum exp(-c q^2)).
+constexpr int32_t kScoreProduct = 0, kScoreSum = 1;
+
+// Sum reading, host side: a point's likelihood exp(-c q^2) is 2^(k2 q^2) with
+// k2 = -c log2(e).  The smallest likelihood, at q = Q (tau for float32 maps),
+// is exp(-tau^2 / (2 sigma^2)); sigma >= tau / 8 keeps it at or above e^-32, a
+// normal float, so no term underflows.
+inline double score_c(const mcl_map_s *m, float sigma) {
+    const double s = m->scale, sg = (double)sigma;
+    return (s * s) / (2.0 * sg * sg);
+}
+inline bool sum_sigma_ok(const mcl_map_s *m, float sigma) { return 8.0 * (double)sigma >= (double)m->tau; }
+inline float sum_k2(const mcl_map_s *m, float sigma) { return (float)(-score_c(m, sigma) * 1.4426950408889634); }
 
 // Coarse level of the nearest lookup: chosen per wave and chunk (auto), or
 // forced to the mask bytes in global memory or the bits in LDS.  Results are

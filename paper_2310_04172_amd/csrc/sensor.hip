@@ -71,6 +71,30 @@ __device__ inline float as_value(int raw) {
 template <typename T>
 constexpr int class_shift() { return kBrickLog2 + (sizeof(T) == 1 ? 0 : sizeof(T) == 2 ? 1 : 2); }
 
+// A lane's partial score over its kU values, in point order.  Product reading:
+// sum q^2 (one fused multiply-add per point).  Sum reading: sum 2^(k2 q^2), the
+// points' likelihoods exp(-c q^2) by the hardware base-2 exponential (k2 q^2
+// lies in [k2 Q^2, 0], which the library keeps above -47, so every term is a
+// normal float); padding slots of a ragged chunk read 0 and add nothing in
+// either reading.
+template <bool TAIL, bool SUM, typename T>
+__device__ __attribute__((always_inline)) inline float lane_score(const int (&raw)[kU], int lane, int nvalid,
+                                                                  float k2) {
+    float s = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        float f = as_value<T>(raw[u]);
+        if constexpr (SUM) {
+            float e = __builtin_amdgcn_exp2f((f * f) * k2);
+            if (TAIL) e = (u * kWave + lane < nvalid) ? e : 0.0f;
+            s = s + e;
+        } else {
+            s = __builtin_fmaf(f, f, s);
+        }
+    }
+    return s;
+}
+
 // Lane partial sum of one particle (pose in A) over this lane's kU points.
 // Coarse level first: the read mask of each point's brick (a signed byte in
 // global memory): a brick wholly at +-Q reads offset 0, the +Q sentinel, so
@@ -78,10 +102,10 @@ constexpr int class_shift() { return kBrickLog2 + (sizeof(T) == 1 ? 0 : sizeof(T
 // value; a gather then touches one shared line for all the others, needs no
 // branches, and all kU gathers stay in flight.  Padding lanes point at the
 // zero sentinel brick, which is read in place.
-template <typename T, bool TAIL>
+template <typename T, bool TAIL, bool SUM>
 __device__ __attribute__((always_inline)) inline float lane_chunk_sum(const MapView &m, const float (&A)[12], const float (&px)[kU],
                                        const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
-                                       bool count = false, int *nmixed = nullptr) {
+                                       float k2, bool count = false, int *nmixed = nullptr) {
     uint32_t off[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -107,24 +131,18 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum(const MapV
         for (int u = 0; u < kU; ++u) c += __builtin_popcountll(__ballot(msk[u] != 0));
         *nmixed += c;
     }
-    float s = 0.0f;
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        float f = as_value<T>(raw[u]);
-        s = __builtin_fmaf(f, f, s);
-    }
-    return s;
+    return lane_score<TAIL, SUM, T>(raw, lane, nvalid, k2);
 }
 
 // The same lookup with the coarse level read from LDS: the workgroup holds the
 // map's read masks as bits, so a point costs one global gather instead of two
 // (and three more instructions).  The bit of slot b sign-extended is the mask
 // (0 or -1).  All 16 LDS reads are issued before the first gather.
-template <typename T, bool TAIL>
+template <typename T, bool TAIL, bool SUM>
 __device__ __attribute__((always_inline)) inline float lane_chunk_sum_lds(const MapView &m, const uint32_t *sbits,
                                                                           const float (&A)[12], const float (&px)[kU],
                                                                           const float (&py)[kU], const float (&pz)[kU],
-                                                                          int lane, int nvalid) {
+                                                                          int lane, int nvalid, float k2) {
     uint32_t off[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -147,13 +165,7 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_lds(const 
         raw[u] = load_raw<T>(m.base, off[u] & (uint32_t)mk);
     }
     __builtin_amdgcn_sched_barrier(0);
-    float s = 0.0f;
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        float f = as_value<T>(raw[u]);
-        s = __builtin_fmaf(f, f, s);
-    }
-    return s;
+    return lane_score<TAIL, SUM, T>(raw, lane, nvalid, k2);
 }
 
 // Trilinear lookup (§III: a pseudo-continuous map value by interpolation): one
@@ -348,11 +360,12 @@ constexpr int kLookNearest = 0, kLookTrilinear = 1, kLookSparse = 2, kLookSparse
 // Particles [p0, p1) of the wave's group against one chunk, with lookup LK
 // (kLookNearestLds here: the coarse level read from LDS).  probe: count the
 // in-place reads of the nearest lookup into *nmixed (wave-uniform).
-template <typename T, bool TAIL, int LK>
+template <typename T, bool TAIL, int LK, bool SUM>
 __device__ __attribute__((always_inline)) inline void chunk_range(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
                                    int p0, int p1, float &acc, const uint32_t *sbits, bool probe = false,
                                    int *nmixed = nullptr) {
+    static_assert(!SUM || LK == kLookNearest || LK == kLookNearestLds, "the sum reading has the nearest lookup only");
     for (int p = p0; p < p1; ++p) {
         float A[12];
 #pragma unroll
@@ -363,9 +376,9 @@ __device__ __attribute__((always_inline)) inline void chunk_range(const SensorJo
         else if constexpr (LK == kLookSparse || LK == kLookSparseWide)
             t = wave_sum(lane_chunk_sum_sparse<T, TAIL, LK == kLookSparseWide>(J.map, J.sp, A, px, py, pz, lane, nvalid));
         else if constexpr (LK == kLookNearestLds)
-            t = wave_sum(lane_chunk_sum_lds<T, TAIL>(J.map, sbits, A, px, py, pz, lane, nvalid));
+            t = wave_sum(lane_chunk_sum_lds<T, TAIL, SUM>(J.map, sbits, A, px, py, pz, lane, nvalid, J.k2));
         else
-            t = wave_sum(lane_chunk_sum<T, TAIL>(J.map, A, px, py, pz, lane, nvalid, probe, nmixed));
+            t = wave_sum(lane_chunk_sum<T, TAIL, SUM>(J.map, A, px, py, pz, lane, nvalid, J.k2, probe, nmixed));
         if (lane == p) acc += t;
     }
 }
@@ -378,7 +391,7 @@ __device__ __attribute__((always_inline)) inline void chunk_range(const SensorJo
 // most points land in the band, and LDS saves a gather per point), else stay
 // on the global masks (global localisation: most points read the shared
 // sentinel line, and the global path issues fewer instructions).
-template <typename T, bool TAIL, int LK>
+template <typename T, bool TAIL, int LK, bool SUM>
 __device__ __attribute__((always_inline)) inline void chunk_group(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
                                    int p0, int p1, float &acc, const uint32_t *sbits) {
@@ -388,15 +401,15 @@ __device__ __attribute__((always_inline)) inline void chunk_group(const SensorJo
         if (J.coarse == kCoarseAuto) {
             int nmixed = 0;
             q0 = min(p0 + kProbe, p1);
-            chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, p0, q0, acc, sbits, true, &nmixed);
+            chunk_range<T, TAIL, kLookNearest, SUM>(J, pa, px, py, pz, lane, nvalid, p0, q0, acc, sbits, true, &nmixed);
             lds = nmixed * 8 > J.lds8 * kChunk * (q0 - p0);
         }
         if (lds)
-            chunk_range<T, TAIL, kLookNearestLds>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
+            chunk_range<T, TAIL, kLookNearestLds, SUM>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
         else
-            chunk_range<T, TAIL, kLookNearest>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
+            chunk_range<T, TAIL, kLookNearest, SUM>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
     } else {
-        chunk_range<T, TAIL, LK>(J, pa, px, py, pz, lane, nvalid, p0, p1, acc, sbits);
+        chunk_range<T, TAIL, LK, SUM>(J, pa, px, py, pz, lane, nvalid, p0, p1, acc, sbits);
     }
 }
 
@@ -419,7 +432,7 @@ __device__ __attribute__((always_inline)) inline ItemPos item_pos(const SensorJo
 
 // One work item: particles 64 g + [p0, p1) of a job against points
 // [4096 piece, 4096 piece + 4096).  Returns lane p's sum for particle 64 g + p.
-template <typename T, int LK>
+template <typename T, int LK, bool SUM>
 __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJob &J, int local, int lane,
                                                                    const uint32_t *sbits) {
     const ItemPos ip = item_pos(J, local);
@@ -446,20 +459,29 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
             pz[u] = gp(J.pts)[(size_t)2 * K + k];
         }
         if (nvalid == kChunk)
-            chunk_group<T, false, LK>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits);
+            chunk_group<T, false, LK, SUM>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits);
         else
-            chunk_group<T, true, LK>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits);
+            chunk_group<T, true, LK, SUM>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits);
     }
     return acc;
 }
 
+// A particle's log-weight from its total: -(S c) for the product reading,
+// log S for the sum reading (0 for an empty scan: no evidence, equal weights).
+template <bool SUM>
+__device__ __attribute__((always_inline)) inline float particle_logw(const SensorJob &J, float S) {
+    if constexpr (SUM) return J.K > 0 ? logf(S) : 0.0f;
+    else return -(S * J.c);
+}
+
 // Output of a work item: l directly (one piece) or the piece's partial sums.
+template <bool SUM>
 __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJob &J, int local, int lane,
                                                                    float acc) {
     const ItemPos ip = item_pos(J, local);
     if (lane >= ip.p0 && lane < ip.p1) {
         if (J.npiece == 1)
-            J.logw[ip.n0 + lane] = -(acc * J.c);
+            J.logw[ip.n0 + lane] = particle_logw<SUM>(J, acc);
         else
             J.part[(size_t)ip.piece * J.N + ip.n0 + lane] = acc;
     }
@@ -469,7 +491,7 @@ __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJ
 // wave for a full grid, several for a persistent one).  The job descriptor is
 // read into scalar registers per item and read again for the store, so it need
 // not stay live across the item.
-template <typename T, int WPB, typename Src, int LK = kLookNearest>
+template <typename T, int WPB, typename Src, int LK = kLookNearest, bool SUM = false>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == kLookTrilinear ? 2 : (LK == kLookNearest || LK == kLookNearestLds || LK == kLookSparse) ? 4 : 3))) void sensor_kernel(Src src) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nitems = src.items();
@@ -503,15 +525,16 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == 
         {
             const SensorJob J = src.load(j);
             local = (int)(item - J.item0);
-            acc = sensor_item<T, LK>(J, local, lane, sbits);
+            acc = sensor_item<T, LK, SUM>(J, local, lane, sbits);
         }
         const SensorJob J = src.load(j);
-        sensor_store(J, local, lane, acc);
+        sensor_store<SUM>(J, local, lane, acc);
     }
 }
 
 // Pairwise sum of the piece partials in a fixed tree (a binary counter over the
-// pieces in order), then l = -(S * c).  Jobs with one piece are done already.
+// pieces in order), then l = -(S * c) (or log S, sum reading).  Jobs with one
+// piece are done already.
 template <typename Src>
 __global__ __launch_bounds__(256) void combine_kernel(Src src) {
     const int64_t nelems = src.elems();
@@ -529,7 +552,7 @@ __global__ __launch_bounds__(256) void combine_kernel(Src src) {
         }
         float s = stack[--depth];
         while (depth > 0) s = stack[--depth] + s;
-        J.logw[n] = -(s * J.c);
+        J.logw[n] = J.score == kScoreSum ? particle_logw<true>(J, s) : particle_logw<false>(J, s);
     }
 }
 
@@ -570,32 +593,40 @@ int device_cus() {
 
 // nitems: the item count when known on the host (sizes a one-wave-per-item
 // grid); a persistent grid does not need it.
-template <typename T, typename Src, int LK = kLookNearest>
+template <typename T, typename Src, int LK = kLookNearest, bool SUM = false>
 static void launch_sensor_t(const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream, size_t lds = 0) {
     const int wpb = cfg.waves_per_block;
     int64_t blocks = (nitems + wpb - 1) / wpb;
     if (cfg.blocks_per_cu > 0) blocks = std::min<int64_t>(blocks, (int64_t)device_cus() * cfg.blocks_per_cu);
     if (blocks < 1) blocks = 1;
     switch (wpb) {
-        case 2: sensor_kernel<T, 2, Src, LK><<<(unsigned)blocks, 128, lds, stream>>>(src); break;
-        case 8: sensor_kernel<T, 8, Src, LK><<<(unsigned)blocks, 512, lds, stream>>>(src); break;
-        default: sensor_kernel<T, 4, Src, LK><<<(unsigned)blocks, 256, lds, stream>>>(src); break;
+        case 2: sensor_kernel<T, 2, Src, LK, SUM><<<(unsigned)blocks, 128, lds, stream>>>(src); break;
+        case 8: sensor_kernel<T, 8, Src, LK, SUM><<<(unsigned)blocks, 512, lds, stream>>>(src); break;
+        default: sensor_kernel<T, 4, Src, LK, SUM><<<(unsigned)blocks, 256, lds, stream>>>(src); break;
     }
+}
+
+template <typename Src, bool SUM>
+static void launch_sensor_dense(int32_t dtype, const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream,
+                                size_t lds) {
+    if (lds > 0) {
+        if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearestLds, SUM>(src, nitems, cfg, stream, lds);
+        else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearestLds, SUM>(src, nitems, cfg, stream, lds);
+        else launch_sensor_t<float, Src, kLookNearestLds, SUM>(src, nitems, cfg, stream, lds);
+    } else if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearest, SUM>(src, nitems, cfg, stream);
+    else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearest, SUM>(src, nitems, cfg, stream);
+    else launch_sensor_t<float, Src, kLookNearest, SUM>(src, nitems, cfg, stream);
 }
 
 // lds > 0: every job of the launch reads the same dense map, whose read bits
 // (nrwords * 4 <= lds bytes) each workgroup copies into LDS; the coarse level
-// is then chosen per wave (the jobs' `coarse` field).
+// is then chosen per wave (the jobs' `coarse` field).  sum: the jobs take the
+// sum reading (kScoreSum), else the product reading.
 template <typename Src>
 mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int64_t nelems, bool combine,
-                             LaunchCfg cfg, hipStream_t stream, size_t lds) {
-    if (lds > 0) {
-        if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
-        else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
-        else launch_sensor_t<float, Src, kLookNearestLds>(src, nitems, cfg, stream, lds);
-    } else if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t>(src, nitems, cfg, stream);
-    else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t>(src, nitems, cfg, stream);
-    else launch_sensor_t<float>(src, nitems, cfg, stream);
+                             LaunchCfg cfg, hipStream_t stream, size_t lds, bool sum) {
+    if (sum) launch_sensor_dense<Src, true>(dtype, src, nitems, cfg, stream, lds);
+    else launch_sensor_dense<Src, false>(dtype, src, nitems, cfg, stream, lds);
     mcl_status st = check_launch("sensor_kernel");
     if (st != MCL_OK || !combine) return st;
     int64_t blocks = std::min<int64_t>((nelems + 255) / 256, (int64_t)device_cus() * 16);
@@ -604,7 +635,7 @@ mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int6
 }
 
 template mcl_status launch_sensor_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t, int64_t,
-                                                           bool, LaunchCfg, hipStream_t, size_t);
+                                                           bool, LaunchCfg, hipStream_t, size_t, bool);
 
 // Sparse maps with pools below 4 GiB (the offset table holds byte offsets):
 // one wave per work item, four waves per workgroup, as for a single call.
@@ -644,7 +675,7 @@ mcl_status launch_sensor_tri_src(int32_t dtype, const Src &src, int64_t nitems, 
 template mcl_status launch_sensor_tri_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t,
                                                                int64_t, bool, hipStream_t);
 template mcl_status launch_sensor_src<OneJob<SensorJob>>(int32_t, const OneJob<SensorJob> &, int64_t, int64_t,
-                                                         bool, LaunchCfg, hipStream_t, size_t);
+                                                         bool, LaunchCfg, hipStream_t, size_t, bool);
 
 SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
                           float *logw, float *part) {
@@ -662,6 +693,8 @@ SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const f
     J.ngroups = (N + kGroup - 1) / kGroup;
     J.nsub = sensor_runs((int64_t)J.ngroups * J.npiece);
     J.lds8 = kLdsEighths;
+    J.score = kScoreProduct;
+    J.k2 = 0.0f;
     return J;
 }
 
@@ -673,11 +706,15 @@ void apply_cfg(SensorJob &J, const LaunchCfg &cfg) {
 }
 
 // part: the piece partials [npiece][N] (npiece > 1), or null for the stream's
-// workspace.
-mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
-                             float *logw, LaunchCfg cfg, hipStream_t stream, float *part) {
+// workspace.  score / k2: the reading (kScoreSum needs a dense map; k2 = -c log2 e).
+static mcl_status launch_sensor_job(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
+                                    float *logw, LaunchCfg cfg, hipStream_t stream, float *part, int32_t score,
+                                    float k2) {
+    const bool sum = score == kScoreSum;
+    if (sum && map->sparse) return fail(MCL_EINVAL, "sensor update: the sum reading needs a dense map");
     if (K == 0) {
-        fill_kernel<<<(N + 255) / 256, 256, 0, stream>>>(logw, N, -(0.0f * c));
+        // no points: l = 0 for every particle in either reading
+        fill_kernel<<<(N + 255) / 256, 256, 0, stream>>>(logw, N, sum ? 0.0f : -(0.0f * c));
         return check_launch("fill_kernel");
     }
     const int npiece = sensor_pieces(K);
@@ -689,15 +726,17 @@ mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, cons
     }
     using Src = OneJob<SensorJob>;
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
+    src.job.score = score;
+    src.job.k2 = k2;
     if (!map->sparse) apply_cfg(src.job, cfg);
     const int64_t nitems = (int64_t)src.job.ngroups * npiece * src.job.nsub;
     src.n = Counts{1, nitems, N, 0};
     const size_t lds_bytes = (((size_t)map->view.nrwords + 3) & ~(size_t)3) * 4;  // 16-byte pieces
     if (!map->sparse && lds_bytes <= kMaxLdsBits && cfg.coarse != kCoarseBytes) {
         src.job.coarse = cfg.coarse;
-        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, lds_bytes);
+        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, lds_bytes, sum);
     }
-    if (!map->sparse) return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, 0);
+    if (!map->sparse) return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, 0, sum);
     // sparse map: one wave per work item, four waves per workgroup
     const unsigned blocks = (unsigned)((nitems + 3) / 4);
     if (map->sp.small) {
@@ -748,9 +787,21 @@ mcl_status launch_sensor_trilinear(mcl_map_s *map, const float *pts, int K, cons
     return check_launch("combine_kernel");
 }
 
+mcl_status launch_sensor_cfg(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
+                             float *logw, LaunchCfg cfg, hipStream_t stream, float *part) {
+    return launch_sensor_job(map, pts, K, poses, N, c, logw, cfg, stream, part, kScoreProduct, 0.0f);
+}
+
 mcl_status launch_sensor(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
                          float *logw, hipStream_t stream, float *part) {
     return launch_sensor_cfg(map, pts, K, poses, N, c, logw, tuned_config(map->dtype, K, N), stream, part);
+}
+
+// Sum reading, launched as the product reading's tuned shape for (dtype, K, N).
+mcl_status launch_sensor_sum(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float k2,
+                             float *logw, hipStream_t stream) {
+    return launch_sensor_job(map, pts, K, poses, N, 0.0f, logw, tuned_config(map->dtype, K, N), stream, nullptr,
+                             kScoreSum, k2);
 }
 
 mcl_status launch_debug_indices(const mcl_map_s *map, const float *pts, int K, const float *poses, int N,

@@ -19,7 +19,7 @@ namespace mcl {
 SensorJob make_sensor_job(const mcl_map_s *, const float *, int, const float *, int, float, float *, float *);
 void apply_cfg(SensorJob &, const LaunchCfg &);
 template <typename Src>
-mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t, size_t);
+mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t, size_t, bool);
 template <typename Src>
 mcl_status launch_sensor_sparse_src(int32_t, const Src &, int64_t, int64_t, bool, hipStream_t);
 template <typename Src>
@@ -35,15 +35,19 @@ void bind_weight_ws(WeightJob &J, void *ws);
 
 constexpr int kMaxJobs = MCL_MAX_JOBS;
 // Sensor groups: storage type (0..2) + 3 x kind, the kind being the nearest
-// lookup on a dense map (0), on a sparse map (1) or the trilinear lookup on a
-// dense map (2); each group present gets one sensor launch.
+// lookup on a dense map (0), on a sparse map (1), the trilinear lookup on a
+// dense map (2) or the nearest lookup on a dense map with the sum reading (3);
+// each group present gets one sensor launch.
 constexpr int kTypes = 3;
-constexpr int kKindDense = 0, kKindSparse = 1, kKindTri = 2;
-constexpr int kGroups = 3 * kTypes;
+constexpr int kKindDense = 0, kKindSparse = 1, kKindTri = 2, kKindDenseSum = 3;
+constexpr int kGroups = 4 * kTypes;
 
 inline int job_kind(const mcl_filter_job &F) {
-    return F.map->sparse ? kKindSparse : F.lookup == MCL_LOOKUP_TRILINEAR ? kKindTri : kKindDense;
+    if (F.map->sparse) return kKindSparse;
+    if (F.lookup == MCL_LOOKUP_TRILINEAR) return kKindTri;
+    return F.score == MCL_SCORE_SUM ? kKindDenseSum : kKindDense;
 }
+inline bool dense_nearest(int kind) { return kind == kKindDense || kind == kKindDenseSum; }
 inline int job_group(const mcl_filter_job &F) { return F.map->dtype + kTypes * job_kind(F); }
 
 static constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -129,6 +133,13 @@ mcl_status check_job(const mcl_filter_job &J, int j) {
         return fail(MCL_EINVAL, at + "lookup must be MCL_LOOKUP_NEAREST or MCL_LOOKUP_TRILINEAR");
     if (J.lookup == MCL_LOOKUP_TRILINEAR && J.map->sparse)
         return fail(MCL_EINVAL, at + "the trilinear lookup needs a dense map");
+    if (J.score != MCL_SCORE_PRODUCT && J.score != MCL_SCORE_SUM)
+        return fail(MCL_EINVAL, at + "score must be MCL_SCORE_PRODUCT or MCL_SCORE_SUM");
+    if (J.score == MCL_SCORE_SUM) {
+        if (J.map->sparse || J.lookup != MCL_LOOKUP_NEAREST)
+            return fail(MCL_EINVAL, at + "the sum reading needs a dense map and the nearest lookup");
+        if (!sum_sigma_ok(J.map, J.sigma)) return fail(MCL_EINVAL, at + "the sum reading needs sigma >= tau / 8");
+    }
     return MCL_OK;
 }
 
@@ -223,7 +234,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     LaunchCfg cfgs[kGroups];
     for (int g = 0; g < kGroups; ++g) {
         cfgs[g] = kDefaultCfg;
-        if (g / kTypes != kKindDense || g_begin[g + 1] == g_begin[g]) continue;
+        if (!dense_nearest(g / kTypes) || g_begin[g + 1] == g_begin[g]) continue;
         int big = order[g_begin[g]];
         for (int t = g_begin[g] + 1; t < g_begin[g + 1]; ++t) {
             const int j = order[t];
@@ -270,6 +281,10 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             SensorJob &J = stbl[s];
             J = make_sensor_job(m, F.points, F.K, F.poses, F.N, c, F.logw, part);
             if (job_kind(F) == kKindTri) J.tri = m->tri;
+            if (job_kind(F) == kKindDenseSum) {
+                J.score = kScoreSum;
+                J.k2 = sum_k2(m, F.sigma);
+            }
             J.coarse = cfgs[g].coarse;
             J.item0 = items;
             J.elem0 = elems;
@@ -337,8 +352,8 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     // A dense group whose jobs all read one map with a small enough bit table
     // gets the kernel that holds those bits in LDS (a power of two bytes, so a
     // graph serves any such map up to that size).
-    for (int g = 0; g < kTypes; ++g) {
-        if (g_begin[g + 1] == g_begin[g] || cfgs[g].coarse == kCoarseBytes) continue;
+    for (int g = 0; g < kGroups; ++g) {
+        if (!dense_nearest(g / kTypes) || g_begin[g + 1] == g_begin[g] || cfgs[g].coarse == kCoarseBytes) continue;
         const mcl_map_s *m0 = jobs[order[g_begin[g]]].map;
         bool shared = true;
         for (int s = g_begin[g] + 1; s < g_begin[g + 1] && shared; ++s) shared = jobs[order[s]].map == m0;
@@ -359,8 +374,8 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             const int type = g % kTypes, kind = g / kTypes;
             const bool comb = use_graph || combine[g];
             mcl_status st =
-                kind == kKindDense  ? launch_sensor_src(type, src, key.items[g], key.elems, comb, cfgs[g], stream,
-                                                        (size_t)key.lds[g])
+                dense_nearest(kind) ? launch_sensor_src(type, src, key.items[g], key.elems, comb, cfgs[g], stream,
+                                                        (size_t)key.lds[g], kind == kKindDenseSum)
                 : kind == kKindSparse ? launch_sensor_sparse_src(type, src, key.items[g], key.elems, comb, stream)
                                       : launch_sensor_tri_src(type, src, key.items[g], key.elems, comb, stream);
             if (st != MCL_OK) return st;

@@ -31,6 +31,7 @@ MCL_OK, MCL_EINVAL, MCL_ENOMEM, MCL_EDEVICE, MCL_ERANGE, MCL_EBUSY = 0, -1, -2, 
 MAX_JOBS = 4096
 TICK_GRAPH, TICK_NOWAIT = 1, 2
 LOOKUP_NEAREST, LOOKUP_TRILINEAR = 0, 1
+SCORE_PRODUCT, SCORE_SUM = 0, 1
 MAX_PARTICLES = 1 << 21
 MAX_POINTS = 1 << 20
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -48,7 +49,7 @@ class FilterJob(C.Structure):
                 ("sigma", C.c_float), ("logw", _P), ("w", _P), ("wq", _P), ("log_z", _P), ("seed", C.c_uint64),
                 ("tick", C.c_uint64),
                 ("idx", _P), ("poses_out", _P), ("est_mean", _P), ("est_idx", _P), ("est_pose", _P),
-                ("lookup", C.c_int32)]
+                ("lookup", C.c_int32), ("score", C.c_int32)]
 
 
 class LaunchConfig(C.Structure):
@@ -62,6 +63,7 @@ _lib.mcl_map_upload_bricks.argtypes = [C.POINTER(MapDesc), C.c_int64, _P, _P, _P
 _lib.mcl_sensor_update.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_sensor_update_trilinear.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_sensor_update_noalloc.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
+_lib.mcl_sensor_update_sum.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P]
 _lib.mcl_normalize.argtypes = [_P, _I, _P, _P, _P, _P]
 _lib.mcl_resample.argtypes = [_P, _I, C.c_uint64, C.c_uint64, _P, _P, _P, _P]
 _lib.mcl_debug_voxel_indices.argtypes = [_P, _P, _I, _P, _I, _P, _P]
@@ -85,7 +87,7 @@ _lib.mcl_bench_stream_read.argtypes = [_P, C.c_size_t, _I, _P, C.c_size_t, _P]
 _lib.mcl_bench_l1_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, _I, _P, C.c_size_t, _P]
 _lib.mcl_last_error.restype = C.c_char_p
 for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_sensor_update", "mcl_sensor_update_trilinear",
-           "mcl_sensor_update_noalloc", "mcl_normalize",
+           "mcl_sensor_update_noalloc", "mcl_sensor_update_sum", "mcl_normalize",
            "mcl_resample",
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_get_launch_config",
            "mcl_pose_estimate", "mcl_motion_update",
@@ -210,6 +212,23 @@ def sensor_update(m: Map, points, poses, sigma: float, logw=None, stream=None):
     _dev(logw, torch.float32, (N,), "logw")
     _check(_lib.mcl_sensor_update(m.handle, _ptr(points) if K else None, K, _ptr(poses), N,
                                   float(sigma), _ptr(logw), _stream(stream)), "mcl_sensor_update")
+    return logw
+
+
+def sensor_update_sum(m: Map, points, poses, sigma: float, logw=None, stream=None):
+    """logw [N] float32 = log sum_k exp(-(1/(2 sigma^2)) m(x_n, z_k)^2), the sum
+    reading of the sensor model (see include/mcl.h)."""
+    import torch
+    K = points.shape[1] if points is not None else 0
+    N = poses.shape[1]
+    _dev(poses, torch.float32, (12, N), "poses")
+    if K:
+        _dev(points, torch.float32, (3, K), "points")
+    if logw is None:
+        logw = torch.empty(N, dtype=torch.float32, device=poses.device)
+    _dev(logw, torch.float32, (N,), "logw")
+    _check(_lib.mcl_sensor_update_sum(m.handle, _ptr(points) if K else None, K, _ptr(poses), N,
+                                      float(sigma), _ptr(logw), _stream(stream)), "mcl_sensor_update_sum")
     return logw
 
 
@@ -343,7 +362,8 @@ class Filter:
     """
 
     def __init__(self, m: Map, points, poses, sigma: float, seed: int, tick: int = 0, want_w: bool = True,
-                 resample_poses: bool = True, want_estimate: bool = False, trilinear: bool = False):
+                 resample_poses: bool = True, want_estimate: bool = False, trilinear: bool = False,
+                 score: str = "product"):
         import torch
         self.map = m
         self.points = points
@@ -352,6 +372,9 @@ class Filter:
         self.seed = int(seed)        # resampling draw of this update: (seed, tick)
         self.tick = int(tick)
         self.trilinear = bool(trilinear)   # the sensor update as mcl_sensor_update_trilinear
+        if score not in ("product", "sum"):
+            raise ValueError("score must be 'product' or 'sum'")
+        self.score = score                  # "sum": the sensor update as mcl_sensor_update_sum
         N = poses.shape[1]
         dev = poses.device
         self.logw = torch.empty(N, dtype=torch.float32, device=dev)
@@ -383,7 +406,8 @@ class Filter:
                          self.sigma, _ptr(self.logw), _ptr(self.w), _ptr(self.wq), _ptr(self.log_z),
                          self.seed & (2 ** 64 - 1), self.tick & (2 ** 64 - 1), _ptr(self.idx), _ptr(self.poses_out),
                          _ptr(self.est_mean),
-                         _ptr(self.est_idx), _ptr(self.est_pose), LOOKUP_TRILINEAR if self.trilinear else LOOKUP_NEAREST)
+                         _ptr(self.est_idx), _ptr(self.est_pose), LOOKUP_TRILINEAR if self.trilinear else LOOKUP_NEAREST,
+                         SCORE_SUM if self.score == "sum" else SCORE_PRODUCT)
 
 
 def tick(filters, graph: bool = False, stream=None, nowait: bool = False) -> bool:

@@ -3,7 +3,8 @@ tests (no method arithmetic here: every expected value comes from `oracle`).
 
 Bars:
  * log-weights within 1e-5 relative of the oracle (float32 sums of squares
-   along a fixed tree; the derivation is in the sensor kernel's header);
+   along a fixed tree; the derivation is in the sensor kernel's header); for
+   the sum reading, within the absolute bound of sum_logw_tol;
  * normalisation, fed the same float32 log-weights on both sides: log Z and the
    weights within the float64 bound below, the fixed-point weights within one
    unit plus that bound;
@@ -26,6 +27,30 @@ def assert_logw_close(gpu, ref, what=""):
     err = np.abs(np.asarray(gpu).astype(np.float64) - ref)
     bad = err > RTOL_LOGW * np.abs(ref)
     assert not bad.any(), f"{what}: {bad.sum()} particles off, worst rel {np.max(err / np.maximum(np.abs(ref), 1e-300))}"
+
+
+def sum_logw_tol(tau, sigma, ref):
+    """Absolute bound on the sum reading's float32 log-weights, per particle.
+
+    Each likelihood 2^(k2 q^2): q^2 and k2 q^2 round once each and k2 once from
+    float64, so the exponent is off by at most 3 u |k2 q^2| (u = 2^-24), i.e. the
+    term by 3 u c q^2 <= 3 u tau^2 / (2 sigma^2) relative; the exponential adds 2
+    ulps.  The positive terms are summed along the product reading's tree: 15
+    roundings in a lane, 6 in the butterfly, 3 over a piece's chunks, at most 8
+    over the pieces: 32 u relative on S.  log S then carries S's relative error
+    as an absolute one, plus 2 ulps of log and 1 of the float32 result.  Total:
+    36 u + 3 u tau^2 / (2 sigma^2) + 3 u |l|."""
+    u = 2.0 ** -24
+    r = float(tau) ** 2 / (2.0 * float(sigma) ** 2)
+    return 36 * u + 3 * u * r + 3 * u * np.abs(np.asarray(ref, np.float64))
+
+
+def assert_sum_logw_close(gpu, ref, tau, sigma, what=""):
+    ref = np.asarray(ref, np.float64)
+    err = np.abs(np.asarray(gpu).astype(np.float64) - ref)
+    tol = sum_logw_tol(tau, sigma, ref)
+    bad = err > tol
+    assert not bad.any(), f"{what}: {bad.sum()} particles off, worst {np.max(err - tol):.3g} above the bound"
 
 
 def normalize_bounds(lw32, lz_ref):

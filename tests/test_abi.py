@@ -28,7 +28,7 @@ def test_header_declares_the_boundary():
     for f in ("mcl_map_upload", "mcl_map_free", "mcl_sensor_update", "mcl_normalize", "mcl_resample",
               "mcl_debug_voxel_indices", "mcl_last_error", "mcl_tick", "mcl_job_bytes", "mcl_autotune",
               "mcl_set_launch_config", "mcl_pose_estimate", "mcl_sensor_update_trilinear", "mcl_motion_update",
-              "mcl_init_uniform", "mcl_map_upload_bricks", "mcl_map_bytes"):
+              "mcl_init_uniform", "mcl_map_upload_bricks", "mcl_map_bytes", "mcl_sensor_update_sum"):
         assert f in names
 
 
@@ -47,6 +47,8 @@ def test_argument_errors_are_reported_on_the_host(mcl):
     assert b"NULL map" in lib.mcl_last_error()
     assert lib.mcl_sensor_update_trilinear(None, fake, 10, fake, 10, 0.1, P(0x2000), None) == mcl.MCL_EINVAL
     assert lib.mcl_sensor_update_trilinear(fake, fake, 10, fake, 10, float("nan"), P(0x2000), None) == mcl.MCL_EINVAL
+    assert lib.mcl_sensor_update_sum(None, fake, 10, fake, 10, 0.1, P(0x2000), None) == mcl.MCL_EINVAL
+    assert lib.mcl_sensor_update_sum(fake, fake, 10, fake, 10, -0.1, P(0x2000), None) == mcl.MCL_EINVAL
     assert lib.mcl_normalize(None, 10, None, fake, None, None) == mcl.MCL_EINVAL
     assert lib.mcl_normalize(fake, 0, None, P(0x9000), None, None) == mcl.MCL_EINVAL
     assert lib.mcl_normalize(fake, mcl.MAX_PARTICLES + 1, None, P(0x90000000), None, None) == mcl.MCL_ERANGE
@@ -113,6 +115,9 @@ def test_tick_and_tuning_argument_errors(mcl):
     jobs[1].est_idx = P(0x7100)
     assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL and b"without est_mean" in lib.mcl_last_error()
     jobs[1].est_idx = None
+    jobs[1].score = 7
+    assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL and b"score must be" in lib.mcl_last_error()
+    jobs[1].score = mcl.SCORE_PRODUCT
     jobs[1].lookup = 5   # neither nearest nor trilinear
     assert lib.mcl_tick(jobs, 2, 0, None) == mcl.MCL_EINVAL and b"lookup must be" in lib.mcl_last_error()
     assert lib.mcl_job_bytes(0, 5) == 0
@@ -140,6 +145,7 @@ def test_binding_constants_match_the_header(mcl):
             "MCL_EDEVICE": mcl.MCL_EDEVICE, "MCL_ERANGE": mcl.MCL_ERANGE, "MCL_EBUSY": mcl.MCL_EBUSY,
             "MCL_TICK_GRAPH": mcl.TICK_GRAPH, "MCL_TICK_NOWAIT": mcl.TICK_NOWAIT, "MCL_MAX_JOBS": mcl.MAX_JOBS,
             "MCL_LOOKUP_NEAREST": mcl.LOOKUP_NEAREST, "MCL_LOOKUP_TRILINEAR": mcl.LOOKUP_TRILINEAR,
+            "MCL_SCORE_PRODUCT": mcl.SCORE_PRODUCT, "MCL_SCORE_SUM": mcl.SCORE_SUM,
             "MCL_WQ_SHIFT": mcl.WQ_SHIFT}
     for name, val in want.items():
         m = re.search(r"#define\s+" + name + r"\s+\(?(-?\d+)\)?", text)

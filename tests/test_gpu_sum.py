@@ -1,0 +1,200 @@
+"""The sum reading of the sensor model (mcl_sensor_update_sum, and the tick's
+MCL_SCORE_SUM jobs) against the CPU oracle, through the C ABI.
+
+Bars: log-weights within the absolute bound of checks.sum_logw_tol (derived
+there from the float32 arithmetic); every launch setting gives the same bits;
+a tick gives each filter the single-filter calls' results bit for bit, and its
+normalisation and resampling follow the oracle as for the product reading.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from tests import checks
+from tests.helpers import make_map, poses_from, random_rotations
+from workloads import configs
+from workloads.tsdf import f32, to_bricks
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "a GPU is required"
+    return t
+
+
+@pytest.fixture(scope="module")
+def mcl():
+    from paper_2310_04172_amd import mcl as m
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def random_case(seed, dims, N, K, dtype="i16", v=0.1, tau=0.3):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    if dtype == "f32":
+        vals = rng.uniform(-tau, tau, size=(nz, ny, nx)).astype(np.float32)
+        vals[:, :, : nx // 3] = np.float32(tau)
+    else:
+        lim = 32767 if dtype == "i16" else 127
+        vals = rng.integers(-lim, lim + 1, size=(nz, ny, nx)).astype(np.int16 if dtype == "i16" else np.int8)
+        vals[:, :, : nx // 3] = lim         # wholly +Q bricks: the sentinel path
+    tmap = make_map(vals, v, origin=(-0.2, 0.1, -0.05), tau=tau, dtype=dtype)
+    ext = np.array(dims) * v
+    poses = poses_from(random_rotations(rng, N), rng.uniform(0, 1, (N, 3)) * ext)
+    pts = rng.normal(0, 0.4 * ext.mean(), size=(3, K)).astype(np.float32)
+    return tmap, pts, poses
+
+
+def gpu_sum(torch, mcl, tmap, pts, poses, sigma, m=None):
+    m = m or mcl.Map.from_tsdf(tmap)
+    lw = mcl.sensor_update_sum(m, dev(torch, pts) if pts.shape[1] else None, dev(torch, poses), sigma)
+    torch.cuda.synchronize()
+    return lw.cpu().numpy()
+
+
+@pytest.mark.parametrize("N,K", [(1, 1), (1, 63), (63, 1000), (65, 1025), (130, 4097), (7, 9000), (200, 64)])
+@pytest.mark.parametrize("dtype", ["i16", "i8", "f32"])
+def test_sum_ragged_sizes(torch, mcl, oracle_lib, N, K, dtype):
+    say(f"case: sum reading ragged N={N} K={K} dtype={dtype}")
+    tmap, pts, poses = random_case(N * 131 + K, (21, 18, 13), N, K, dtype)
+    sigma = f32(0.15)
+    lw = gpu_sum(torch, mcl, tmap, pts, poses, sigma)
+    ref = oracle_lib.sensor_update_sum(tmap, pts, poses, sigma)
+    checks.assert_sum_logw_close(lw, ref, tmap.tau, sigma, f"N={N} K={K} {dtype}")
+
+
+@pytest.mark.parametrize("ratio", [2.0, 4.0, 8.0])
+def test_sum_sigma_range(torch, mcl, oracle_lib, ratio):
+    """sigma from tau / 2 down to the smallest allowed, tau / 8 (likelihoods down to e^-32)."""
+    say(f"case: sum reading sigma = tau / {ratio}")
+    tmap, pts, poses = random_case(int(ratio) + 40, (30, 26, 14), 300, 6000, "i16")
+    sigma = f32(float(tmap.tau) / ratio)
+    lw = gpu_sum(torch, mcl, tmap, pts, poses, sigma)
+    ref = oracle_lib.sensor_update_sum(tmap, pts, poses, sigma)
+    checks.assert_sum_logw_close(lw, ref, tmap.tau, sigma, f"tau/{ratio}")
+
+
+def test_sum_closed_forms_and_limits(torch, mcl, oracle_lib):
+    """Empty scan: 0.  Every point outside: log K - c Q^2.  One point: the
+    product reading's value.  sigma below tau / 8 and sparse maps are refused."""
+    say("case: sum reading closed forms")
+    tmap, pts, poses = random_case(9, (16, 16, 8), 70, 50, "i16")
+    sigma = f32(0.12)
+    m = mcl.Map.from_tsdf(tmap)
+    assert np.all(gpu_sum(torch, mcl, tmap, np.zeros((3, 0), np.float32), poses, sigma, m) == 0.0)
+    far = np.full((3, 50), 1e4, np.float32)
+    cq2 = float(tmap.tau) ** 2 / (2 * float(sigma) ** 2)       # c Q^2
+    expect = math.log(50) - cq2
+    lw = gpu_sum(torch, mcl, tmap, far, poses, sigma, m)
+    np.testing.assert_allclose(lw, expect, rtol=0, atol=float(checks.sum_logw_tol(tmap.tau, sigma, expect)))
+    one = pts[:, :1]
+    lp = mcl.sensor_update(m, dev(torch, one), dev(torch, poses), sigma).cpu().numpy()
+    ls = gpu_sum(torch, mcl, tmap, one, poses, sigma, m)
+    checks.assert_sum_logw_close(ls, lp.astype(np.float64), tmap.tau, sigma, "single point")
+    with pytest.raises(mcl.MclError, match="sigma >= tau / 8"):
+        gpu_sum(torch, mcl, tmap, pts, poses, f32(float(tmap.tau) / 8.5), m)
+    coords, vals = to_bricks(tmap)
+    sp = mcl.Map.from_bricks((tmap.nx, tmap.ny, tmap.nz), tmap.voxel, tmap.origin, tmap.tau, "i16", coords, vals)
+    with pytest.raises(mcl.MclError, match="dense map"):
+        gpu_sum(torch, mcl, tmap, pts, poses, sigma, sp)
+
+
+@pytest.mark.parametrize("coarse", [0, 1, 2])
+def test_sum_launch_settings_change_no_bit(torch, mcl, oracle_lib, coarse):
+    """The coarse level in LDS bits, in global bytes or chosen per wave, with
+    different launch shapes: the same bits, and the oracle's values."""
+    say(f"case: sum reading, coarse mode {coarse}")
+    N, K = 700, 9000
+    tmap, pts, poses = random_case(3, (40, 36, 20), N, K, "i16")
+    sigma = f32(0.1)
+    m = mcl.Map.from_tsdf(tmap)
+    base = gpu_sum(torch, mcl, tmap, pts, poses, sigma, m)
+    ref = oracle_lib.sensor_update_sum(tmap, pts, poses, sigma)
+    checks.assert_sum_logw_close(base, ref, tmap.tau, sigma, "default launch")
+    try:
+        for wpb, bpc, runs, l8 in ((2, 0, 1, 4), (8, 4, 16, 8), (4, 16, 64, 5)):
+            mcl.set_launch_config("i16", K, N, (wpb, bpc, coarse, runs, l8))
+            got = gpu_sum(torch, mcl, tmap, pts, poses, sigma, m)
+            assert np.array_equal(got.view(np.uint32), base.view(np.uint32)), (wpb, bpc, coarse, runs, l8)
+    finally:
+        mcl.set_launch_config("i16", K, N, None)
+
+
+def test_sum_in_tick(torch, mcl, oracle_lib):
+    """Filters of both readings in one tick, eager and replayed: each gets the
+    single-filter calls' results bit for bit; the sum filters' log-weights
+    follow the oracle, and their resampled indices the oracle's resampling of
+    the GPU's fixed-point weights."""
+    say("case: sum reading in a tick")
+    rng = np.random.default_rng(12)
+    tmaps = [random_case(20 + i, (40, 36, 20), 1, 1, dt)[0] for i, dt in enumerate(("i16", "i8", "f32"))]
+    maps = [mcl.Map.from_tsdf(t) for t in tmaps]
+    specs = [(0, 1, 1, "sum"), (1, 63, 1025, "sum"), (2, 65, 9000, "product"), (0, 1000, 5000, "sum"),
+             (1, 130, 0, "sum"), (2, 700, 4097, "sum"), (0, 3000, 700, "product"), (0, 2000, 12000, "sum")]
+    filters, host = [], []
+    for (mi, N, K, score) in specs:
+        tmap = tmaps[mi]
+        ext = np.array(tmap.dims) * tmap.voxel
+        poses = poses_from(random_rotations(rng, N), rng.uniform(0, 1, (N, 3)) * ext)
+        pts = rng.normal(0, 0.3 * ext.mean(), size=(3, K)).astype(np.float32)
+        f = mcl.Filter(maps[mi], dev(torch, pts) if K else None, dev(torch, poses), f32(0.1 + 0.02 * mi),
+                       int(rng.integers(0, 2 ** 63)), score=score)
+        filters.append(f)
+        host.append((tmap, pts, poses))
+    side = torch.cuda.Stream()
+    for graph in (False, True, True):
+        with torch.cuda.stream(side):
+            mcl.tick(filters, graph=graph, stream=side)
+        side.synchronize()
+        for f, (tmap, pts, poses) in zip(filters, host):
+            upd = mcl.sensor_update_sum if f.score == "sum" else mcl.sensor_update
+            lw = upd(f.map, f.points, f.poses, f.sigma)
+            w, wq, lz = mcl.normalize(lw)
+            idx, pout = mcl.resample(wq, f.seed, f.tick, f.poses)
+            torch.cuda.synchronize()
+            for name, a, b in (("logw", f.logw, lw), ("wq", f.wq, wq), ("idx", f.idx, idx),
+                               ("poses_out", f.poses_out, pout)):
+                x, y = a.cpu().numpy(), b.cpu().numpy()
+                assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), \
+                    f"graph={graph} N={f.N} K={f.K} {f.score}: {name}"
+            if f.score == "sum" and not graph:
+                ref = oracle_lib.sensor_update_sum(tmap, pts, poses, f.sigma)
+                got = f.logw.cpu().numpy()
+                checks.assert_sum_logw_close(got, ref, tmap.tau, f.sigma, f"tick N={f.N} K={f.K}")
+                wq_ref = checks.check_normalize(oracle_lib, got, f.wq.cpu().numpy(), what="tick normalise")
+                checks.check_resample(oracle_lib, wq_ref, f.seed, f.tick, f.idx.cpu().numpy(), poses,
+                                      f.poses_out.cpu().numpy(), "tick resample")
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return configs.config2()
+
+
+def test_sum_global_workload_sampled(torch, mcl, oracle_lib, cfg2):
+    """The global-localisation workload at full size (N = 10^6) with the sum
+    reading: a seeded 512-particle subset against the oracle."""
+    w = cfg2
+    say(f"case: sum reading, plain-global full size N={w.N} K={w.K}")
+    m = mcl.Map.from_tsdf(w.tmap)
+    lw = mcl.sensor_update_sum(m, dev(torch, w.points), dev(torch, w.poses), w.sigma)
+    torch.cuda.synchronize()
+    lw = lw.cpu().numpy()
+    sub = configs.subset_indices(2, w.N)[:512]
+    ref = oracle_lib.sensor_update_sum(w.tmap, w.points, np.ascontiguousarray(w.poses[:, sub]), w.sigma, nthreads=8)
+    checks.assert_sum_logw_close(lw[sub], ref, w.tmap.tau, w.sigma, "config2 subset, sum reading")
+    assert np.all(np.isfinite(lw)) and np.all(lw <= math.log(w.K) + 1e-5)
