@@ -591,11 +591,36 @@ int device_cus() {
     return cus;
 }
 
+// LDS bytes a compute unit holds (64 KiB if the device does not say).
+static size_t device_lds_per_cu() {
+    static size_t lds = 0;
+    if (!lds) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            lds = p.maxSharedMemoryPerMultiProcessor;
+        if (lds == 0) lds = 64 * 1024;
+    }
+    return lds;
+}
+
+// Waves per workgroup of a launch whose workgroups each hold `lds` bytes of read
+// bits: the requested number, raised (up to 8) until the workgroups that fit a
+// compute unit's LDS hold the 16 waves its registers allow (4 per SIMD), so
+// that a large bit table does not cut the occupancy.  Any shape gives the same
+// bits.
+static int lds_waves_per_block(int wpb, size_t lds) {
+    if (lds == 0) return wpb;
+    const size_t fit = device_lds_per_cu() / lds;
+    while (wpb < 8 && fit * (size_t)wpb < 16) wpb *= 2;
+    return wpb;
+}
+
 // nitems: the item count when known on the host (sizes a one-wave-per-item
 // grid); a persistent grid does not need it.
 template <typename T, typename Src, int LK = kLookNearest, bool SUM = false>
 static void launch_sensor_t(const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream, size_t lds = 0) {
-    const int wpb = cfg.waves_per_block;
+    const int wpb = lds_waves_per_block(cfg.waves_per_block, lds);
     int64_t blocks = (nitems + wpb - 1) / wpb;
     if (cfg.blocks_per_cu > 0) blocks = std::min<int64_t>(blocks, (int64_t)device_cus() * cfg.blocks_per_cu);
     if (blocks < 1) blocks = 1;
