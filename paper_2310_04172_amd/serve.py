@@ -110,6 +110,7 @@ class Robot:
 @dataclass
 class ServeStats:
     latencies_ms: list = field(default_factory=list)
+    phases: list = field(default_factory=list)      # the robot's phase of each completed update
     completed: int = 0
     dropped: int = 0
     arrived: int = 0
@@ -128,7 +129,19 @@ class ServeStats:
                 "dropped": self.dropped, "drop_rate": self.dropped / max(1, self.arrived),
                 "evals_per_s": self.evals / max(self.wall_s, 1e-9), "ticks": self.ticks, "busy": self.busy,
                 "uploaded_MB": self.uploaded_bytes / 1e6,
-                "max_resident_GiB": self.max_resident_bytes / 2 ** 30, "wall_s": self.wall_s}
+                "max_resident_GiB": self.max_resident_bytes / 2 ** 30, "wall_s": self.wall_s,
+                "by_phase": self.by_phase()}
+
+    def by_phase(self) -> dict:
+        """Completed updates and their p50 / p99 latency per robot phase."""
+        out = {}
+        ph = np.asarray(self.phases)
+        lat = np.asarray(self.latencies_ms)
+        for name in sorted(set(self.phases)):
+            x = lat[ph == name]
+            out[name] = {"completed": int(x.size), "p50_ms": float(np.percentile(x, 50)),
+                         "p99_ms": float(np.percentile(x, 99))}
+        return out
 
 
 class Engine:
@@ -200,6 +213,7 @@ class Engine:
         if self.on_complete is not None:
             self.on_complete(r, r.filt)
         self.stats.latencies_ms.append((t_done - r.in_flight) * 1e3)
+        self.stats.phases.append(r.phase)
         self.stats.completed += 1
         n_evals = r.poses.shape[1] * r.K
         self.stats.evals += n_evals

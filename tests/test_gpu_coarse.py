@@ -5,8 +5,9 @@ summation order), and those bits must meet the float32 bar against the CPU
 oracle.  Cases: one and several chunks and pieces, ragged tails, groups
 shorter than a wave, all storage types, particles spread over the map and
 clustered round one pose (the two regimes the per-wave choice separates), the
-full global-localisation workload in both regimes, and a map whose bit table
-is too large for LDS (every mode falls back to the global bytes)."""
+full global-localisation workload in both regimes, a map whose bit table is
+too large for LDS (every mode falls back to the global bytes), and one whose
+table fits LDS only with more waves per workgroup."""
 
 import sys
 
@@ -124,6 +125,38 @@ def test_bit_table_too_large_for_lds(torch, mcl, oracle_lib):
     m = mcl.Map.from_tsdf(tmap)
     outs = all_modes(mcl, m, dev(torch, pts), dev(torch, poses), f32(0.075), "i8")
     assert_same(outs, "large map")
+    ref = oracle_lib.sensor_update(tmap, pts, poses, f32(0.075))
+    assert np.all(np.abs(outs[0] - ref) <= RTOL * np.abs(ref))
+    assert np.unique(np.round(ref, 3)).size > N // 2
+
+
+@pytest.mark.parametrize("wpb", [2, 4, 8])
+def test_large_bit_table_in_lds(torch, mcl, oracle_lib, wpb):
+    """1024 x 2048 x 128 int8 voxels = 262,144 bricks: a 32 KiB bit table, which
+    fits LDS but at 2 or 4 waves per workgroup would leave too few waves per
+    compute unit, so the launch raises its waves per workgroup.  Every shape
+    and mode gives the same bits, within the bar of the oracle."""
+    say(f"case: coarse modes, 32 KiB bit table, {wpb} waves per workgroup")
+    rng = np.random.default_rng(23)
+    dims = (1024, 2048, 128)
+    vals = np.full(dims[::-1], 127, np.int8)
+    vals[40:80, 900:1000, 400:520] = rng.integers(-127, 128, (40, 100, 120)).astype(np.int8)
+    tmap = make_map(vals, 0.05, dtype="i8", tau=0.15)
+    N, K = 130, 5000
+    lo = np.array([400, 900, 40]) * 0.05
+    hi = np.array([520, 1000, 80]) * 0.05
+    poses = poses_from(random_rotations(rng, N), rng.uniform(lo, hi, (N, 3)))
+    pts = rng.normal(0, 1.0, (3, K)).astype(np.float32)
+    m = mcl.Map.from_tsdf(tmap)
+    X, P = dev(torch, pts), dev(torch, poses)
+    outs = []
+    try:
+        for mode in (0, 1, 2):
+            mcl.set_launch_config("i8", K, N, (wpb, 0, mode))
+            outs.append(mcl.sensor_update(m, X, P, f32(0.075)).cpu().numpy())
+    finally:
+        mcl.set_launch_config("i8", K, N, None)
+    assert_same(outs, f"32 KiB table, {wpb} waves")
     ref = oracle_lib.sensor_update(tmap, pts, poses, f32(0.075))
     assert np.all(np.abs(outs[0] - ref) <= RTOL * np.abs(ref))
     assert np.unique(np.round(ref, 3)).size > N // 2
