@@ -378,8 +378,10 @@ size_t mcl_job_bytes(int32_t N, int32_t K);
  *   lds_threshold:   with coarse = 0, a wave reads the bits in LDS when more than
  *                    lds_threshold / 8 of its probe lookups read in place (1..8;
  *                    0 = the default 6).
- * Sparse maps use a fixed shape.  mcl_tick uses, per storage type, the setting
- * stored for the largest filter of that type. */
+ * Sparse maps use a fixed shape.  mcl_tick uses, per storage type, the shape and
+ * runs stored for the largest filter of that type (which also decides whether
+ * the launch holds the bits in LDS), and for each filter the coarse mode and
+ * threshold stored for its own size class. */
 typedef struct {
     int32_t waves_per_block;
     int32_t blocks_per_cu;

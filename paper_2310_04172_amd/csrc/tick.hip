@@ -228,9 +228,10 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         if (hipMalloc((void **)&S.dev, want) != hipSuccess) return fail(MCL_ENOMEM, "tick: workspace allocation failed");
         S.dev_bytes = want;
     }
-    // launch shape, runs and coarse-level mode per sensor group: those tuned
-    // for the group's largest filter (dense nearest lookups; the sparse and
-    // trilinear launches have a fixed shape)
+    // launch shape and runs per sensor group: those tuned for the group's
+    // largest filter (dense nearest lookups; the sparse and trilinear launches
+    // have a fixed shape); the coarse-level mode and threshold per filter, from
+    // its own size class (below)
     LaunchCfg cfgs[kGroups];
     for (int g = 0; g < kGroups; ++g) {
         cfgs[g] = kDefaultCfg;
@@ -285,11 +286,20 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
                 J.score = kScoreSum;
                 J.k2 = sum_k2(m, F.sigma);
             }
-            J.coarse = cfgs[g].coarse;
             J.item0 = items;
             J.elem0 = elems;
             J.nsub = nsub;
             apply_cfg(J, cfgs[g]);
+            if (dense_nearest(job_kind(F))) {
+                // where a filter reads the coarse level suits the spread of its own
+                // particles: its own size class's setting (whether the launch holds
+                // the bits in LDS at all is the group's)
+                const LaunchCfg own = tuned_config(m->dtype, F.K, F.N);
+                J.coarse = own.coarse;
+                J.lds8 = own.lds8 > 0 ? own.lds8 : kLdsEighths;
+            } else {
+                J.coarse = cfgs[g].coarse;
+            }
             items += (int64_t)J.ngroups * J.npiece * J.nsub;
             elems += F.N;
             W.logw = F.logw;
