@@ -49,7 +49,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-BOX_CPU_SHARE = 16   # host threads a one-GPU machine gives a job, whatever the host has
+HOST_THREAD_CAP = 16   # host threads a one-GPU job is given, whatever the host has
 
 
 def cpu_info() -> dict:
@@ -70,8 +70,8 @@ def cpu_info() -> dict:
 
 
 def cpu_threads() -> int:
-    """The oracle's threads: every CPU this process may use, up to the box's share."""
-    return max(1, min(BOX_CPU_SHARE, cpu_info()["affinity"]))
+    """The oracle's threads: every CPU this process may use, up to a one-GPU job's share."""
+    return max(1, min(HOST_THREAD_CAP, cpu_info()["affinity"]))
 
 
 def cpu_baseline(w, target_s: float = 20.0) -> dict:
@@ -97,7 +97,7 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
     return {"value": evals / dt / 1e9, "unit": "G particle-point evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} of {w.N} particles x {w.K} points (sensor update + normalise + resample), {dt:.1f} s",
             "cpu": cpu_info(), "threads_note": f"one thread per CPU of this process's affinity set, at most the "
-                                               f"{BOX_CPU_SHARE} a one-GPU box allots"}
+                                               f"{HOST_THREAD_CAP} a one-GPU job is given"}
 
 
 # the sources that make up the sensor kernel's device code and its map layout
