@@ -180,6 +180,19 @@ def test_sum_in_tick(torch, mcl, oracle_lib):
                                       f.poses_out.cpu().numpy(), "tick resample")
 
 
+def test_sum_max_points(torch, mcl, oracle_lib):
+    """K = MCL_MAX_POINTS: 256 pieces per particle, whose partial sums of
+    likelihoods the combine kernel adds in its deepest tree before the log; 70
+    particles (one full and one ragged group)."""
+    K, N = mcl.MAX_POINTS, 70
+    say(f"case: sum reading at K = {K}, N = {N}")
+    tmap, pts, poses = random_case(78, (40, 36, 20), N, K, "i16")
+    sigma = f32(0.15)
+    lw = gpu_sum(torch, mcl, tmap, pts, poses, sigma)
+    ref = oracle_lib.sensor_update_sum(tmap, pts, poses, sigma, nthreads=8)
+    checks.assert_sum_logw_close(lw, ref, tmap.tau, sigma, "K = MCL_MAX_POINTS")
+
+
 @pytest.fixture(scope="module")
 def cfg2():
     return configs.config2()
