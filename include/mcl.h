@@ -115,7 +115,8 @@ size_t mcl_map_bytes(mcl_map map);
  * where m(x_n, z_k) is the map value of the voxel containing the scan point z_k
  * transformed by particle pose x_n (R p + t), and +tau for points outside the
  * map.  This is the log of the product of Eq. (3) over the scan without its
- * constant factor, which cancels in normalisation.
+ * constant factor, which cancels in normalisation (the full log-likelihood is
+ * logw[n] - (K / 2) ln(2 pi sigma^2)).
  * The voxel of a point follows a fixed float32 recipe (round-to-nearest-even;
  * fma is the IEEE fused multiply-add, one rounding): with
  * inv_v = (float)(1.0 / (double)voxel),
@@ -136,7 +137,8 @@ mcl_status mcl_sensor_update(mcl_map map, const float *points, int32_t K, const 
  * paper does not say how the points' likelihoods combine; this entry point
  * takes their sum instead of their product).  For every particle n:
  *     logw[n] = log sum_k exp(-(1 / (2 sigma^2)) * m(x_n, z_k)^2),
- * the log of the sum of Eq. (3) over the scan without its constant factor;
+ * the log of the sum of Eq. (3) over the scan without its constant factor
+ * (the full log of the sum is logw[n] - (1 / 2) ln(2 pi sigma^2));
  * logw[n] = 0 when K = 0 (no evidence: equal weights, as mcl_sensor_update
  * gives).  Lookup and voxel recipe as for mcl_sensor_update.  Each likelihood
  * is computed in float32 as 2^(k2 q^2) with k2 = -c log2(e) (c the score
