@@ -397,6 +397,40 @@ class Filter:
     def K(self):
         return 0 if self.points is None else self.points.shape[1]
 
+    # ------------------------------------------------------ checkpoint / resume
+    def state_dict(self) -> dict:
+        """The filter's state as host copies: the particle set the next update
+        reads, and (seed, tick), which fix that update's resampling draw.  The
+        copy runs on the current stream: work that writes the poses on another
+        stream must have completed."""
+        return {"poses": self.poses.cpu().numpy(), "sigma": self.sigma, "seed": self.seed, "tick": self.tick,
+                "score": self.score, "trilinear": self.trilinear}
+
+    def load_state_dict(self, state: dict):
+        """Restores a state_dict() into this filter's buffers (same N; the copy
+        runs on the current stream); the next update then draws exactly as the
+        saved filter's would have."""
+        import torch
+        poses = np.ascontiguousarray(state["poses"], np.float32)
+        if poses.shape != tuple(self.poses.shape):
+            raise ValueError(f"poses of shape {poses.shape} for a filter of shape {tuple(self.poses.shape)}")
+        self.poses.copy_(torch.from_numpy(poses))
+        self.sigma, self.seed, self.tick = float(state["sigma"]), int(state["seed"]), int(state["tick"])
+        self.score, self.trilinear = str(state["score"]), bool(state["trilinear"])
+
+    def save(self, path: str):
+        """state_dict() to a .npz file (plain arrays, no pickled objects)."""
+        st = self.state_dict()
+        np.savez(path, poses=st["poses"], sigma=np.float64(st["sigma"]), seed=np.uint64(st["seed"]),
+                 tick=np.uint64(st["tick"]), score=np.str_(st["score"]), trilinear=np.bool_(st["trilinear"]))
+
+    def load(self, path: str):
+        """Restores a file written by save()."""
+        with np.load(path, allow_pickle=False) as z:
+            self.load_state_dict({"poses": z["poses"], "sigma": float(z["sigma"]), "seed": int(z["seed"]),
+                                  "tick": int(z["tick"]), "score": str(z["score"]),
+                                  "trilinear": bool(z["trilinear"])})
+
     def job(self) -> FilterJob:
         import torch
         _dev(self.poses, torch.float32, (12, self.N), "poses")

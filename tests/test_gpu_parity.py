@@ -178,7 +178,8 @@ def test_negative_zero_coordinates(torch, mcl, oracle_lib):
 
 
 def test_permutation_and_determinism(torch, mcl):
-    """Bit-identical results for the same particle whatever its slot, N or run."""
+    """Bit-identical results for the same particle whatever its slot, N, run or
+    stream (the sums have a fixed order and no atomics)."""
     say("case: determinism")
     tmap, pts, poses = random_case(9, (40, 40, 20), 300, 9000)
     m = mcl.Map.from_tsdf(tmap)
@@ -192,6 +193,22 @@ def test_permutation_and_determinism(torch, mcl):
     assert np.array_equal(c, a[perm])
     d = mcl.sensor_update(m, X, dev(torch, poses[:, 17:18]), f32(0.2)).cpu().numpy()
     assert d[0] == a[17]
+    # ten more runs, alternating the default stream and a side stream, and the
+    # whole chain (normalise, resample): the same bits every time
+    side = torch.cuda.Stream()
+    w0, wq0, lz0 = mcl.normalize(dev(torch, a))
+    idx0, _ = mcl.resample(wq0, 5, 3, P)
+    ref = [x.cpu().numpy() for x in (w0, wq0, lz0, idx0)]
+    for r in range(10):
+        s = side if r % 2 else torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            lw = mcl.sensor_update(m, X, P, f32(0.2), stream=s)
+            w, wq, lz = mcl.normalize(lw, stream=s)
+            idx, _ = mcl.resample(wq, 5, 3, P, stream=s)
+        s.synchronize()
+        assert np.array_equal(lw.cpu().numpy().view(np.uint32), a.view(np.uint32)), r
+        for x, y in zip((w, wq, lz, idx), ref):
+            assert np.array_equal(x.cpu().numpy().view(np.uint8), y.view(np.uint8)), r
 
 
 # --------------------------------------------------------- workload configs
