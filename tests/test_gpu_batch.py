@@ -133,6 +133,29 @@ def test_tick_graph_replay(torch, mcl, maps):
             assert_same(got[i], single(torch, mcl, f), f"replay {rep} job {i}")
 
 
+def test_tick_max_jobs(torch, mcl, maps):
+    """MCL_MAX_JOBS filters in one tick (every storage type, N from 1 to 40, K
+    from 0 to 300, every second filter with a pose estimate), eager and
+    replayed from a graph: the job searches over 4,096 entries and the prefix
+    offsets hold, and a seeded sample of filters (with the first and the last)
+    gets its single calls' results bit for bit."""
+    n = mcl.MAX_JOBS
+    say(f"case: tick with {n} filters")
+    rng = np.random.default_rng(77)
+    specs = [(int(rng.integers(0, 4)), int(rng.integers(1, 41)), int(rng.integers(0, 301))) for _ in range(n)]
+    filters = job_set(torch, mcl, 78, maps, specs)
+    sample = sorted({0, n - 1, *rng.choice(n, size=126, replace=False).tolist()})
+    s = torch.cuda.Stream()
+    for graph in (False, True):
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            mcl.tick(filters, graph=graph, stream=s)
+        s.synchronize()
+        for i in sample:
+            f = filters[i]
+            assert_same(outputs(torch, f), single(torch, mcl, f), f"graph={graph} job {i} (N={f.N}, K={f.K})")
+
+
 def test_launch_shapes_are_bit_identical(torch, mcl, tmp_path, monkeypatch):
     say("case: launch shapes")
     cache = tmp_path / "tune.txt"

@@ -111,6 +111,14 @@ def test_sum_closed_forms_and_limits(torch, mcl, oracle_lib):
     sp = mcl.Map.from_bricks((tmap.nx, tmap.ny, tmap.nz), tmap.voxel, tmap.origin, tmap.tau, "i16", coords, vals)
     with pytest.raises(mcl.MclError, match="dense map"):
         gpu_sum(torch, mcl, tmap, pts, poses, sigma, sp)
+    # in a tick: a sum job on a sparse map, with the trilinear lookup, or with too
+    # small a sigma is refused before anything is enqueued
+    X, P = dev(torch, pts), dev(torch, poses)
+    for bad in (mcl.Filter(sp, X, P, sigma, 1, score="sum"),
+                mcl.Filter(m, X, P, sigma, 1, score="sum", trilinear=True),
+                mcl.Filter(m, X, P, f32(float(tmap.tau) / 9), 1, score="sum")):
+        with pytest.raises(mcl.MclError, match="sum reading"):
+            mcl.tick([mcl.Filter(m, X, P, sigma, 2), bad])
 
 
 @pytest.mark.parametrize("coarse", [0, 1, 2])
