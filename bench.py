@@ -482,6 +482,80 @@ def run_estimate(args):
     return out
 
 
+NSWEEP = (1024, 4096, 16384, 50000, 100000, 262144, 1048576, 2097152)
+
+
+def run_nsweep(args):
+    """Sensor-update time against the particle count (the paper's run-time
+    comparison: normally distributed clouds, linear in N): the global map and
+    VLP-16 scan, particles Gaussian round the true pose (0.5 m, 5 degrees), for
+    each N the launch tuned, then the sensor update alone and the whole step
+    (sensor update, normalise, resample) timed with HIP events.  A least-squares
+    line t = a + b N over N >= 16384 and its largest relative residual test the
+    linearity."""
+    import torch
+    from paper_2310_04172_amd import mcl
+    from workloads import configs
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    per = {}
+    m = None
+    for N in NSWEEP:
+        w = configs.config2_local(N)
+        if m is None:
+            m = mcl.Map.from_tsdf(w.tmap)
+        pts = torch.from_numpy(w.points).to(dev)
+        poses = torch.from_numpy(w.poses).to(dev)
+        K = w.K
+        logw = torch.empty(N, dtype=torch.float32, device=dev)
+        wq = torch.empty(N, dtype=torch.uint64, device=dev)
+        lz = torch.empty(1, dtype=torch.float64, device=dev)
+        idx = torch.empty(N, dtype=torch.int32, device=dev)
+        pout = torch.empty_like(poses)
+        if args.autotune:
+            mcl.autotune(m, pts, poses, w.sigma)
+        reps = max(5, min(200, int(2e10 // (N * K))))
+
+        def timed(full):
+            for _ in range(2):
+                mcl.sensor_update(m, pts, poses, w.sigma, logw, stream)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                mcl.sensor_update(m, pts, poses, w.sigma, logw, stream)
+                if full:
+                    mcl.normalize(logw, None, wq, lz, want_w=False, stream=stream)
+                    mcl.resample(wq, w.seed, 0, poses, pout, idx, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps
+
+        ms_s, ms_f = timed(False), timed(True)
+        per[str(N)] = {"K": K, "sensor_ms": ms_s, "step_ms": ms_f, "evals_per_s_G": N * K / (ms_s * 1e-3) / 1e9,
+                       "particles_per_s_M": N / (ms_f * 1e-3) / 1e6, "reps": reps,
+                       "launch": list(mcl.get_launch_config(w.tmap.dtype, K, N))}
+        log(f"N={N}: sensor {ms_s:.4f} ms ({per[str(N)]['evals_per_s_G']:.0f} G evals/s), step {ms_f:.4f} ms")
+        del pts, poses, logw, wq, lz, idx, pout
+    xs = np.array([n for n in NSWEEP if n >= 16384], np.float64)
+    ys = np.array([per[str(int(n))]["sensor_ms"] for n in xs])
+    A = np.vstack([np.ones_like(xs), xs]).T
+    (a0, b0), *_ = np.linalg.lstsq(A, ys, rcond=None)
+    resid = ys - (a0 + b0 * xs)
+    fit = {"intercept_ms": float(a0), "ms_per_million_particles": float(b0 * 1e6),
+           "max_relative_residual": float(np.max(np.abs(resid) / ys)),
+           "r2": float(1.0 - np.sum(resid ** 2) / np.sum((ys - ys.mean()) ** 2))}
+    log(f"linear fit over N >= 16384: {json.dumps(fit)}")
+    big = per[str(NSWEEP[-2])]
+    out = base_record(args, METRIC + " [sensor update against the particle count]", big["evals_per_s_G"],
+                      big["step_ms"],
+                      {"workload": "N-sweep: 1024x1024x128@0.05m int16 warehouse, VLP-16 16x1800, particles "
+                                   "Gaussian round the true pose (0.5 m, 5 deg), N = 1,024 .. 2,097,152",
+                       "per_N": per, "linear_fit": fit, "value_at_N": NSWEEP[-2],
+                       "launch_autotuned": bool(args.autotune)})
+    return out
+
+
 def run_loop(args):
     """The whole MCL loop on the device for the global-localisation workload:
     particles initialised uniformly in free space once, then per iteration
@@ -736,7 +810,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="global", choices=["global", "converged", "small", "batched", "served", "precision", "estimate", "trilinear", "loop",
-                                                    "sparse", "sum"])
+                                                    "sparse", "sum", "nsweep"])
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -772,6 +846,8 @@ def main():
         out = run_estimate(args)
     elif args.workload == "loop":
         out = run_loop(args)
+    elif args.workload == "nsweep":
+        out = run_nsweep(args)
     else:
         t0 = time.perf_counter()
         w = (configs.config1() if args.workload == "small" else

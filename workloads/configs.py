@@ -227,6 +227,20 @@ def config2_converged(n_particles=1_000_000) -> Workload:
                     tmap, pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), resample_seed(2), (gxyz, grpy))
 
 
+def config2_local(n_particles: int, s_xyz: float = 0.5, s_rpy_deg: float = 5.0) -> Workload:
+    """The global-localisation map and scan with the particles normally
+    distributed round the true pose (s_xyz metres, s_rpy_deg degrees per axis),
+    as the clouds the paper times its sensor update on against the particle count."""
+    sc, tmap = warehouse_map(2)
+    gxyz, grpy = ground_truth_pose(rng(2, 1), sc, (1.0, 1.0), (50.2, 50.2), sc.floor_z)
+    R, t = pose_matrix(gxyz, grpy)
+    pts = raycast_scan(sc, tmap, R, t, beam_dirs(azimuths=1800, **VLP16), 100.0, 0.03, rng(2, 2))
+    xyz, rpy = gaussian_particles(rng(2, 10, n_particles), gxyz, grpy, n_particles, s_xyz=s_xyz, s_rpy_deg=s_rpy_deg)
+    return Workload(f"plain-local: 1024x1024x128@0.05m int16 warehouse, VLP-16 16x1800, N={n_particles} "
+                    f"Gaussian round the true pose ({s_xyz} m, {s_rpy_deg} deg)",
+                    tmap, pts, poses_soa(xyz, rpy), f32(tmap.tau / 2), resample_seed(2), (gxyz, grpy))
+
+
 def config3(n_particles=262_144, dtype="i16") -> Workload:
     sc, tmap = warehouse_map(2, keep_d64=True)
     if dtype != "i16":
