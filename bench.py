@@ -754,7 +754,8 @@ def served_setup(args, sw, torch, mcl, served):
 
     def make_robots():
         return [Robot(sp.rid, maps[sp.map_idx], host_scans[sp.map_idx][sp.scan_idx],
-                      served.sigma_for(sw.tmaps[sp.map_idx]), [(sw.global_updates, "global"), (None, "track")])
+                      served.sigma_for(sw.tmaps[sp.map_idx]), [(sw.global_updates, "global"), (None, "track")],
+                      map_id=sp.map_idx)
                 for sp in specs]
 
     return make_robots, init
@@ -776,10 +777,13 @@ def run_served(args):
     budget = int(args.budget_gib * (1 << 30))
     res = {}
     for name, kw in (("served", dict(plain=False, graph=args.graph)), ("plain_sequential", dict(plain=True))):
+        req_log = open(f"{args.request_log}.{name}.jsonl", "w") if args.request_log else None
         eng = Engine(make_robots(), init_particles, budget_bytes=budget, max_evals_per_tick=args.tick_evals, seed=5,
-                     n_streams=args.streams, depth=args.depth, order=args.order,
+                     n_streams=args.streams, depth=args.depth, order=args.order, log=req_log,
                      **kw)
         st = eng.run(sw.trace)
+        if req_log is not None:
+            req_log.close()
         res[name] = st.summary()
         log(f"{name}: {json.dumps(res[name])}")
         del eng
@@ -818,6 +822,8 @@ def main():
     ap.add_argument("--tick-evals", type=float, default=5e9, help="served: cap on particle-point evals per tick")
     ap.add_argument("--streams", type=int, default=2, help="served: streams")
     ap.add_argument("--depth", type=int, default=1, help="served: ticks in flight per stream")
+    ap.add_argument("--request-log", default="", help="served: write one JSON line per completed update to "
+                    "PREFIX.served.jsonl and PREFIX.plain_sequential.jsonl")
     ap.add_argument("--order", choices=("fifo", "stale"), default="stale",
                     help="served: oldest scan first, or the robot with the oldest last update first")
     ap.add_argument("--no-cpu-baseline", action="store_true")

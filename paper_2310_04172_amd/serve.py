@@ -39,6 +39,7 @@ a caller-supplied function of (robot, phase, stream) that calls the library.
 from __future__ import annotations
 
 import collections
+import json
 import time
 from dataclasses import dataclass, field
 
@@ -97,6 +98,10 @@ class Robot:
     evals_done: int = 0
     last_done: float = -1.0     # completion time of the last update (-1: none yet)
     ready: object = None        # event after the initialisation, until the first update is enqueued
+    map_id: int = -1            # which resident map (for the request log)
+    resident: float | None = None   # when the robot's current particle set was made resident
+    started: float | None = None    # when its update in flight was enqueued
+    tick_no: int = -1               # the tick that carries it
 
     @property
     def K(self):
@@ -155,11 +160,16 @@ class Engine:
     before the resampled set becomes the robot's particle set (tests read the
     update's inputs and outputs there).
     torch_module: the torch module the engine takes streams, events and buffers
-    from (default: torch itself; tests of the host logic pass a stand-in)."""
+    from (default: torch itself; tests of the host logic pass a stand-in).
+    log: optional text stream; one JSON line per completed update (robot, map,
+    phase, N, K, evaluations, tick, stream, and in seconds from the start of the
+    run the request's arrival, enqueue and completion and the time the robot's
+    particle set was made resident, which precedes the arrival for a robot that
+    stays resident between updates)."""
 
     def __init__(self, robots, init_particles, budget_bytes: int = 64 << 30, max_evals_per_tick: float = 1.2e11,
                  n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0, depth: int = 1,
-                 order: str = "fifo", on_complete=None, torch_module=None):
+                 order: str = "fifo", on_complete=None, torch_module=None, log=None):
         if torch_module is None:
             import torch as torch_module
         torch = self.torch = torch_module
@@ -171,6 +181,8 @@ class Engine:
         self.graph = graph and not plain
         self.seed = seed
         self.on_complete = on_complete
+        self.log = log
+        self._t0 = time.perf_counter()
         self.streams = [torch.cuda.Stream() for _ in range(1 if plain else n_streams)]
         self.copy_stream = torch.cuda.Stream()
         self.depth = 1 if plain else max(1, int(depth))    # ticks in flight per stream
@@ -197,6 +209,7 @@ class Engine:
             r.filt = mcl.Filter(r.map, r.points, r.poses, r.sigma, robot_seed(self.seed, r.rid), want_w=False)
         r.ready = torch.cuda.Event()
         r.ready.record(stream)
+        r.resident = time.perf_counter() - self._t0
         r.filt.poses_out = r.spare
         r.bytes = need
         self.used += need
@@ -209,13 +222,19 @@ class Engine:
         self.used -= r.bytes
         r.bytes = 0
 
-    def _finish(self, r: Robot, t_done: float):
+    def _finish(self, r: Robot, t_done: float, si: int):
         if self.on_complete is not None:
             self.on_complete(r, r.filt)
         self.stats.latencies_ms.append((t_done - r.in_flight) * 1e3)
         self.stats.phases.append(r.phase)
         self.stats.completed += 1
         n_evals = r.poses.shape[1] * r.K
+        if self.log is not None:
+            self.log.write(json.dumps({
+                "robot": r.rid, "map": r.map_id, "phase": r.phase, "N": int(r.poses.shape[1]), "K": int(r.K),
+                "evals": int(n_evals), "tick": r.tick_no, "stream": si, "arrival_s": r.in_flight,
+                "resident_s": r.resident, "enqueued_s": r.started, "done_s": t_done,
+                "latency_ms": (t_done - r.in_flight) * 1e3}) + "\n")
         self.stats.evals += n_evals
         r.evals_done += n_evals
         r.in_flight = None
@@ -278,7 +297,7 @@ class Engine:
         st = self.stats
         ref = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        t0 = self._t0 = time.perf_counter()
         ref.record()
         ref.synchronize()
         t_ref = time.perf_counter() - t0
@@ -302,7 +321,7 @@ class Engine:
                 if ev.query():
                     t_done = t_ref + ref.elapsed_time(ev) * 1e-3
                     for r in rs:
-                        self._finish(r, t_done)
+                        self._finish(r, t_done, si)
                     inflight.remove(item)
                     busy[si] -= 1
                     progressed = True
@@ -325,8 +344,10 @@ class Engine:
                 if batch:
                     self._upload(batch, s)
                     if self._submit(batch, s):
+                        t_sub = time.perf_counter() - t0
                         for r in batch:
                             r.in_flight, r.pending, r.ready = r.pending, None, None
+                            r.started, r.tick_no = t_sub, st.ticks
                         ev = torch.cuda.Event(enable_timing=True)
                         ev.record(s)
                         inflight.append((ev, batch, si))

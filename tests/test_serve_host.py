@@ -298,3 +298,32 @@ def test_request_order(lib, order):
     assert st.completed == 2
     # one request at a time: the robot whose particle set was made first went first
     assert made[0][0] == (0 if order == "fifo" else 1)
+
+
+def test_request_log_lines(lib):
+    """One JSON line per completed update, with the robot, map, phase, sizes,
+    tick and stream, and times ordered arrival <= enqueue <= completion; the
+    time the particle set became resident precedes the enqueue, and precedes
+    the arrival too once a tracking robot stays resident."""
+    import io
+    import json
+
+    robots, init, made = make(3, lib, phases=((1, "global"), (None, "track")), N=10, K=5)
+    for i, r in enumerate(robots):
+        r.map_id = i % 2
+    buf = io.StringIO()
+    eng = serve.Engine(robots, init, n_streams=2, max_evals_per_tick=2 * 10 * 5, torch_module=FakeTorch, log=buf)
+    st = run(eng, [(0.0, 0), (0.0, 1), (0.0, 2), (0.02, 0), (0.04, 0)])
+    lines = [json.loads(x) for x in buf.getvalue().splitlines()]
+    assert len(lines) == st.completed == 5 and st.dropped == 0
+    for x in lines:
+        assert x["map"] == x["robot"] % 2
+        assert x["N"] == 10 and x["K"] == 5 and x["evals"] == 50
+        assert x["arrival_s"] <= x["enqueued_s"] <= x["done_s"]
+        assert x["resident_s"] <= x["enqueued_s"]
+        assert abs(x["latency_ms"] - (x["done_s"] - x["arrival_s"]) * 1e3) < 1e-9
+        assert 0 <= x["tick"] < st.ticks and x["stream"] in (0, 1)
+    r0 = [x for x in lines if x["robot"] == 0]
+    assert [x["phase"] for x in r0] == ["global", "track", "track"]
+    # the global phase's set was released; the tracking set stayed resident
+    assert r0[0]["resident_s"] < r0[1]["resident_s"] == r0[2]["resident_s"] < r0[2]["arrival_s"]
