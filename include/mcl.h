@@ -412,6 +412,20 @@ mcl_status mcl_set_launch_config(int32_t dtype, int32_t K, int32_t N, const mcl_
  * else the default {4, 0, 0, 0, 0}. */
 mcl_status mcl_get_launch_config(int32_t dtype, int32_t K, int32_t N, mcl_launch_config *out);
 
+/* Launch shape of the normalisation and resampling (Sec. V-A, Sec. III):
+ * mcl_normalize and mcl_resample on a filter of at most max_n particles, and
+ * mcl_tick when none of its filters has more, run one workgroup per filter in
+ * one launch instead of a chain of three launches over the chip (six in a
+ * tick).  Both shapes perform the same floating-point operations in the same
+ * order, so every output is bit-identical either way; only the time differs.
+ * max_n in [0, 4096]; 0 turns the one-launch shape off; the default is 4096.
+ * Process-wide; a tick replayed from a graph uses the graph of the shape its
+ * filters select.  Errors: MCL_ERANGE for max_n out of range. */
+mcl_status mcl_set_weights_fused_max(int32_t max_n);
+
+/* The current max_n of mcl_set_weights_fused_max. */
+int32_t mcl_get_weights_fused_max(void);
+
 /* Test support: the voxel each (particle, point) pair reads, by the same
  * device code as mcl_sensor_update.  lin_idx: device output [N][K] int64,
  * i + nx*(j + ny*k), or -1 outside the map.  N*K must not exceed 2^31. */

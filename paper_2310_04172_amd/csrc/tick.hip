@@ -30,6 +30,9 @@ template <typename Src>
 mcl_status launch_resample_src(const Src &, int64_t, int64_t, hipStream_t);
 template <typename Src>
 mcl_status launch_estimate_src(const Src &, int64_t, int64_t, hipStream_t);
+template <bool NORM, bool RS, typename Src>
+mcl_status launch_weights_fused_src(const Src &, int, hipStream_t);
+int weights_fused_max();
 size_t weight_ws_bytes(int N);
 void bind_weight_ws(WeightJob &J, void *ws);
 
@@ -74,9 +77,10 @@ struct GraphKey {
     std::array<int64_t, kGroups> items;
     int64_t elems, blocks, eblocks, ejobs;
     std::array<int64_t, kGroups> lds;  // LDS bytes for the read bits of a group's shared map, or 0
+    int fused;                          // weights stage: one workgroup per filter (1) or the chains (0)
     bool operator<(const GraphKey &o) const {
-        return std::tie(mask, wpb, bpc, items, elems, blocks, eblocks, ejobs, lds) <
-               std::tie(o.mask, o.wpb, o.bpc, o.items, o.elems, o.blocks, o.eblocks, o.ejobs, o.lds);
+        return std::tie(mask, wpb, bpc, items, elems, blocks, eblocks, ejobs, lds, fused) <
+               std::tie(o.mask, o.wpb, o.bpc, o.items, o.elems, o.blocks, o.eblocks, o.ejobs, o.lds, o.fused);
     }
 };
 
@@ -354,7 +358,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     // replay serves any tick that fits; surplus waves exit at once).
     const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
     const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
-    GraphKey key{mask, {}, {}, {}, 0, 0, 0, 0, {}};
+    GraphKey key{mask, {}, {}, {}, 0, 0, 0, 0, {}, 0};
     for (int g = 0; g < kGroups; ++g) {
         key.wpb[g] = cfgs[g].waves_per_block;
         key.bpc[g] = cfgs[g].blocks_per_cu;
@@ -375,6 +379,11 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     key.blocks = use_graph ? bucket(wblk) : wblk;
     key.eblocks = use_graph ? bucket(eblk) : eblk;
     key.ejobs = use_graph ? bucket(ne) : ne;
+    {
+        int max_n = 0;
+        for (int j = 0; j < n_jobs; ++j) max_n = std::max(max_n, (int)jobs[j].N);
+        key.fused = max_n <= weights_fused_max();
+    }
     auto chain = [&]() -> mcl_status {
         for (int g = 0; g < kGroups; ++g) {
             if (!(mask >> g & 1)) continue;
@@ -391,14 +400,21 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             if (st != MCL_OK) return st;
         }
         JobTable<WeightJob> wsrc{dwt, dcnt + kWeightCnt};
-        mcl_status st = launch_normalize_src(wsrc, use_graph ? kMaxJobs : n_jobs, key.blocks, key.elems, stream);
+        // every filter has at least one weight block, so a tick that replays this
+        // graph has no more filters than key.blocks
+        const int fjobs = use_graph ? (int)std::min<int64_t>(key.blocks, kMaxJobs) : n_jobs;
+        if (key.fused && !key.ejobs) return launch_weights_fused_src<true, true>(wsrc, fjobs, stream);
+        mcl_status st = key.fused ? launch_weights_fused_src<true, false>(wsrc, fjobs, stream)
+                                  : launch_normalize_src(wsrc, use_graph ? kMaxJobs : n_jobs, key.blocks, key.elems,
+                                                         stream);
         if (st != MCL_OK) return st;
         if (key.ejobs) {
             JobTable<EstJob> esrc{reinterpret_cast<const EstJob *>(S.dev + kEstTblOff), dcnt + kEstCnt};
             st = launch_estimate_src(esrc, key.eblocks, key.ejobs, stream);
             if (st != MCL_OK) return st;
         }
-        return launch_resample_src(wsrc, key.blocks, key.elems, stream);
+        return key.fused ? launch_weights_fused_src<false, true>(wsrc, fjobs, stream)
+                         : launch_resample_src(wsrc, key.blocks, key.elems, stream);
     };
     // every map the tick reads: an event after its work (deferred mcl_map_free)
     auto note_uses = [&]() -> mcl_status {

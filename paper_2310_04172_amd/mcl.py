@@ -80,6 +80,9 @@ _lib.mcl_map_bytes.restype = C.c_size_t
 _lib.mcl_autotune.argtypes = [_P, _P, _I, _P, _I, C.c_float, _P, _P, C.POINTER(LaunchConfig)]
 _lib.mcl_set_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_get_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
+_lib.mcl_set_weights_fused_max.argtypes = [_I]
+_lib.mcl_get_weights_fused_max.argtypes = []
+_lib.mcl_get_weights_fused_max.restype = C.c_int32
 _lib.mcl_bench_gather_offsets.argtypes = [_P, _P, _I, _P, _I, _I, _P, _P]
 _lib.mcl_bench_gather_replay.argtypes = [_P, _P, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]
 _lib.mcl_bench_line_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, _I, C.c_uint32, _I, _P, C.c_size_t, _P]
@@ -90,6 +93,7 @@ for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_senso
            "mcl_sensor_update_noalloc", "mcl_sensor_update_sum", "mcl_normalize",
            "mcl_resample",
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_get_launch_config",
+           "mcl_set_weights_fused_max",
            "mcl_pose_estimate", "mcl_motion_update",
            "mcl_init_uniform", "mcl_init_gaussian", "mcl_debug_philox", "mcl_bench_gather_offsets",
            "mcl_bench_gather_replay", "mcl_bench_line_gather", "mcl_bench_stream_read", "mcl_bench_l1_gather"):
@@ -485,6 +489,19 @@ def set_launch_config(dtype: str, K: int, N: int, cfg=None):
     coarse: 0 auto, 1 global bytes, 2 LDS bits; runs: 0 automatic or a power of two <= 64."""
     c = None if cfg is None else C.byref(LaunchConfig(*cfg))
     _check(_lib.mcl_set_launch_config(DTYPE_CODE[dtype], K, N, c), "mcl_set_launch_config")
+
+
+def set_weights_fused_max(max_n: int):
+    """Filters of at most max_n particles normalise and resample with one
+    workgroup each in one launch (0: never); the results are the same bits
+    either way.  Returns the previous value."""
+    prev = int(_lib.mcl_get_weights_fused_max())
+    _check(_lib.mcl_set_weights_fused_max(int(max_n)), "mcl_set_weights_fused_max")
+    return prev
+
+
+def get_weights_fused_max() -> int:
+    return int(_lib.mcl_get_weights_fused_max())
 
 
 # ------------------------------------------------------------ measurement support

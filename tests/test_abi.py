@@ -127,6 +127,14 @@ def test_tick_and_tuning_argument_errors(mcl):
     assert lib.mcl_set_launch_config(0, 1000, 1000, C.byref(bad)) == mcl.MCL_EINVAL
     assert lib.mcl_set_launch_config(5, 1000, 1000, None) == mcl.MCL_EINVAL
     assert lib.mcl_autotune(None, None, 0, None, 0, 0.1, None, None, None) == mcl.MCL_EINVAL
+    # the one-launch weights limit: [0, 4096], host state only
+    prev = mcl.get_weights_fused_max()
+    assert prev == 4096
+    assert lib.mcl_set_weights_fused_max(-1) == mcl.MCL_ERANGE
+    assert lib.mcl_set_weights_fused_max(4097) == mcl.MCL_ERANGE
+    assert mcl.get_weights_fused_max() == prev
+    assert mcl.set_weights_fused_max(1000) == prev and mcl.get_weights_fused_max() == 1000
+    assert mcl.set_weights_fused_max(prev) == 1000
     # measurement calls: NULL arguments, sizes, sinks shorter than the grid
     assert lib.mcl_bench_gather_offsets(None, P(0x1000), 10, P(0x2000), 10, 0, P(0x3000), None) == mcl.MCL_EINVAL
     assert lib.mcl_bench_gather_replay(P(0x1000), P(0x2000), 100, 10, 1, 1, 1, P(0x3000), 256, None) == mcl.MCL_EINVAL

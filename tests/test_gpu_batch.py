@@ -156,6 +156,38 @@ def test_tick_max_jobs(torch, mcl, maps):
             assert_same(outputs(torch, f), single(torch, mcl, f), f"graph={graph} job {i} (N={f.N}, K={f.K})")
 
 
+def test_tick_one_launch_weights_equal_chains(torch, mcl, maps):
+    """The tick's weights stage with one workgroup per filter (all filters at
+    most the limit: one launch, or two around the pose estimates) and as the
+    launch chains (limit 0, or one filter above it): the same bits, eagerly and
+    replayed from graphs."""
+    say("case: tick weights stage, one launch vs chains")
+    prev = mcl.get_weights_fused_max()
+    specs = [(0, 1, 1), (1, 63, 1025), (2, 65, 9000), (0, 1000, 5000), (3, 130, 0), (1, 4096, 4096),
+             (2, 7, 4097), (0, 4095, 300), (3, 2000, 12000)]
+    s = torch.cuda.Stream()
+    try:
+        for est in (True, False):
+            results = []
+            for limit in (4096, 0, 1000):       # 1000: the larger filters take the chains
+                mcl.set_weights_fused_max(limit)
+                for graph in (False, True):
+                    filters = job_set(torch, mcl, 21, maps, specs)
+                    if not est:
+                        for f in filters:
+                            f.est_mean = f.est_idx = f.est_pose = None
+                    torch.cuda.synchronize()
+                    with torch.cuda.stream(s):
+                        mcl.tick(filters, graph=graph, stream=s)
+                    s.synchronize()
+                    results.append((limit, graph, [outputs(torch, f) for f in filters]))
+            for limit, graph, got in results[1:]:
+                for i in range(len(specs)):
+                    assert_same(got[i], results[0][2][i], f"est={est} limit={limit} graph={graph} job {i}")
+    finally:
+        mcl.set_weights_fused_max(prev)
+
+
 def test_launch_shapes_are_bit_identical(torch, mcl, tmp_path, monkeypatch):
     say("case: launch shapes")
     cache = tmp_path / "tune.txt"
