@@ -210,3 +210,21 @@ def test_tune_cache_is_read_back(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True).stdout
     lines = out.strip().splitlines()
     assert lines == ["(2, 8, 1, 4, 5)", "(2, 4, 0, 1, 7)", "(4, 0, 0, 0, 0)"], out
+
+
+def test_c_consumer_builds(tmp_path):
+    """The plain-C consumer (tests/c/mcl_consumer.c: mcl.h and the HIP runtime's
+    C API only) compiles as C11 without warnings and links to the library; the
+    GPU test runs it."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    if gcc is None or not os.path.exists(os.path.join(rocm, "include", "hip", "hip_runtime_api.h")):
+        pytest.skip("gcc or the HIP headers not available")
+    pkg = os.path.join(ROOT, "paper_2310_04172_amd")
+    r = subprocess.run([gcc, "-std=c11", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                        f"-I{rocm}/include", f"-I{os.path.join(ROOT, 'include')}",
+                        os.path.join(ROOT, "tests", "c", "mcl_consumer.c"), "-o", str(tmp_path / "mcl_consumer"),
+                        f"-L{rocm}/lib", "-lamdhip64", f"-L{pkg}", "-lmcl"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
