@@ -780,7 +780,7 @@ def run_served(args):
         req_log = open(f"{args.request_log}.{name}.jsonl", "w") if args.request_log else None
         eng = Engine(make_robots(), init_particles, budget_bytes=budget, max_evals_per_tick=args.tick_evals, seed=5,
                      n_streams=args.streams, depth=args.depth, order=args.order, log=req_log,
-                     **kw)
+                     small_lane_evals=args.small_lane_evals if not kw["plain"] else None, **kw)
         st = eng.run(sw.trace)
         if req_log is not None:
             req_log.close()
@@ -798,7 +798,8 @@ def run_served(args):
                                    "host memory on a copy stream",
                        "trace_s": args.trace_seconds, "robots": len(sw.robots), "budget_GiB": args.budget_gib,
                        "graph": args.graph, "tick_evals_cap": args.tick_evals,
-                       "streams": args.streams, "depth": args.depth, "order": args.order})
+                       "streams": args.streams, "depth": args.depth, "order": args.order,
+                       "small_lane_evals": args.small_lane_evals})
     out["steps"] = sv["completed"]
     out["warmup"] = 0
     out["latency_ms"] = {f"p{q}": sv[f"p{q}_ms"] for q in (10, 50, 90, 99)}
@@ -822,6 +823,8 @@ def main():
     ap.add_argument("--tick-evals", type=float, default=5e9, help="served: cap on particle-point evals per tick")
     ap.add_argument("--streams", type=int, default=2, help="served: streams")
     ap.add_argument("--depth", type=int, default=1, help="served: ticks in flight per stream")
+    ap.add_argument("--small-lane-evals", type=float, default=None,
+                    help="served: stream 0 takes only requests of at most this many evaluations")
     ap.add_argument("--request-log", default="", help="served: write one JSON line per completed update to "
                     "PREFIX.served.jsonl and PREFIX.plain_sequential.jsonl")
     ap.add_argument("--order", choices=("fifo", "stale"), default="stale",

@@ -165,11 +165,15 @@ class Engine:
     phase, N, K, evaluations, tick, stream, and in seconds from the start of the
     run the request's arrival, enqueue and completion and the time the robot's
     particle set was made resident, which precedes the arrival for a robot that
-    stays resident between updates)."""
+    stays resident between updates).
+    small_lane_evals: optional; with two or more streams, stream 0 takes only
+    requests of at most this many particle-point evaluations (the other streams
+    take any), so small updates (tracking) never queue behind large ones (global
+    localisation) for a stream; it stays idle while no small request waits."""
 
     def __init__(self, robots, init_particles, budget_bytes: int = 64 << 30, max_evals_per_tick: float = 1.2e11,
                  n_streams: int = 2, plain: bool = False, graph: bool = False, seed: int = 0, depth: int = 1,
-                 order: str = "fifo", on_complete=None, torch_module=None, log=None):
+                 order: str = "fifo", on_complete=None, torch_module=None, log=None, small_lane_evals=None):
         if torch_module is None:
             import torch as torch_module
         torch = self.torch = torch_module
@@ -189,6 +193,9 @@ class Engine:
         if order not in ("fifo", "stale"):
             raise ValueError("order must be 'fifo' or 'stale'")
         self.order = order
+        if small_lane_evals is not None and len(self.streams) < 2:
+            raise ValueError("a small-request lane needs two or more streams")
+        self.small_lane = None if small_lane_evals is None else float(small_lane_evals)
         self.used = 0
         self.stats = ServeStats()
 
@@ -326,15 +333,21 @@ class Engine:
                     busy[si] -= 1
                     progressed = True
             free = [i for i, b in enumerate(busy) if b < self.depth]
-            if free:
-                si = free[0]
+            key = (lambda r: r.pending) if self.order == "fifo" else (lambda r: (r.last_done, r.pending))
+            cands = sorted((r for r in self.robots if r.pending is not None and r.in_flight is None), key=key) \
+                if free else []
+            # the small-request lane (stream 0) is tried first, then the other free streams
+            for si in free:
                 s = self.streams[si]
-                key = (lambda r: r.pending) if self.order == "fifo" else (lambda r: (r.last_done, r.pending))
-                cands = sorted((r for r in self.robots if r.pending is not None and r.in_flight is None), key=key)
+                lane = self.small_lane is not None and si == 0
                 batch, evals = [], 0.0
                 for r in cands:
+                    if r.in_flight is not None:      # taken by the other stream in this pass
+                        continue
                     e = self.init_particles(r, r.phase, s, probe=True) * r.K if r.filt is None else \
                         r.poses.shape[1] * r.K
+                    if lane and e > self.small_lane:
+                        continue
                     if batch and (self.plain or evals + e > self.max_evals):
                         break
                     if not self._admit(r, s):
@@ -356,6 +369,8 @@ class Engine:
                         progressed = True
                     else:
                         st.busy += 1
+                if self.small_lane is None:
+                    break                            # one stream per pass, as before the lane existed
             if ptr >= len(trace) and not inflight and (not drain or not any(
                     r.pending is not None for r in self.robots)):
                 break

@@ -327,3 +327,40 @@ def test_request_log_lines(lib):
     assert [x["phase"] for x in r0] == ["global", "track", "track"]
     # the global phase's set was released; the tracking set stayed resident
     assert r0[0]["resident_s"] < r0[1]["resident_s"] == r0[2]["resident_s"] < r0[2]["arrival_s"]
+
+
+def test_small_request_lane(lib):
+    """With a small-request lane, stream 0 takes only requests of at most the
+    lane's evaluations and the other stream any: the large request (robot 0,
+    1000 particles) runs on stream 1 while the small ones (robots 1 and 2, 10
+    particles) run together on stream 0 in the same pass; a lone large request
+    leaves stream 0 idle.  Without the lane the first free stream takes the
+    oldest request, large or small."""
+    K = 5
+    sizes = {0: 1000, 1: 10, 2: 10}
+
+    def init(r, phase, stream, probe=False):
+        return sizes[r.rid] if probe else FakeTensor((12, sizes[r.rid]), "init")
+
+    def robots():
+        return [serve.Robot(i, "map", FakeTensor((3, K), "host"), 0.1, [(None, "track")]) for i in range(3)]
+
+    eng = serve.Engine(robots(), init, n_streams=2, max_evals_per_tick=1e9, torch_module=FakeTorch,
+                       small_lane_evals=100)
+    st = eng.run([(0.0, 0), (0.0, 1), (0.0, 2)])
+    assert st.completed == 3
+    on = {rid: s for s, jobs in lib.ticks for rid, _, _ in jobs}
+    assert on[0] is eng.streams[1] and on[1] is eng.streams[0] and on[2] is eng.streams[0]
+    assert len(lib.ticks) == 2
+    # a lone large request: stream 0 never runs it
+    lib.ticks.clear()
+    eng = serve.Engine(robots(), init, n_streams=2, torch_module=FakeTorch, small_lane_evals=100)
+    eng.run([(0.0, 0), (0.01, 0), (0.02, 0)])
+    assert lib.ticks and all(s is eng.streams[1] for s, _ in lib.ticks)
+    # without the lane: oldest first on the first free stream, one stream per pass
+    lib.ticks.clear()
+    eng = serve.Engine(robots(), init, n_streams=2, max_evals_per_tick=1e9, torch_module=FakeTorch)
+    eng.run([(0.0, 0), (0.0, 1), (0.0, 2)])
+    assert lib.ticks[0][0] is eng.streams[0] and lib.ticks[0][1][0][0] == 0
+    with pytest.raises(ValueError):
+        serve.Engine(robots(), init, n_streams=1, torch_module=FakeTorch, small_lane_evals=100)
