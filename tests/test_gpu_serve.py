@@ -2,8 +2,8 @@
 
 * Every robot's result is the same served in the mix as replayed alone with the
   single-filter calls (bit for bit), under a memory budget small enough to make
-  robots wait for admission, with two streams, one stream two ticks deep, and
-  both request orders.
+  robots wait for admission, with two streams, one stream two ticks deep, both
+  request orders, and a small-request lane.
 * On the served workload's four maps at their particle-count ranges, every
   completed update is checked against the CPU oracle as it completes.
 """
@@ -39,14 +39,15 @@ def setup(torch, mcl, sw, n_global_updates, seed=11):
     return maps, init, robots, phases
 
 
-@pytest.mark.parametrize("n_streams,depth,order", [(2, 1, "fifo"), (1, 2, "fifo"), (2, 1, "stale")])
-def test_served_equals_alone(n_streams, depth, order):
+@pytest.mark.parametrize("n_streams,depth,order,lane", [(2, 1, "fifo", None), (1, 2, "fifo", None),
+                                                       (2, 1, "stale", None), (2, 1, "stale", 1e8)])
+def test_served_equals_alone(n_streams, depth, order, lane):
     import torch
     from paper_2310_04172_amd import mcl
     from paper_2310_04172_amd.serve import Engine, Robot, robot_seed
     from workloads import served
 
-    say(f"case: served engine, small trace, {n_streams} streams x {depth} ticks, order {order}")
+    say(f"case: served engine, small trace, {n_streams} streams x {depth} ticks, order {order}, lane {lane}")
     sw = served.build(n_robots=12, trace_s=2.0, rate_hz=10.0, scans_per_map=2, map_subset=[0, 3])
     for sp in sw.robots:          # keep the test small: scale particle counts down
         sp.n_global = 1 + sp.n_global // 64
@@ -54,7 +55,7 @@ def test_served_equals_alone(n_streams, depth, order):
     maps, init, robots, phases = setup(torch, mcl, sw, 3)
     big = max(mcl.job_bytes(sp.n_global, sw.scans[sp.map_idx][sp.scan_idx].shape[1]) for sp in sw.robots)
     eng = Engine(robots(), init, budget_bytes=3 * big, max_evals_per_tick=2e9, seed=9, n_streams=n_streams,
-                 depth=depth, order=order)
+                 depth=depth, order=order, small_lane_evals=lane)
     st = eng.run(sw.trace)
     summ = st.summary()
     say(f"served: {summ}")
