@@ -482,6 +482,63 @@ def run_estimate(args):
     return out
 
 
+WEIGHTS_N = (64, 256, 1000, 2048, 4096)
+
+
+def run_weights(args):
+    """Normalisation + resampling of one small filter (log-weights normal round
+    -50, sd 2; seeded), as one launch each (one workgroup, the default up to
+    4,096 particles) and as the three-launch chains (mcl_set_weights_fused_max(0)):
+    per N, 200 back-to-back call pairs after 10 warm-up ones, timed with HIP
+    events on the stream (GPU time per pair including the launch gaps)."""
+    import torch
+    from paper_2310_04172_amd import mcl
+
+    stream = torch.cuda.current_stream()
+    prev = mcl.get_weights_fused_max()
+    res = {}
+    try:
+        for N in WEIGHTS_N:
+            g = torch.Generator(device="cuda")
+            g.manual_seed(N)
+            lw = (torch.randn(N, generator=g, device="cuda") * 2.0 - 50.0).float()
+            poses = torch.randn((12, N), generator=g, device="cuda")
+            w = torch.empty(N, dtype=torch.float64, device="cuda")
+            wq = torch.empty(N, dtype=torch.uint64, device="cuda")
+            lz = torch.empty(1, dtype=torch.float64, device="cuda")
+            idx = torch.empty(N, dtype=torch.int32, device="cuda")
+            pout = torch.empty_like(poses)
+            row = {}
+            for shape, limit in (("one_launch", 4096), ("chains", 0)):
+                mcl.set_weights_fused_max(limit)
+
+                def pair():
+                    mcl.normalize(lw, w, wq, lz, stream=stream)
+                    mcl.resample(wq, 1, 2, poses, pout, idx, stream=stream)
+                for _ in range(10):
+                    pair()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(200):
+                    pair()
+                b.record(stream)
+                torch.cuda.synchronize()
+                row[shape + "_us"] = a.elapsed_time(b) * 1e3 / 200
+            res[str(N)] = row
+            log(f"N={N}: one launch {row['one_launch_us']:.1f} us, chains {row['chains_us']:.1f} us per pair")
+    finally:
+        mcl.set_weights_fused_max(prev)
+    N = 1000
+    out = base_record(args, "normalise + resample: particles/s (G/s)", N / (res[str(N)]["one_launch_us"] * 1e-6) / 1e9,
+                      res[str(N)]["one_launch_us"] * 1e-3,
+                      {"workload": "normalise + resample of one small filter, N = 64 .. 4096, one launch vs chains",
+                       "per_N": res}, dtype="f64")
+    out["unit"] = "G particles/s"
+    out["steps"] = 200
+    out["warmup"] = 10
+    return out
+
+
 NSWEEP = (1024, 4096, 16384, 50000, 100000, 262144, 1048576, 2097152)
 
 
@@ -815,7 +872,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="global", choices=["global", "converged", "small", "batched", "served", "precision", "estimate", "trilinear", "loop",
-                                                    "sparse", "sum", "nsweep"])
+                                                    "sparse", "sum", "nsweep", "weights"])
     ap.add_argument("--robots", type=int, default=256)
     ap.add_argument("--trace-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -857,6 +914,8 @@ def main():
         out = run_loop(args)
     elif args.workload == "nsweep":
         out = run_nsweep(args)
+    elif args.workload == "weights":
+        out = run_weights(args)
     else:
         t0 = time.perf_counter()
         w = (configs.config1() if args.workload == "small" else

@@ -115,6 +115,8 @@ class Robot:
 @dataclass
 class ServeStats:
     latencies_ms: list = field(default_factory=list)
+    waits_ms: list = field(default_factory=list)    # arrival to enqueue (waiting for a stream / admission)
+    service_ms: list = field(default_factory=list)  # enqueue to completion (its tick, and ticks queued before it)
     phases: list = field(default_factory=list)      # the robot's phase of each completed update
     completed: int = 0
     dropped: int = 0
@@ -138,14 +140,20 @@ class ServeStats:
                 "by_phase": self.by_phase()}
 
     def by_phase(self) -> dict:
-        """Completed updates and their p50 / p99 latency per robot phase."""
+        """Completed updates per robot phase: p50 / p99 of the latency and of its
+        two parts, the wait for a stream and the service once enqueued."""
         out = {}
         ph = np.asarray(self.phases)
-        lat = np.asarray(self.latencies_ms)
+        parts = {"": np.asarray(self.latencies_ms), "wait_": np.asarray(self.waits_ms),
+                 "service_": np.asarray(self.service_ms)}
         for name in sorted(set(self.phases)):
-            x = lat[ph == name]
-            out[name] = {"completed": int(x.size), "p50_ms": float(np.percentile(x, 50)),
-                         "p99_ms": float(np.percentile(x, 99))}
+            sel = ph == name
+            d = {"completed": int(sel.sum())}
+            for pre, a in parts.items():
+                if a.size == ph.size:
+                    d[f"{pre}p50_ms"] = float(np.percentile(a[sel], 50))
+                    d[f"{pre}p99_ms"] = float(np.percentile(a[sel], 99))
+            out[name] = d
         return out
 
 
@@ -233,6 +241,8 @@ class Engine:
         if self.on_complete is not None:
             self.on_complete(r, r.filt)
         self.stats.latencies_ms.append((t_done - r.in_flight) * 1e3)
+        self.stats.waits_ms.append((r.started - r.in_flight) * 1e3)
+        self.stats.service_ms.append((t_done - r.started) * 1e3)
         self.stats.phases.append(r.phase)
         self.stats.completed += 1
         n_evals = r.poses.shape[1] * r.K

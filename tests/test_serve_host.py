@@ -327,6 +327,12 @@ def test_request_log_lines(lib):
     assert [x["phase"] for x in r0] == ["global", "track", "track"]
     # the global phase's set was released; the tracking set stayed resident
     assert r0[0]["resident_s"] < r0[1]["resident_s"] == r0[2]["resident_s"] < r0[2]["arrival_s"]
+    # the statistics split each latency into the wait for a stream and the service
+    for lat, w, sv in zip(st.latencies_ms, st.waits_ms, st.service_ms):
+        assert w >= 0 and sv >= 0 and abs(lat - (w + sv)) < 1e-9
+    bp = st.by_phase()
+    assert set(bp) == {"global", "track"} and bp["global"]["completed"] == 3
+    assert all(k in bp["track"] for k in ("p99_ms", "wait_p50_ms", "wait_p99_ms", "service_p50_ms", "service_p99_ms"))
 
 
 def test_small_request_lane(lib):
