@@ -251,7 +251,7 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
     log(f"step {ms_step:.3f} ms, sensor kernel {sensor_ms:.3f} ms")
     est = time_estimate(torch, mcl, logw, poses, stream)
     log(f"pose estimate {est['us']:.2f} us, {est['achieved_GBs']:.0f} GB/s")
-    tick_lat = None
+    tick_lat = cap_lat = None
     if workload_key == "small":
         # the same update as one graph-replayed tick (one call, one launch of
         # a captured chain): the latency a small filter sees on the batched path
@@ -268,6 +268,31 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
                 tl.append((time.perf_counter() - t1) * 1e3)
         tick_lat = {"p50": percentile(tl, 50), "p99": percentile(tl, 99), "mean": float(np.mean(tl))}
         log(f"graph-replayed tick: p50 {tick_lat['p50']:.3f} ms, p99 {tick_lat['p99']:.3f} ms")
+        # the same update captured by the caller into a graph: the no-allocation
+        # sensor update, normalise and resample enqueue kernels only
+        cap = torch.cuda.Stream()
+
+        def update():
+            mcl.sensor_update_noalloc(m, pts, poses, w.sigma, logw, stream=cap)
+            mcl.normalize(logw, None, wq, lz, want_w=False, stream=cap)
+            mcl.resample(wq, w.seed, 0, poses, poses_out, idx, cap)
+        with torch.cuda.stream(cap):
+            update()              # the weights stage's workspace on this stream exists from here on
+        cap.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=cap):
+            update()
+        torch.cuda.synchronize()
+        cl = []
+        for i in range(args.warmup + args.steps):
+            t1 = time.perf_counter()
+            graph.replay()
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                cl.append((time.perf_counter() - t1) * 1e3)
+        del graph
+        cap_lat = {"p50": percentile(cl, 50), "p99": percentile(cl, 99), "mean": float(np.mean(cl))}
+        log(f"caller-captured update: p50 {cap_lat['p50']:.3f} ms, p99 {cap_lat['p99']:.3f} ms")
     if args.copy_calib_mib:
         n = args.copy_calib_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -288,6 +313,8 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
     out["latency_ms"] = spread(lat)
     if tick_lat:
         out["tick_graph_latency_ms"] = tick_lat
+    if cap_lat:
+        out["captured_update_latency_ms"] = cap_lat
     out["pose_estimate"] = est
     if sparse_info:
         out["config"]["sparse_map"] = sparse_info

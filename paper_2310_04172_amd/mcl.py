@@ -219,6 +219,22 @@ def sensor_update(m: Map, points, poses, sigma: float, logw=None, stream=None):
     return logw
 
 
+def sensor_update_noalloc(m: Map, points, poses, sigma: float, logw, stream=None):
+    """mcl_sensor_update's result, computed with the library's fixed scratch
+    array instead of a workspace (no device allocation; for graph capture).
+    logw must be given, since allocating it would defeat the purpose."""
+    import torch
+    K = points.shape[1] if points is not None else 0
+    N = poses.shape[1]
+    _dev(poses, torch.float32, (12, N), "poses")
+    if K:
+        _dev(points, torch.float32, (3, K), "points")
+    _dev(logw, torch.float32, (N,), "logw")
+    _check(_lib.mcl_sensor_update_noalloc(m.handle, _ptr(points) if K else None, K, _ptr(poses), N,
+                                          float(sigma), _ptr(logw), _stream(stream)), "mcl_sensor_update_noalloc")
+    return logw
+
+
 def sensor_update_sum(m: Map, points, poses, sigma: float, logw=None, stream=None):
     """logw [N] float32 = log sum_k exp(-(1/(2 sigma^2)) m(x_n, z_k)^2), the sum
     reading of the sensor model (see include/mcl.h)."""
