@@ -49,6 +49,7 @@ struct SensorJob {
     int32_t score;        // kScoreProduct or kScoreSum (how the points' likelihoods combine)
     float k2;             // sum reading: -c log2(e), so a point's likelihood is 2^(k2 q^2)
     int32_t pad_;
+    const float *pc;      // [N][12] the particles' pose constants, or null: broadcast from the lanes
 };
 
 // How a particle's points combine: the product of their likelihoods (l = -c sum q^2)

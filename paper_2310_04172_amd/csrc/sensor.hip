@@ -19,6 +19,7 @@
 // 6-level wave tree, 4 chunks per piece in order, pairwise over pieces): the
 // same particle gives the same bits whatever N, grid or batch it runs in.
 #include <algorithm>
+#include <type_traits>
 
 #include "jobs.h"
 #include "voxel.h"
@@ -357,19 +358,42 @@ __device__ __attribute__((always_inline)) inline float lane_chunk_sum_sparse(con
 // Lookup kinds of the sensor kernel (sparse: pools below / above 4 GiB).
 constexpr int kLookNearest = 0, kLookTrilinear = 1, kLookSparse = 2, kLookSparseWide = 3, kLookNearestLds = 4;
 
-// Particles [p0, p1) of the wave's group against one chunk, with lookup LK
-// (kLookNearestLds here: the coarse level read from LDS).  probe: count the
-// in-place reads of the nearest lookup into *nmixed (wave-uniform).
-template <typename T, bool TAIL, int LK, bool SUM>
+// Particles [p0, p1) of the wave's group (particles n0 + p) against one chunk,
+// with lookup LK (kLookNearestLds here: the coarse level read from LDS).
+// probe: count the in-place reads of the nearest lookup into *nmixed
+// (wave-uniform).  A particle's 12 pose constants, the same for every lane,
+// come into scalar registers: with PCT by scalar loads from the job's table of
+// them, issued one particle ahead so that they arrive while the previous
+// particle's lookups run (no vector instruction), else by a read of lane p's
+// registers (one vector instruction each); the values, and so the results, are
+// the same.
+template <typename T, bool TAIL, int LK, bool SUM, bool PCT = false>
 __device__ __attribute__((always_inline)) inline void chunk_range(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
-                                   int p0, int p1, float &acc, const uint32_t *sbits, bool probe = false,
+                                   int p0, int p1, float &acc, const uint32_t *sbits, int n0, bool probe = false,
                                    int *nmixed = nullptr) {
     static_assert(!SUM || LK == kLookNearest || LK == kLookNearestLds, "the sum reading has the nearest lookup only");
+    typedef const __attribute__((address_space(4))) float *cptr;
+    float nx[12];  // with the table: the next particle's constants, loaded one particle ahead
+    if constexpr (PCT) {
+        if (p0 < p1) {
+            cptr q = (cptr)(J.pc + (size_t)(n0 + p0) * 12);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) nx[j] = q[j];
+        }
+    }
     for (int p = p0; p < p1; ++p) {
         float A[12];
+        if constexpr (PCT) {
 #pragma unroll
-        for (int j = 0; j < 12; ++j) A[j] = bcast(pa[j], p);
+            for (int j = 0; j < 12; ++j) A[j] = nx[j];
+            cptr q = (cptr)(J.pc + (size_t)(n0 + min(p + 1, p1 - 1)) * 12);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) nx[j] = q[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 12; ++j) A[j] = bcast(pa[j], p);
+        }
         float t;
         if constexpr (LK == kLookTrilinear)
             t = wave_sum(lane_chunk_sum_tri<T, TAIL>(J.tri, A, px, py, pz, lane, nvalid));
@@ -391,25 +415,25 @@ __device__ __attribute__((always_inline)) inline void chunk_range(const SensorJo
 // most points land in the band, and LDS saves a gather per point), else stay
 // on the global masks (global localisation: most points read the shared
 // sentinel line, and the global path issues fewer instructions).
-template <typename T, bool TAIL, int LK, bool SUM>
+template <typename T, bool TAIL, int LK, bool SUM, bool PCT = false>
 __device__ __attribute__((always_inline)) inline void chunk_group(const SensorJob &J, const float (&pa)[12], const float (&px)[kU],
                                    const float (&py)[kU], const float (&pz)[kU], int lane, int nvalid,
-                                   int p0, int p1, float &acc, const uint32_t *sbits) {
+                                   int p0, int p1, float &acc, const uint32_t *sbits, int n0) {
     if constexpr (LK == kLookNearestLds) {
         int q0 = p0;
         bool lds = J.coarse == kCoarseBits;
         if (J.coarse == kCoarseAuto) {
             int nmixed = 0;
             q0 = min(p0 + kProbe, p1);
-            chunk_range<T, TAIL, kLookNearest, SUM>(J, pa, px, py, pz, lane, nvalid, p0, q0, acc, sbits, true, &nmixed);
+            chunk_range<T, TAIL, kLookNearest, SUM, PCT>(J, pa, px, py, pz, lane, nvalid, p0, q0, acc, sbits, n0, true, &nmixed);
             lds = nmixed * 8 > J.lds8 * kChunk * (q0 - p0);
         }
         if (lds)
-            chunk_range<T, TAIL, kLookNearestLds, SUM>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
+            chunk_range<T, TAIL, kLookNearestLds, SUM, PCT>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits, n0);
         else
-            chunk_range<T, TAIL, kLookNearest, SUM>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits);
+            chunk_range<T, TAIL, kLookNearest, SUM, PCT>(J, pa, px, py, pz, lane, nvalid, q0, p1, acc, sbits, n0);
     } else {
-        chunk_range<T, TAIL, LK, SUM>(J, pa, px, py, pz, lane, nvalid, p0, p1, acc, sbits);
+        chunk_range<T, TAIL, LK, SUM, PCT>(J, pa, px, py, pz, lane, nvalid, p0, p1, acc, sbits, n0);
     }
 }
 
@@ -432,7 +456,7 @@ __device__ __attribute__((always_inline)) inline ItemPos item_pos(const SensorJo
 
 // One work item: particles 64 g + [p0, p1) of a job against points
 // [4096 piece, 4096 piece + 4096).  Returns lane p's sum for particle 64 g + p.
-template <typename T, int LK, bool SUM>
+template <typename T, int LK, bool SUM, bool PCT = false>
 __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJob &J, int local, int lane,
                                                                    const uint32_t *sbits) {
     const ItemPos ip = item_pos(J, local);
@@ -442,8 +466,8 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
     const MapView &m = J.map;
     const int K = J.K;
 
-    float pa[12];
-    pose_consts(J.poses, J.N, n0 + min(lane, gcount - 1), m, pa);
+    float pa[12];  // this lane's particle's pose constants (read only without the table)
+    if constexpr (!PCT) pose_consts(J.poses, J.N, n0 + min(lane, gcount - 1), m, pa);
 
     float acc = 0.0f;
     const int kb = piece * kPiece;
@@ -459,9 +483,9 @@ __device__ __attribute__((always_inline)) inline float sensor_item(const SensorJ
             pz[u] = gp(J.pts)[(size_t)2 * K + k];
         }
         if (nvalid == kChunk)
-            chunk_group<T, false, LK, SUM>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits);
+            chunk_group<T, false, LK, SUM, PCT>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits, n0);
         else
-            chunk_group<T, true, LK, SUM>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits);
+            chunk_group<T, true, LK, SUM, PCT>(J, pa, px, py, pz, lane, nvalid, ip.p0, ip.p1, acc, sbits, n0);
     }
     return acc;
 }
@@ -491,7 +515,7 @@ __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJ
 // wave for a full grid, several for a persistent one).  The job descriptor is
 // read into scalar registers per item and read again for the store, so it need
 // not stay live across the item.
-template <typename T, int WPB, typename Src, int LK = kLookNearest, bool SUM = false>
+template <typename T, int WPB, typename Src, int LK = kLookNearest, bool SUM = false, bool PCT = false>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == kLookTrilinear ? 2 : (LK == kLookNearest || LK == kLookNearestLds || LK == kLookSparse) ? 4 : 3))) void sensor_kernel(Src src) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nitems = src.items();
@@ -525,7 +549,7 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == 
         {
             const SensorJob J = src.load(j);
             local = (int)(item - J.item0);
-            acc = sensor_item<T, LK, SUM>(J, local, lane, sbits);
+            acc = sensor_item<T, LK, SUM, PCT>(J, local, lane, sbits);
         }
         const SensorJob J = src.load(j);
         sensor_store<SUM>(J, local, lane, acc);
@@ -554,6 +578,18 @@ __global__ __launch_bounds__(256) void combine_kernel(Src src) {
         while (depth > 0) s = stack[--depth] + s;
         J.logw[n] = J.score == kScoreSum ? particle_logw<true>(J, s) : particle_logw<false>(J, s);
     }
+}
+
+// The pose constants of every particle (pose prologue), by the same device code
+// the lanes use, into a table the sensor kernel reads with scalar loads.
+__global__ __launch_bounds__(256) void pose_consts_kernel(MapView m, const float *__restrict__ poses, int N,
+                                                          float *__restrict__ pc) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    float pa[12];
+    pose_consts(poses, N, n, m, pa);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) pc[(size_t)n * 12 + j] = pa[j];
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ out, int n, float v) {
@@ -618,29 +654,48 @@ static int lds_waves_per_block(int wpb, size_t lds) {
 
 // nitems: the item count when known on the host (sizes a one-wave-per-item
 // grid); a persistent grid does not need it.
-template <typename T, typename Src, int LK = kLookNearest, bool SUM = false>
+template <typename T, typename Src, int LK = kLookNearest, bool SUM = false, bool PCT = false>
 static void launch_sensor_t(const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream, size_t lds = 0) {
     const int wpb = lds_waves_per_block(cfg.waves_per_block, lds);
     int64_t blocks = (nitems + wpb - 1) / wpb;
     if (cfg.blocks_per_cu > 0) blocks = std::min<int64_t>(blocks, (int64_t)device_cus() * cfg.blocks_per_cu);
     if (blocks < 1) blocks = 1;
     switch (wpb) {
-        case 2: sensor_kernel<T, 2, Src, LK, SUM><<<(unsigned)blocks, 128, lds, stream>>>(src); break;
-        case 8: sensor_kernel<T, 8, Src, LK, SUM><<<(unsigned)blocks, 512, lds, stream>>>(src); break;
-        default: sensor_kernel<T, 4, Src, LK, SUM><<<(unsigned)blocks, 256, lds, stream>>>(src); break;
+        case 2: sensor_kernel<T, 2, Src, LK, SUM, PCT><<<(unsigned)blocks, 128, lds, stream>>>(src); break;
+        case 8: sensor_kernel<T, 8, Src, LK, SUM, PCT><<<(unsigned)blocks, 512, lds, stream>>>(src); break;
+        default: sensor_kernel<T, 4, Src, LK, SUM, PCT><<<(unsigned)blocks, 256, lds, stream>>>(src); break;
     }
 }
+
+template <typename Src, bool SUM, bool PCT>
+static void launch_sensor_dense(int32_t dtype, const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream,
+                                size_t lds) {
+    if (lds > 0) {
+        if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearestLds, SUM, PCT>(src, nitems, cfg, stream, lds);
+        else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearestLds, SUM, PCT>(src, nitems, cfg, stream, lds);
+        else launch_sensor_t<float, Src, kLookNearestLds, SUM, PCT>(src, nitems, cfg, stream, lds);
+    } else if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearest, SUM, PCT>(src, nitems, cfg, stream);
+    else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearest, SUM, PCT>(src, nitems, cfg, stream);
+    else launch_sensor_t<float, Src, kLookNearest, SUM, PCT>(src, nitems, cfg, stream);
+}
+
+// A single filter whose pose-constant table was filled (pc set) reads it with
+// scalar loads; batched jobs and the no-allocation call broadcast from lanes.
+template <typename S>
+struct single_filter : std::false_type {};
+template <typename J>
+struct single_filter<OneJob<J>> : std::true_type {};
 
 template <typename Src, bool SUM>
 static void launch_sensor_dense(int32_t dtype, const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream,
                                 size_t lds) {
-    if (lds > 0) {
-        if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearestLds, SUM>(src, nitems, cfg, stream, lds);
-        else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearestLds, SUM>(src, nitems, cfg, stream, lds);
-        else launch_sensor_t<float, Src, kLookNearestLds, SUM>(src, nitems, cfg, stream, lds);
-    } else if (dtype == MCL_TSDF_I16) launch_sensor_t<int16_t, Src, kLookNearest, SUM>(src, nitems, cfg, stream);
-    else if (dtype == MCL_TSDF_I8) launch_sensor_t<int8_t, Src, kLookNearest, SUM>(src, nitems, cfg, stream);
-    else launch_sensor_t<float, Src, kLookNearest, SUM>(src, nitems, cfg, stream);
+    if constexpr (single_filter<Src>::value) {
+        if (src.job.pc) {
+            launch_sensor_dense<Src, SUM, true>(dtype, src, nitems, cfg, stream, lds);
+            return;
+        }
+    }
+    launch_sensor_dense<Src, SUM, false>(dtype, src, nitems, cfg, stream, lds);
 }
 
 // lds > 0: every job of the launch reads the same dense map, whose read bits
@@ -730,6 +785,30 @@ void apply_cfg(SensorJob &J, const LaunchCfg &cfg) {
     J.lds8 = cfg.lds8 > 0 ? cfg.lds8 : kLdsEighths;
 }
 
+// The stream's workspace of a single-filter update: the piece partials
+// [npiece][N] (npiece > 1), then the pose-constant table [N][12], filled by one
+// pose_consts_kernel launch.  part given (the no-allocation call): the partials
+// go there and the lanes broadcast the pose constants instead (same bits).
+static mcl_status sensor_workspace(const mcl_map_s *map, const float *poses, int N, int npiece, bool table,
+                                   hipStream_t stream, float *&part, const float *&pc) {
+    pc = nullptr;
+    if (part) {
+        if (npiece == 1) part = nullptr;
+        return MCL_OK;
+    }
+    const size_t part_bytes = npiece > 1 ? (((size_t)npiece * N * sizeof(float) + 255) & ~(size_t)255) : 0;
+    const size_t pc_bytes = table ? (size_t)N * 12 * sizeof(float) : 0;
+    if (part_bytes + pc_bytes == 0) return MCL_OK;
+    char *ws = static_cast<char *>(workspace(stream, part_bytes + pc_bytes));
+    if (!ws) return fail(MCL_ENOMEM, "sensor_update: workspace allocation failed");
+    part = npiece > 1 ? reinterpret_cast<float *>(ws) : nullptr;
+    if (!table) return MCL_OK;
+    float *t = reinterpret_cast<float *>(ws + part_bytes);
+    pose_consts_kernel<<<(unsigned)((N + 255) / 256), 256, 0, stream>>>(map->view, poses, N, t);
+    pc = t;
+    return check_launch("pose_consts_kernel");
+}
+
 // part: the piece partials [npiece][N] (npiece > 1), or null for the stream's
 // workspace.  score / k2: the reading (kScoreSum needs a dense map; k2 = -c log2 e).
 static mcl_status launch_sensor_job(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
@@ -743,14 +822,12 @@ static mcl_status launch_sensor_job(const mcl_map_s *map, const float *pts, int 
         return check_launch("fill_kernel");
     }
     const int npiece = sensor_pieces(K);
-    if (npiece == 1) {
-        part = nullptr;
-    } else if (!part) {
-        part = static_cast<float *>(workspace(stream, (size_t)npiece * N * sizeof(float)));
-        if (!part) return fail(MCL_ENOMEM, "sensor_update: workspace allocation failed");
-    }
+    const float *pc = nullptr;
+    mcl_status wst = sensor_workspace(map, poses, N, npiece, !map->sparse, stream, part, pc);
+    if (wst != MCL_OK) return wst;
     using Src = OneJob<SensorJob>;
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
+    src.job.pc = pc;
     src.job.score = score;
     src.job.k2 = k2;
     if (!map->sparse) apply_cfg(src.job, cfg);
@@ -792,10 +869,9 @@ mcl_status launch_sensor_trilinear(mcl_map_s *map, const float *pts, int K, cons
     }
     const int npiece = sensor_pieces(K);
     float *part = nullptr;
-    if (npiece > 1) {
-        part = static_cast<float *>(workspace(stream, (size_t)npiece * N * sizeof(float)));
-        if (!part) return fail(MCL_ENOMEM, "sensor_update_trilinear: workspace allocation failed");
-    }
+    const float *pc = nullptr;
+    mcl_status wst = sensor_workspace(map, poses, N, npiece, false, stream, part, pc);
+    if (wst != MCL_OK) return wst;
     using Src = OneJob<SensorJob>;
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
     src.job.tri = map->tri;
