@@ -592,6 +592,24 @@ __global__ __launch_bounds__(256) void pose_consts_kernel(MapView m, const float
     for (int j = 0; j < 12; ++j) pc[(size_t)n * 12 + j] = pa[j];
 }
 
+// The same for every particle of every job of a batched launch (jobs whose pc
+// is set; elements by the jobs' particle offsets).
+template <typename Src>
+__global__ __launch_bounds__(256) void pose_consts_jobs_kernel(Src src) {
+    const int64_t nelems = src.elems();
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nelems; e += (int64_t)gridDim.x * 256) {
+        const int j = find_job(src, e, [](const SensorJob &J) { return J.elem0; });
+        const SensorJob &J = src.get(j);
+        if (!J.pc) continue;
+        const int n = (int)(e - J.elem0);
+        float pa[12];
+        pose_consts(J.poses, J.N, n, J.map, pa);
+        float *out = const_cast<float *>(J.pc) + (size_t)n * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) out[k] = pa[k];
+    }
+}
+
 __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ out, int n, float v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = v;
@@ -679,34 +697,30 @@ static void launch_sensor_dense(int32_t dtype, const Src &src, int64_t nitems, L
     else launch_sensor_t<float, Src, kLookNearest, SUM, PCT>(src, nitems, cfg, stream);
 }
 
-// A single filter whose pose-constant table was filled (pc set) reads it with
-// scalar loads; batched jobs and the no-allocation call broadcast from lanes.
-template <typename S>
-struct single_filter : std::false_type {};
-template <typename J>
-struct single_filter<OneJob<J>> : std::true_type {};
-
 template <typename Src, bool SUM>
 static void launch_sensor_dense(int32_t dtype, const Src &src, int64_t nitems, LaunchCfg cfg, hipStream_t stream,
-                                size_t lds) {
-    if constexpr (single_filter<Src>::value) {
-        if (src.job.pc) {
-            launch_sensor_dense<Src, SUM, true>(dtype, src, nitems, cfg, stream, lds);
-            return;
-        }
-    }
-    launch_sensor_dense<Src, SUM, false>(dtype, src, nitems, cfg, stream, lds);
+                                size_t lds, bool pct) {
+    if (pct) launch_sensor_dense<Src, SUM, true>(dtype, src, nitems, cfg, stream, lds);
+    else launch_sensor_dense<Src, SUM, false>(dtype, src, nitems, cfg, stream, lds);
 }
 
 // lds > 0: every job of the launch reads the same dense map, whose read bits
 // (nrwords * 4 <= lds bytes) each workgroup copies into LDS; the coarse level
 // is then chosen per wave (the jobs' `coarse` field).  sum: the jobs take the
 // sum reading (kScoreSum), else the product reading.
+// pct: every job of the launch has its pose-constant table (pc): filled here
+// first (batched jobs) or by the caller (a single filter, pc_ready).
 template <typename Src>
 mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int64_t nelems, bool combine,
-                             LaunchCfg cfg, hipStream_t stream, size_t lds, bool sum) {
-    if (sum) launch_sensor_dense<Src, true>(dtype, src, nitems, cfg, stream, lds);
-    else launch_sensor_dense<Src, false>(dtype, src, nitems, cfg, stream, lds);
+                             LaunchCfg cfg, hipStream_t stream, size_t lds, bool sum, bool pct, bool pc_ready) {
+    if (pct && !pc_ready) {
+        const int64_t blocks = std::min<int64_t>((nelems + 255) / 256, (int64_t)device_cus() * 16);
+        pose_consts_jobs_kernel<<<(unsigned)std::max<int64_t>(blocks, 1), 256, 0, stream>>>(src);
+        mcl_status st = check_launch("pose_consts_jobs_kernel");
+        if (st != MCL_OK) return st;
+    }
+    if (sum) launch_sensor_dense<Src, true>(dtype, src, nitems, cfg, stream, lds, pct);
+    else launch_sensor_dense<Src, false>(dtype, src, nitems, cfg, stream, lds, pct);
     mcl_status st = check_launch("sensor_kernel");
     if (st != MCL_OK || !combine) return st;
     int64_t blocks = std::min<int64_t>((nelems + 255) / 256, (int64_t)device_cus() * 16);
@@ -715,7 +729,7 @@ mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int6
 }
 
 template mcl_status launch_sensor_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t, int64_t,
-                                                           bool, LaunchCfg, hipStream_t, size_t, bool);
+                                                           bool, LaunchCfg, hipStream_t, size_t, bool, bool, bool);
 
 // Sparse maps with pools below 4 GiB (the offset table holds byte offsets):
 // one wave per work item, four waves per workgroup, as for a single call.
@@ -755,7 +769,7 @@ mcl_status launch_sensor_tri_src(int32_t dtype, const Src &src, int64_t nitems, 
 template mcl_status launch_sensor_tri_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t,
                                                                int64_t, bool, hipStream_t);
 template mcl_status launch_sensor_src<OneJob<SensorJob>>(int32_t, const OneJob<SensorJob> &, int64_t, int64_t,
-                                                         bool, LaunchCfg, hipStream_t, size_t, bool);
+                                                         bool, LaunchCfg, hipStream_t, size_t, bool, bool, bool);
 
 SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
                           float *logw, float *part) {
@@ -836,9 +850,11 @@ static mcl_status launch_sensor_job(const mcl_map_s *map, const float *pts, int 
     const size_t lds_bytes = (((size_t)map->view.nrwords + 3) & ~(size_t)3) * 4;  // 16-byte pieces
     if (!map->sparse && lds_bytes <= kMaxLdsBits && cfg.coarse != kCoarseBytes) {
         src.job.coarse = cfg.coarse;
-        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, lds_bytes, sum);
+        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, lds_bytes, sum, pc != nullptr,
+                                 true);
     }
-    if (!map->sparse) return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, 0, sum);
+    if (!map->sparse)
+        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, 0, sum, pc != nullptr, true);
     // sparse map: one wave per work item, four waves per workgroup
     const unsigned blocks = (unsigned)((nitems + 3) / 4);
     if (map->sp.small) {

@@ -19,7 +19,8 @@ namespace mcl {
 SensorJob make_sensor_job(const mcl_map_s *, const float *, int, const float *, int, float, float *, float *);
 void apply_cfg(SensorJob &, const LaunchCfg &);
 template <typename Src>
-mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t, size_t, bool);
+mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t, size_t, bool, bool,
+                             bool);
 template <typename Src>
 mcl_status launch_sensor_sparse_src(int32_t, const Src &, int64_t, int64_t, bool, hipStream_t);
 template <typename Src>
@@ -110,17 +111,20 @@ void drop_graphs(TickState &S) {
     S.graph_defs.clear();
 }
 
-size_t job_ws_bytes(int N, int K, bool est) {
+// Library workspace of one filter in a tick: weights stage, piece partials,
+// the particles' pose constants (dense maps, nearest lookup), pose estimate.
+size_t job_ws_bytes(int N, int K, bool est, bool pct) {
     const int np = sensor_pieces(K);
     size_t b = align256(weight_ws_bytes(N));
     if (np > 1) b += align256((size_t)np * N * sizeof(float));
+    if (pct) b += align256((size_t)N * 12 * sizeof(float));
     if (est) b += align256(estimate_ws_bytes(N));
     return b;
 }
 
 }  // namespace
 
-size_t tick_job_bytes(int N, int K) { return job_ws_bytes(N, K, true); }
+size_t tick_job_bytes(int N, int K) { return job_ws_bytes(N, K, true, true); }
 
 mcl_status check_job(const mcl_filter_job &J, int j) {
     std::string at = "tick: job " + std::to_string(j) + ": ";
@@ -195,7 +199,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     size_t need = kTablesBytes;
     int n_est = 0;
     for (int j = 0; j < n_jobs; ++j) {
-        need += job_ws_bytes(jobs[j].N, jobs[j].K, jobs[j].est_mean != nullptr);
+        need += job_ws_bytes(jobs[j].N, jobs[j].K, jobs[j].est_mean != nullptr, dense_nearest(job_kind(jobs[j])));
         n_est += jobs[j].est_mean != nullptr;
     }
     if (n_est) mask |= 1 << kGroups;
@@ -285,6 +289,10 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             }
             SensorJob &J = stbl[s];
             J = make_sensor_job(m, F.points, F.K, F.poses, F.N, c, F.logw, part);
+            if (dense_nearest(job_kind(F))) {  // the pose-constant table, filled by the launch chain
+                J.pc = reinterpret_cast<const float *>(ws);
+                ws += align256((size_t)F.N * 12 * sizeof(float));
+            }
             if (job_kind(F) == kKindTri) J.tri = m->tri;
             if (job_kind(F) == kKindDenseSum) {
                 J.score = kScoreSum;
@@ -394,7 +402,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             const bool comb = use_graph || combine[g];
             mcl_status st =
                 dense_nearest(kind) ? launch_sensor_src(type, src, key.items[g], key.elems, comb, cfgs[g], stream,
-                                                        (size_t)key.lds[g], kind == kKindDenseSum)
+                                                        (size_t)key.lds[g], kind == kKindDenseSum, true, false)
                 : kind == kKindSparse ? launch_sensor_sparse_src(type, src, key.items[g], key.elems, comb, stream)
                                       : launch_sensor_tri_src(type, src, key.items[g], key.elems, comb, stream);
             if (st != MCL_OK) return st;
