@@ -153,10 +153,12 @@ mcl_status mcl_sensor_update_sum(mcl_map map, const float *points, int32_t K, co
 
 /* The sensor update for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
- * Results are bit for bit those of mcl_sensor_update (same kernels).  Instead
- * of the stream's workspace, the piece partials (N * ceil(K / 4096) floats when
- * K > 4096; none otherwise) live in a fixed device array of
- * MCL_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on until
+ * Results are bit for bit those of mcl_sensor_update (same kernels, the same
+ * arithmetic).  Instead of the stream's workspace (the piece partials and a
+ * table of the particles' 12 pose constants), the piece partials
+ * (N * ceil(K / 4096) floats when K > 4096; none otherwise) live in a fixed
+ * device array, and the pose constants are passed between lanes; the array is
+ * of MCL_NOALLOC_SCRATCH_BYTES, which the library holds on each GPU it runs on until
  * the process ends.  The call allocates nothing and records no map-use event
  * (so mcl_map_free does not wait for this work: keep the map alive until the
  * stream has run it).  Every call on one GPU shares that GPU's array: calls
