@@ -18,6 +18,12 @@ constexpr int kGroup = 64;                        // particles per group (lane p
 
 inline int sensor_pieces(int K) { return K <= 0 ? 1 : (K + kPiece - 1) / kPiece; }
 
+// Launches of at least this many particle-point evaluations first write every
+// particle's pose constants to a table that the sensor kernel reads with scalar
+// loads; smaller ones broadcast them between lanes (the table's extra launch
+// costs more than it saves there).  The same values either way.
+constexpr int64_t kPoseTableMinEvals = int64_t(1) << 29;
+
 // Work items are (group, piece, run): a launch with few (group, piece) pairs
 // splits each group's particles into nsub runs of 64 / nsub (a power of two up
 // to 64), one work item each, until it has about kTargetItems items (four per

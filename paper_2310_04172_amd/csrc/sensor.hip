@@ -801,8 +801,10 @@ void apply_cfg(SensorJob &J, const LaunchCfg &cfg) {
 
 // The stream's workspace of a single-filter update: the piece partials
 // [npiece][N] (npiece > 1), then the pose-constant table [N][12], filled by one
-// pose_consts_kernel launch.  part given (the no-allocation call): the partials
-// go there and the lanes broadcast the pose constants instead (same bits).
+// pose_consts_kernel launch (for launches of at least kPoseTableMinEvals
+// evaluations: below that the extra launch costs more than the table saves).
+// part given (the no-allocation call): the partials go there and the lanes
+// broadcast the pose constants instead (same bits).
 static mcl_status sensor_workspace(const mcl_map_s *map, const float *poses, int N, int npiece, bool table,
                                    hipStream_t stream, float *&part, const float *&pc) {
     pc = nullptr;
@@ -837,7 +839,8 @@ static mcl_status launch_sensor_job(const mcl_map_s *map, const float *pts, int 
     }
     const int npiece = sensor_pieces(K);
     const float *pc = nullptr;
-    mcl_status wst = sensor_workspace(map, poses, N, npiece, !map->sparse, stream, part, pc);
+    mcl_status wst = sensor_workspace(map, poses, N, npiece, !map->sparse && (int64_t)N * K >= kPoseTableMinEvals,
+                                      stream, part, pc);
     if (wst != MCL_OK) return wst;
     using Src = OneJob<SensorJob>;
     Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};

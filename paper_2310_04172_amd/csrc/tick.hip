@@ -79,9 +79,10 @@ struct GraphKey {
     int64_t elems, blocks, eblocks, ejobs;
     std::array<int64_t, kGroups> lds;  // LDS bytes for the read bits of a group's shared map, or 0
     int fused;                          // weights stage: one workgroup per filter (1) or the chains (0)
+    int pct;                            // groups whose jobs read pose-constant tables (bit per group)
     bool operator<(const GraphKey &o) const {
-        return std::tie(mask, wpb, bpc, items, elems, blocks, eblocks, ejobs, lds, fused) <
-               std::tie(o.mask, o.wpb, o.bpc, o.items, o.elems, o.blocks, o.eblocks, o.ejobs, o.lds, o.fused);
+        return std::tie(mask, wpb, bpc, items, elems, blocks, eblocks, ejobs, lds, fused, pct) <
+               std::tie(o.mask, o.wpb, o.bpc, o.items, o.elems, o.blocks, o.eblocks, o.ejobs, o.lds, o.fused, o.pct);
     }
 };
 
@@ -251,6 +252,14 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         }
         cfgs[g] = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
     }
+    // pose-constant tables for a dense nearest group with enough evaluations
+    bool pct[kGroups] = {};
+    for (int g = 0; g < kGroups; ++g) {
+        if (!dense_nearest(g / kTypes)) continue;
+        int64_t ev = 0;
+        for (int t = g_begin[g]; t < g_begin[g + 1]; ++t) ev += (int64_t)jobs[order[t]].N * jobs[order[t]].K;
+        pct[g] = ev >= kPoseTableMinEvals;
+    }
     // runs per group where not tuned: one value for the whole tick, from its
     // total (group, piece) pairs
     int64_t pairs = 0;
@@ -289,8 +298,8 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             }
             SensorJob &J = stbl[s];
             J = make_sensor_job(m, F.points, F.K, F.poses, F.N, c, F.logw, part);
-            if (dense_nearest(job_kind(F))) {  // the pose-constant table, filled by the launch chain
-                J.pc = reinterpret_cast<const float *>(ws);
+            if (dense_nearest(job_kind(F))) {  // the pose-constant table's room; filled by the launch chain
+                if (pct[g]) J.pc = reinterpret_cast<const float *>(ws);
                 ws += align256((size_t)F.N * 12 * sizeof(float));
             }
             if (job_kind(F) == kKindTri) J.tri = m->tri;
@@ -366,7 +375,8 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     // replay serves any tick that fits; surplus waves exit at once).
     const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
     const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
-    GraphKey key{mask, {}, {}, {}, 0, 0, 0, 0, {}, 0};
+    GraphKey key{mask, {}, {}, {}, 0, 0, 0, 0, {}, 0, 0};
+    for (int g = 0; g < kGroups; ++g) key.pct |= (int)pct[g] << g;
     for (int g = 0; g < kGroups; ++g) {
         key.wpb[g] = cfgs[g].waves_per_block;
         key.bpc[g] = cfgs[g].blocks_per_cu;
@@ -402,7 +412,8 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             const bool comb = use_graph || combine[g];
             mcl_status st =
                 dense_nearest(kind) ? launch_sensor_src(type, src, key.items[g], key.elems, comb, cfgs[g], stream,
-                                                        (size_t)key.lds[g], kind == kKindDenseSum, true, false)
+                                                        (size_t)key.lds[g], kind == kKindDenseSum, (key.pct >> g) & 1,
+                                                        false)
                 : kind == kKindSparse ? launch_sensor_sparse_src(type, src, key.items[g], key.elems, comb, stream)
                                       : launch_sensor_tri_src(type, src, key.items[g], key.elems, comb, stream);
             if (st != MCL_OK) return st;

@@ -2,7 +2,10 @@
 ABI: bit for bit the results of mcl_sensor_update, on two calls in a row (the
 second smaller, so it reads a scratch array that still holds the first call's
 partials), plus one without partials; sizes beyond the fixed array are refused
-before anything runs."""
+before anything runs.  On the global workload mcl_sensor_update reads the
+particles' pose constants from its table and the no-allocation call passes them
+between lanes, so the first case also checks that the two paths agree bit for
+bit."""
 
 import ctypes as C
 import sys
