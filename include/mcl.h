@@ -428,6 +428,23 @@ mcl_status mcl_set_weights_fused_max(int32_t max_n);
 /* The current max_n of mcl_set_weights_fused_max. */
 int32_t mcl_get_weights_fused_max(void);
 
+/* Order in which the sensor update (Sec. III, Eq. 3) visits a filter's
+ * particles: mcl_sensor_update, mcl_sensor_update_sum and mcl_tick sort a
+ * dense-map filter of at least min_evals particle-point evaluations (N * K) by
+ * the cell of its particles' x-y positions (64 x 64 cells over the map, in
+ * Morton order) before the lookups, so that particles evaluated together, and
+ * by the same part of the chip, read nearby map regions and share cache lines.
+ * Each particle's log-weight is computed by exactly the same operations and
+ * written to its own index, so every output is bit-identical with or without
+ * the order; only the time differs.  The order costs four short launches and
+ * 8 bytes per particle of workspace.  A negative min_evals turns it off; the
+ * default is 2^32.  Process-wide; the sparse-map and trilinear lookups and
+ * mcl_sensor_update_noalloc never order.  Always MCL_OK. */
+mcl_status mcl_set_spatial_order_min(int64_t min_evals);
+
+/* The current min_evals of mcl_set_spatial_order_min. */
+int64_t mcl_get_spatial_order_min(void);
+
 /* Test support: the voxel each (particle, point) pair reads, by the same
  * device code as mcl_sensor_update.  lin_idx: device output [N][K] int64,
  * i + nx*(j + ny*k), or -1 outside the map.  N*K must not exceed 2^31. */

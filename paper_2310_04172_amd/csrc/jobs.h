@@ -24,6 +24,25 @@ inline int sensor_pieces(int K) { return K <= 0 ? 1 : (K + kPiece - 1) / kPiece;
 // costs more than it saves there).  The same values either way.
 constexpr int64_t kPoseTableMinEvals = int64_t(1) << 29;
 
+// Spatial order of a filter's particles for the sensor launch.  A filter of at
+// least spatial_order_min() evaluations is counting-sorted by the cell of its
+// particles' x-y position (kOrderSide x kOrderSide cells over the map's extent,
+// cells in Morton order) as its pose-constant table is written: slot s of the
+// table holds particle orig[s], so a wave's particles lie close together and so
+// do those of neighbouring work items, whose lookups then share cache lines.
+// Each particle's sum is formed exactly as before and written back to its own
+// index, so results do not depend on the order.
+constexpr int kOrderSide = 64;
+constexpr int kOrderCells = kOrderSide * kOrderSide;
+constexpr int kOrderBlock = 4096;                 // particles per counting block (256 threads x 16)
+constexpr int64_t kOrderDefaultMin = int64_t(1) << 32;
+int64_t spatial_order_min();                      // < 0: never
+inline bool spatial_order(int64_t evals) {
+    const int64_t m = spatial_order_min();
+    return m >= 0 && evals >= m;
+}
+inline int order_blocks(int N) { return (N + kOrderBlock - 1) / kOrderBlock; }
+
 // Work items are (group, piece, run): a launch with few (group, piece) pairs
 // splits each group's particles into nsub runs of 64 / nsub (a power of two up
 // to 64), one work item each, until it has about kTargetItems items (four per
@@ -55,7 +74,11 @@ struct SensorJob {
     int32_t score;        // kScoreProduct or kScoreSum (how the points' likelihoods combine)
     float k2;             // sum reading: -c log2(e), so a point's likelihood is 2^(k2 q^2)
     int32_t pad_;
-    const float *pc;      // [N][12] the particles' pose constants, or null: broadcast from the lanes
+    const float *pc;      // [N][12] the pose constants of the particle in each slot, or null: broadcast from the lanes
+    int32_t *ocell;       // spatial order: [kOrderCells] particles per cell, then the cell's first slot
+    int32_t *orank;       // spatial order: [N] a particle's rank within its cell
+    int32_t *orig;        // spatial order: [N] the particle in each slot; null: slot n holds particle n
+    int64_t oblk0;        // spatial order: first counting block of this job in the launch
 };
 
 // How a particle's points combine: the product of their likelihoods (l = -c sum q^2)

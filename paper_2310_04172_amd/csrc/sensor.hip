@@ -19,6 +19,7 @@
 // 6-level wave tree, 4 chunks per piece in order, pairwise over pieces): the
 // same particle gives the same bits whatever N, grid or batch it runs in.
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "jobs.h"
@@ -504,10 +505,11 @@ __device__ __attribute__((always_inline)) inline void sensor_store(const SensorJ
                                                                    float acc) {
     const ItemPos ip = item_pos(J, local);
     if (lane >= ip.p0 && lane < ip.p1) {
+        const int slot = ip.n0 + lane;
         if (J.npiece == 1)
-            J.logw[ip.n0 + lane] = particle_logw<SUM>(J, acc);
+            J.logw[J.orig ? J.orig[slot] : slot] = particle_logw<SUM>(J, acc);
         else
-            J.part[(size_t)ip.piece * J.N + ip.n0 + lane] = acc;
+            J.part[(size_t)ip.piece * J.N + slot] = acc;
     }
 }
 
@@ -541,7 +543,17 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == 
         }
         __syncthreads();
     }
-    for (int64_t item = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems;
+    // Workgroups go to the chip's 8 dies (XCDs, each with its own L2) in turn:
+    // workgroup b to die b mod 8.  Die x takes the x-th eighth of the work items
+    // instead, consecutive ones, so with the particles in spatial order each
+    // die's L2 holds the lines of one region of the map (a permutation of the
+    // workgroups: any order gives the same results).
+    int64_t first = blockIdx.x;
+    if (gridDim.x >= 8u) {
+        const uint32_t per = gridDim.x >> 3, extra = gridDim.x & 7u, x = blockIdx.x & 7u;
+        first = (int64_t)(x * per + min(x, extra) + (blockIdx.x >> 3));
+    }
+    for (int64_t item = first * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems;
          item += stride) {
         const int j = find_job_uniform(src, item, [](const SensorJob &J) { return J.item0; });
         float acc;
@@ -576,24 +588,119 @@ __global__ __launch_bounds__(256) void combine_kernel(Src src) {
         }
         float s = stack[--depth];
         while (depth > 0) s = stack[--depth] + s;
-        J.logw[n] = J.score == kScoreSum ? particle_logw<true>(J, s) : particle_logw<false>(J, s);
+        J.logw[J.orig ? J.orig[n] : n] = J.score == kScoreSum ? particle_logw<true>(J, s) : particle_logw<false>(J, s);
+    }
+}
+
+// Spatial order.  The cell of a particle: its x-y position in cells of
+// 1/kOrderSide of the map's extent per axis (clamped to the map; NaN to cell 0),
+// numbered in Morton order (the bits of the cell's x and y interleaved), so
+// cells close in number lie close in the map.
+__device__ inline uint32_t spread_bits(uint32_t v) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) r |= ((v >> b) & 1u) << (2 * b);
+    return r;
+}
+
+__device__ inline int order_cell(const SensorJob &J, int n) {
+    static_assert(kOrderSide == 64, "six bits per axis");
+    const MapView &m = J.map;
+    const float tx = gp(J.poses)[(size_t)9 * J.N + n], ty = gp(J.poses)[(size_t)10 * J.N + n];
+    const float hx = (float)kOrderSide / (float)m.nx, hy = (float)kOrderSide / (float)m.ny;
+    const float top = (float)(kOrderSide - 1);
+    // fmaxf returns the other operand for a NaN, so NaN lands in cell 0
+    const float fx = fminf(fmaxf((tx - m.ox) * m.inv_v * hx, 0.0f), top);
+    const float fy = fminf(fmaxf((ty - m.oy) * m.inv_v * hy, 0.0f), top);
+    return (int)(spread_bits((uint32_t)fx) | (spread_bits((uint32_t)fy) << 1));
+}
+
+// Clears the cell counters of every ordered job (one workgroup per job).
+template <typename Src>
+__global__ __launch_bounds__(256) void order_zero_kernel(Src src) {
+    for (int j = blockIdx.x; j < src.count(); j += gridDim.x) {
+        const SensorJob &J = src.get(j);
+        if (!J.orig) continue;
+        for (int c = threadIdx.x; c < kOrderCells; c += 256) J.ocell[c] = 0;
+    }
+}
+
+// Counts the particles of each cell and gives each particle its rank within its
+// cell: per block of kOrderBlock particles of one job a histogram in LDS (the
+// LDS adds give the ranks within the block), then one global add per occupied
+// cell, which returns the block's first rank in that cell.  Which block comes
+// first in a cell depends on timing; every particle still gets a distinct slot
+// and the results do not depend on the slots.
+template <typename Src>
+__global__ __launch_bounds__(256) void order_count_kernel(Src src) {
+    __shared__ int hist[kOrderCells];
+    constexpr int kPer = kOrderBlock / 256;
+    const int64_t nblk = src.blocks();
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int j = find_job_uniform(src, b, [](const SensorJob &J) { return J.oblk0; });
+        const SensorJob &J = src.get(j);
+        for (int c = threadIdx.x; c < kOrderCells; c += 256) hist[c] = 0;
+        __syncthreads();
+        const int n0 = (int)(b - J.oblk0) * kOrderBlock;
+        int cell[kPer], rank[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int n = n0 + i * 256 + (int)threadIdx.x;
+            cell[i] = n < J.N ? order_cell(J, n) : -1;
+            rank[i] = cell[i] >= 0 ? atomicAdd(&hist[cell[i]], 1) : 0;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < kOrderCells; c += 256) {
+            const int k = hist[c];
+            if (k) hist[c] = atomicAdd(&J.ocell[c], k);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            if (cell[i] >= 0) J.orank[n0 + i * 256 + (int)threadIdx.x] = hist[cell[i]] + rank[i];
+        __syncthreads();
+    }
+}
+
+// Each cell's count becomes its first slot: the exclusive prefix sum over the
+// cells in order (one workgroup per ordered job).
+template <typename Src>
+__global__ __launch_bounds__(256) void order_scan_kernel(Src src) {
+    __shared__ int tot[256];
+    constexpr int kPer = kOrderCells / 256;
+    const int t = threadIdx.x;
+    for (int j = blockIdx.x; j < src.count(); j += gridDim.x) {
+        const SensorJob &J = src.get(j);
+        if (!J.orig) continue;
+        int v[kPer], s = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            v[i] = J.ocell[t * kPer + i];
+            s += v[i];
+        }
+        tot[t] = s;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int x = t >= d ? tot[t - d] : 0;
+            __syncthreads();
+            tot[t] += x;
+            __syncthreads();
+        }
+        int run = tot[t] - s;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            J.ocell[t * kPer + i] = run;
+            run += v[i];
+        }
+        __syncthreads();
     }
 }
 
 // The pose constants of every particle (pose prologue), by the same device code
-// the lanes use, into a table the sensor kernel reads with scalar loads.
-__global__ __launch_bounds__(256) void pose_consts_kernel(MapView m, const float *__restrict__ poses, int N,
-                                                          float *__restrict__ pc) {
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= N) return;
-    float pa[12];
-    pose_consts(poses, N, n, m, pa);
-#pragma unroll
-    for (int j = 0; j < 12; ++j) pc[(size_t)n * 12 + j] = pa[j];
-}
-
-// The same for every particle of every job of a batched launch (jobs whose pc
-// is set; elements by the jobs' particle offsets).
+// the lanes use, into the table the sensor kernel reads with scalar loads (jobs
+// whose pc is set; elements by the jobs' particle offsets).  An ordered job's
+// particle goes to slot (first slot of its cell) + (its rank in the cell), and
+// the slot records the particle.
 template <typename Src>
 __global__ __launch_bounds__(256) void pose_consts_jobs_kernel(Src src) {
     const int64_t nelems = src.elems();
@@ -604,9 +711,15 @@ __global__ __launch_bounds__(256) void pose_consts_jobs_kernel(Src src) {
         const int n = (int)(e - J.elem0);
         float pa[12];
         pose_consts(J.poses, J.N, n, J.map, pa);
-        float *out = const_cast<float *>(J.pc) + (size_t)n * 12;
+        int slot = n;
+        if (J.orig) {
+            slot = J.ocell[order_cell(J, n)] + J.orank[n];
+            J.orig[slot] = n;
+        }
+        // a slot's 48 bytes as three 16-byte stores (tables are 256-byte aligned)
+        f32x4 *out = reinterpret_cast<f32x4 *>(const_cast<float *>(J.pc) + (size_t)slot * 12);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) out[k] = pa[k];
+        for (int k = 0; k < 3; ++k) out[k] = f32x4{pa[4 * k], pa[4 * k + 1], pa[4 * k + 2], pa[4 * k + 3]};
     }
 }
 
@@ -708,12 +821,27 @@ static void launch_sensor_dense(int32_t dtype, const Src &src, int64_t nitems, L
 // (nrwords * 4 <= lds bytes) each workgroup copies into LDS; the coarse level
 // is then chosen per wave (the jobs' `coarse` field).  sum: the jobs take the
 // sum reading (kScoreSum), else the product reading.
-// pct: every job of the launch has its pose-constant table (pc): filled here
-// first (batched jobs) or by the caller (a single filter, pc_ready).
+// pct: every job of the launch has its pose-constant table (pc), filled here
+// first.  ord: some jobs are put in spatial order (orig set) as their tables
+// are filled: src.blocks() counting blocks, oblocks (at least as many) sizing
+// the grid, and ojobs workgroups for the per-job passes.
 template <typename Src>
 mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int64_t nelems, bool combine,
-                             LaunchCfg cfg, hipStream_t stream, size_t lds, bool sum, bool pct, bool pc_ready) {
-    if (pct && !pc_ready) {
+                             LaunchCfg cfg, hipStream_t stream, size_t lds, bool sum, bool pct, bool ord,
+                             int64_t oblocks, int ojobs) {
+    if (pct) {
+        if (ord) {
+            const unsigned jb = (unsigned)std::max(ojobs, 1);
+            order_zero_kernel<<<jb, 256, 0, stream>>>(src);
+            mcl_status st = check_launch("order_zero_kernel");
+            if (st != MCL_OK) return st;
+            order_count_kernel<<<(unsigned)std::max<int64_t>(std::min<int64_t>(oblocks, 2048), 1), 256, 0, stream>>>(src);
+            st = check_launch("order_count_kernel");
+            if (st != MCL_OK) return st;
+            order_scan_kernel<<<jb, 256, 0, stream>>>(src);
+            st = check_launch("order_scan_kernel");
+            if (st != MCL_OK) return st;
+        }
         const int64_t blocks = std::min<int64_t>((nelems + 255) / 256, (int64_t)device_cus() * 16);
         pose_consts_jobs_kernel<<<(unsigned)std::max<int64_t>(blocks, 1), 256, 0, stream>>>(src);
         mcl_status st = check_launch("pose_consts_jobs_kernel");
@@ -729,7 +857,8 @@ mcl_status launch_sensor_src(int32_t dtype, const Src &src, int64_t nitems, int6
 }
 
 template mcl_status launch_sensor_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t, int64_t,
-                                                           bool, LaunchCfg, hipStream_t, size_t, bool, bool, bool);
+                                                           bool, LaunchCfg, hipStream_t, size_t, bool, bool, bool,
+                                                           int64_t, int);
 
 // Sparse maps with pools below 4 GiB (the offset table holds byte offsets):
 // one wave per work item, four waves per workgroup, as for a single call.
@@ -769,7 +898,8 @@ mcl_status launch_sensor_tri_src(int32_t dtype, const Src &src, int64_t nitems, 
 template mcl_status launch_sensor_tri_src<JobTable<SensorJob>>(int32_t, const JobTable<SensorJob> &, int64_t,
                                                                int64_t, bool, hipStream_t);
 template mcl_status launch_sensor_src<OneJob<SensorJob>>(int32_t, const OneJob<SensorJob> &, int64_t, int64_t,
-                                                         bool, LaunchCfg, hipStream_t, size_t, bool, bool, bool);
+                                                         bool, LaunchCfg, hipStream_t, size_t, bool, bool, bool,
+                                                         int64_t, int);
 
 SensorJob make_sensor_job(const mcl_map_s *map, const float *pts, int K, const float *poses, int N, float c,
                           float *logw, float *part) {
@@ -800,29 +930,40 @@ void apply_cfg(SensorJob &J, const LaunchCfg &cfg) {
 }
 
 // The stream's workspace of a single-filter update: the piece partials
-// [npiece][N] (npiece > 1), then the pose-constant table [N][12], filled by one
-// pose_consts_kernel launch (for launches of at least kPoseTableMinEvals
-// evaluations: below that the extra launch costs more than the table saves).
-// part given (the no-allocation call): the partials go there and the lanes
-// broadcast the pose constants instead (same bits).
-static mcl_status sensor_workspace(const mcl_map_s *map, const float *poses, int N, int npiece, bool table,
-                                   hipStream_t stream, float *&part, const float *&pc) {
-    pc = nullptr;
+// [npiece][N] (npiece > 1), then, with the table, the pose-constant table
+// [N][12] (filled by the launch), then, with the spatial order, the cell
+// counters and the particles' ranks and slots.  part given (the no-allocation
+// call): the partials go there, and neither the table nor the order is used
+// (the lanes broadcast the pose constants; same bits).
+static mcl_status sensor_workspace(SensorJob &J, int N, int npiece, bool table, bool ord, hipStream_t stream,
+                                   float *part) {
+    J.pc = nullptr;
+    J.ocell = J.orank = J.orig = nullptr;
+    J.oblk0 = 0;
     if (part) {
-        if (npiece == 1) part = nullptr;
+        J.part = npiece > 1 ? part : nullptr;
         return MCL_OK;
     }
-    const size_t part_bytes = npiece > 1 ? (((size_t)npiece * N * sizeof(float) + 255) & ~(size_t)255) : 0;
-    const size_t pc_bytes = table ? (size_t)N * 12 * sizeof(float) : 0;
-    if (part_bytes + pc_bytes == 0) return MCL_OK;
-    char *ws = static_cast<char *>(workspace(stream, part_bytes + pc_bytes));
+    auto a256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t part_bytes = npiece > 1 ? a256((size_t)npiece * N * sizeof(float)) : 0;
+    const size_t pc_bytes = table ? a256((size_t)N * 12 * sizeof(float)) : 0;
+    const size_t idx_bytes = a256((size_t)N * sizeof(int32_t));
+    const size_t ord_bytes = ord ? a256(kOrderCells * sizeof(int32_t)) + 2 * idx_bytes : 0;
+    J.part = nullptr;
+    if (part_bytes + pc_bytes + ord_bytes == 0) return MCL_OK;
+    char *ws = static_cast<char *>(workspace(stream, part_bytes + pc_bytes + ord_bytes));
     if (!ws) return fail(MCL_ENOMEM, "sensor_update: workspace allocation failed");
-    part = npiece > 1 ? reinterpret_cast<float *>(ws) : nullptr;
-    if (!table) return MCL_OK;
-    float *t = reinterpret_cast<float *>(ws + part_bytes);
-    pose_consts_kernel<<<(unsigned)((N + 255) / 256), 256, 0, stream>>>(map->view, poses, N, t);
-    pc = t;
-    return check_launch("pose_consts_kernel");
+    if (npiece > 1) J.part = reinterpret_cast<float *>(ws);
+    ws += part_bytes;
+    if (table) J.pc = reinterpret_cast<const float *>(ws);
+    ws += pc_bytes;
+    if (ord) {
+        J.ocell = reinterpret_cast<int32_t *>(ws);
+        ws += a256(kOrderCells * sizeof(int32_t));
+        J.orank = reinterpret_cast<int32_t *>(ws);
+        J.orig = reinterpret_cast<int32_t *>(ws + idx_bytes);
+    }
+    return MCL_OK;
 }
 
 // part: the piece partials [npiece][N] (npiece > 1), or null for the stream's
@@ -838,26 +979,28 @@ static mcl_status launch_sensor_job(const mcl_map_s *map, const float *pts, int 
         return check_launch("fill_kernel");
     }
     const int npiece = sensor_pieces(K);
-    const float *pc = nullptr;
-    mcl_status wst = sensor_workspace(map, poses, N, npiece, !map->sparse && (int64_t)N * K >= kPoseTableMinEvals,
-                                      stream, part, pc);
-    if (wst != MCL_OK) return wst;
     using Src = OneJob<SensorJob>;
-    Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
-    src.job.pc = pc;
+    Src src{make_sensor_job(map, pts, K, poses, N, c, logw, nullptr), {}};
+    // the pose-constant table and the spatial order: dense maps, not the no-allocation call
+    const int64_t evals = (int64_t)N * K;
+    const bool ord = !map->sparse && !part && spatial_order(evals);
+    const bool table = !map->sparse && !part && (evals >= kPoseTableMinEvals || ord);
+    mcl_status wst = sensor_workspace(src.job, N, npiece, table, ord, stream, part);
+    if (wst != MCL_OK) return wst;
     src.job.score = score;
     src.job.k2 = k2;
     if (!map->sparse) apply_cfg(src.job, cfg);
     const int64_t nitems = (int64_t)src.job.ngroups * npiece * src.job.nsub;
-    src.n = Counts{1, nitems, N, 0};
+    const int64_t oblocks = ord ? order_blocks(N) : 0;
+    src.n = Counts{1, nitems, N, oblocks};
     const size_t lds_bytes = (((size_t)map->view.nrwords + 3) & ~(size_t)3) * 4;  // 16-byte pieces
     if (!map->sparse && lds_bytes <= kMaxLdsBits && cfg.coarse != kCoarseBytes) {
         src.job.coarse = cfg.coarse;
-        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, lds_bytes, sum, pc != nullptr,
-                                 true);
+        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, lds_bytes, sum, table, ord,
+                                 oblocks, 1);
     }
     if (!map->sparse)
-        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, 0, sum, pc != nullptr, true);
+        return launch_sensor_src(map->dtype, src, nitems, N, npiece > 1, cfg, stream, 0, sum, table, ord, oblocks, 1);
     // sparse map: one wave per work item, four waves per workgroup
     const unsigned blocks = (unsigned)((nitems + 3) / 4);
     if (map->sp.small) {
@@ -887,12 +1030,10 @@ mcl_status launch_sensor_trilinear(mcl_map_s *map, const float *pts, int K, cons
         return check_launch("fill_kernel");
     }
     const int npiece = sensor_pieces(K);
-    float *part = nullptr;
-    const float *pc = nullptr;
-    mcl_status wst = sensor_workspace(map, poses, N, npiece, false, stream, part, pc);
-    if (wst != MCL_OK) return wst;
     using Src = OneJob<SensorJob>;
-    Src src{make_sensor_job(map, pts, K, poses, N, c, logw, part), {}};
+    Src src{make_sensor_job(map, pts, K, poses, N, c, logw, nullptr), {}};
+    mcl_status wst = sensor_workspace(src.job, N, npiece, false, false, stream, nullptr);
+    if (wst != MCL_OK) return wst;
     src.job.tri = map->tri;
     const int64_t nitems = (int64_t)src.job.ngroups * npiece * src.job.nsub;
     src.n = Counts{1, nitems, N, 0};
@@ -933,3 +1074,16 @@ mcl_status launch_debug_indices(const mcl_map_s *map, const float *pts, int K, c
 }
 
 }  // namespace mcl
+
+// ------------------------------------------------------------------ spatial order
+namespace mcl {
+static std::atomic<int64_t> g_order_min{kOrderDefaultMin};
+int64_t spatial_order_min() { return g_order_min.load(std::memory_order_relaxed); }
+}  // namespace mcl
+
+extern "C" mcl_status mcl_set_spatial_order_min(int64_t min_evals) {
+    mcl::g_order_min.store(min_evals, std::memory_order_relaxed);
+    return MCL_OK;
+}
+
+extern "C" int64_t mcl_get_spatial_order_min(void) { return mcl::spatial_order_min(); }

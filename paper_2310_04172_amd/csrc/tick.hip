@@ -20,7 +20,7 @@ SensorJob make_sensor_job(const mcl_map_s *, const float *, int, const float *, 
 void apply_cfg(SensorJob &, const LaunchCfg &);
 template <typename Src>
 mcl_status launch_sensor_src(int32_t, const Src &, int64_t, int64_t, bool, LaunchCfg, hipStream_t, size_t, bool, bool,
-                             bool);
+                             bool, int64_t, int);
 template <typename Src>
 mcl_status launch_sensor_sparse_src(int32_t, const Src &, int64_t, int64_t, bool, hipStream_t);
 template <typename Src>
@@ -80,9 +80,11 @@ struct GraphKey {
     std::array<int64_t, kGroups> lds;  // LDS bytes for the read bits of a group's shared map, or 0
     int fused;                          // weights stage: one workgroup per filter (1) or the chains (0)
     int pct;                            // groups whose jobs read pose-constant tables (bit per group)
+    int ord;                            // groups with jobs in spatial order (bit per group)
     bool operator<(const GraphKey &o) const {
-        return std::tie(mask, wpb, bpc, items, elems, blocks, eblocks, ejobs, lds, fused, pct) <
-               std::tie(o.mask, o.wpb, o.bpc, o.items, o.elems, o.blocks, o.eblocks, o.ejobs, o.lds, o.fused, o.pct);
+        return std::tie(mask, wpb, bpc, items, elems, blocks, eblocks, ejobs, lds, fused, pct, ord) <
+               std::tie(o.mask, o.wpb, o.bpc, o.items, o.elems, o.blocks, o.eblocks, o.ejobs, o.lds, o.fused, o.pct,
+                        o.ord);
     }
 };
 
@@ -112,13 +114,19 @@ void drop_graphs(TickState &S) {
     S.graph_defs.clear();
 }
 
+// The spatial order's room: cell counters, the particles' ranks and slots.
+size_t order_ws_bytes(int N) {
+    return align256(kOrderCells * sizeof(int32_t)) + 2 * align256((size_t)N * sizeof(int32_t));
+}
+
 // Library workspace of one filter in a tick: weights stage, piece partials,
-// the particles' pose constants (dense maps, nearest lookup), pose estimate.
+// the particles' pose constants and spatial order (dense maps, nearest
+// lookup), pose estimate.
 size_t job_ws_bytes(int N, int K, bool est, bool pct) {
     const int np = sensor_pieces(K);
     size_t b = align256(weight_ws_bytes(N));
     if (np > 1) b += align256((size_t)np * N * sizeof(float));
-    if (pct) b += align256((size_t)N * 12 * sizeof(float));
+    if (pct) b += align256((size_t)N * 12 * sizeof(float)) + order_ws_bytes(N);
     if (est) b += align256(estimate_ws_bytes(N));
     return b;
 }
@@ -252,13 +260,18 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
         }
         cfgs[g] = tuned_config(jobs[big].map->dtype, jobs[big].K, jobs[big].N);
     }
-    // pose-constant tables for a dense nearest group with enough evaluations
-    bool pct[kGroups] = {};
+    // pose-constant tables for a dense nearest group with enough evaluations,
+    // or with a filter large enough for the spatial order (which the tables carry)
+    bool pct[kGroups] = {}, ord[kGroups] = {};
     for (int g = 0; g < kGroups; ++g) {
         if (!dense_nearest(g / kTypes)) continue;
         int64_t ev = 0;
-        for (int t = g_begin[g]; t < g_begin[g + 1]; ++t) ev += (int64_t)jobs[order[t]].N * jobs[order[t]].K;
-        pct[g] = ev >= kPoseTableMinEvals;
+        for (int t = g_begin[g]; t < g_begin[g + 1]; ++t) {
+            const int64_t e = (int64_t)jobs[order[t]].N * jobs[order[t]].K;
+            ev += e;
+            ord[g] = ord[g] || spatial_order(e);
+        }
+        pct[g] = ev >= kPoseTableMinEvals || ord[g];
     }
     // runs per group where not tuned: one value for the whole tick, from its
     // total (group, piece) pairs
@@ -276,6 +289,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     char *ws = S.dev + kTablesBytes;
     bool combine[kGroups] = {};
     int64_t wblk = 0, welem = 0;
+    int64_t oblocks[kGroups] = {};
     for (int g = 0; g < kGroups; ++g) {
         int64_t items = 0, elems = 0;
         SensorJob *stbl = reinterpret_cast<SensorJob *>(S.host + kSensorTblOff + g * kSensorTblBytes) - g_begin[g];
@@ -298,9 +312,19 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             }
             SensorJob &J = stbl[s];
             J = make_sensor_job(m, F.points, F.K, F.poses, F.N, c, F.logw, part);
-            if (dense_nearest(job_kind(F))) {  // the pose-constant table's room; filled by the launch chain
+            if (dense_nearest(job_kind(F))) {  // the pose-constant table's and the order's room; filled by the launch chain
                 if (pct[g]) J.pc = reinterpret_cast<const float *>(ws);
                 ws += align256((size_t)F.N * 12 * sizeof(float));
+                if (pct[g] && spatial_order((int64_t)F.N * F.K)) {
+                    J.ocell = reinterpret_cast<int32_t *>(ws);
+                    J.orank = reinterpret_cast<int32_t *>(ws + align256(kOrderCells * sizeof(int32_t)));
+                    J.orig = J.orank + align256((size_t)F.N * sizeof(int32_t)) / sizeof(int32_t);
+                    J.oblk0 = oblocks[g];
+                    oblocks[g] += order_blocks(F.N);
+                } else {
+                    J.oblk0 = oblocks[g];  // no counting blocks of its own
+                }
+                ws += order_ws_bytes(F.N);
             }
             if (job_kind(F) == kKindTri) J.tri = m->tri;
             if (job_kind(F) == kKindDenseSum) {
@@ -351,7 +375,7 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
                 eelem += F.N;
             }
         }
-        cnt[g] = Counts{g_begin[g + 1] - g_begin[g], items, elems, 0};
+        cnt[g] = Counts{g_begin[g + 1] - g_begin[g], items, elems, oblocks[g]};
     }
     cnt[kWeightCnt] = Counts{n_jobs, 0, welem, wblk};
     cnt[kEstCnt] = Counts{ne, 0, eelem, eblk};
@@ -375,8 +399,11 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
     // replay serves any tick that fits; surplus waves exit at once).
     const Counts *dcnt = reinterpret_cast<const Counts *>(S.dev);
     const WeightJob *dwt = reinterpret_cast<const WeightJob *>(S.dev + kWeightTblOff);
-    GraphKey key{mask, {}, {}, {}, 0, 0, 0, 0, {}, 0, 0};
-    for (int g = 0; g < kGroups; ++g) key.pct |= (int)pct[g] << g;
+    GraphKey key{mask, {}, {}, {}, 0, 0, 0, 0, {}, 0, 0, 0};
+    for (int g = 0; g < kGroups; ++g) {
+        key.pct |= (int)pct[g] << g;
+        key.ord |= (int)ord[g] << g;
+    }
     for (int g = 0; g < kGroups; ++g) {
         key.wpb[g] = cfgs[g].waves_per_block;
         key.bpc[g] = cfgs[g].blocks_per_cu;
@@ -410,10 +437,13 @@ extern "C" mcl_status mcl_tick(const mcl_filter_job *jobs, int32_t n_jobs, int32
             // under a graph every group may combine (a job with one piece is skipped inside)
             const int type = g % kTypes, kind = g / kTypes;
             const bool comb = use_graph || combine[g];
+            // the order's grids: fixed under a graph (surplus workgroups exit)
+            const int64_t oblk = use_graph ? 2048 : oblocks[g];
+            const int ojobs = use_graph ? 64 : g_begin[g + 1] - g_begin[g];
             mcl_status st =
                 dense_nearest(kind) ? launch_sensor_src(type, src, key.items[g], key.elems, comb, cfgs[g], stream,
                                                         (size_t)key.lds[g], kind == kKindDenseSum, (key.pct >> g) & 1,
-                                                        false)
+                                                        (key.ord >> g) & 1, oblk, ojobs)
                 : kind == kKindSparse ? launch_sensor_sparse_src(type, src, key.items[g], key.elems, comb, stream)
                                       : launch_sensor_tri_src(type, src, key.items[g], key.elems, comb, stream);
             if (st != MCL_OK) return st;

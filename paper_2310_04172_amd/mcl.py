@@ -83,6 +83,9 @@ _lib.mcl_get_launch_config.argtypes = [_I, _I, _I, C.POINTER(LaunchConfig)]
 _lib.mcl_set_weights_fused_max.argtypes = [_I]
 _lib.mcl_get_weights_fused_max.argtypes = []
 _lib.mcl_get_weights_fused_max.restype = C.c_int32
+_lib.mcl_set_spatial_order_min.argtypes = [C.c_int64]
+_lib.mcl_get_spatial_order_min.argtypes = []
+_lib.mcl_get_spatial_order_min.restype = C.c_int64
 _lib.mcl_bench_gather_offsets.argtypes = [_P, _P, _I, _P, _I, _I, _P, _P]
 _lib.mcl_bench_gather_replay.argtypes = [_P, _P, _I, _I, _I, _I, _I, _P, C.c_size_t, _P]
 _lib.mcl_bench_line_gather.argtypes = [_P, C.c_size_t, _I, _I, _I, _I, C.c_uint32, _I, _P, C.c_size_t, _P]
@@ -93,7 +96,7 @@ for _f in ("mcl_map_upload", "mcl_map_upload_bricks", "mcl_map_free", "mcl_senso
            "mcl_sensor_update_noalloc", "mcl_sensor_update_sum", "mcl_normalize",
            "mcl_resample",
            "mcl_debug_voxel_indices", "mcl_tick", "mcl_autotune", "mcl_set_launch_config", "mcl_get_launch_config",
-           "mcl_set_weights_fused_max",
+           "mcl_set_weights_fused_max", "mcl_set_spatial_order_min",
            "mcl_pose_estimate", "mcl_motion_update",
            "mcl_init_uniform", "mcl_init_gaussian", "mcl_debug_philox", "mcl_bench_gather_offsets",
            "mcl_bench_gather_replay", "mcl_bench_line_gather", "mcl_bench_stream_read", "mcl_bench_l1_gather"):
@@ -518,6 +521,19 @@ def set_weights_fused_max(max_n: int):
 
 def get_weights_fused_max() -> int:
     return int(_lib.mcl_get_weights_fused_max())
+
+
+def set_spatial_order_min(min_evals: int):
+    """Dense-map sensor updates of at least min_evals particle-point evaluations
+    visit the particles sorted by their x-y cell (negative: never); the results
+    are the same bits either way.  Returns the previous value."""
+    prev = int(_lib.mcl_get_spatial_order_min())
+    _check(_lib.mcl_set_spatial_order_min(int(min_evals)), "mcl_set_spatial_order_min")
+    return prev
+
+
+def get_spatial_order_min() -> int:
+    return int(_lib.mcl_get_spatial_order_min())
 
 
 # ------------------------------------------------------------ measurement support

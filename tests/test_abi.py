@@ -135,6 +135,12 @@ def test_tick_and_tuning_argument_errors(mcl):
     assert mcl.get_weights_fused_max() == prev
     assert mcl.set_weights_fused_max(1000) == prev and mcl.get_weights_fused_max() == 1000
     assert mcl.set_weights_fused_max(prev) == 1000
+    # the spatial order's threshold: any value, negative turns it off; host state only
+    prev = mcl.get_spatial_order_min()
+    assert prev == 1 << 32
+    assert lib.mcl_set_spatial_order_min(-1) == mcl.MCL_OK and mcl.get_spatial_order_min() == -1
+    assert mcl.set_spatial_order_min(0) == -1 and mcl.get_spatial_order_min() == 0
+    assert mcl.set_spatial_order_min(prev) == 0 and mcl.get_spatial_order_min() == prev
     # measurement calls: NULL arguments, sizes, sinks shorter than the grid
     assert lib.mcl_bench_gather_offsets(None, P(0x1000), 10, P(0x2000), 10, 0, P(0x3000), None) == mcl.MCL_EINVAL
     assert lib.mcl_bench_gather_replay(P(0x1000), P(0x2000), 100, 10, 1, 1, 1, P(0x3000), 256, None) == mcl.MCL_EINVAL
