@@ -547,10 +547,13 @@ __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(LK == 
     // workgroup b to die b mod 8.  Die x takes the x-th eighth of the work items
     // instead, consecutive ones, so with the particles in spatial order each
     // die's L2 holds the lines of one region of the map (a permutation of the
-    // workgroups: any order gives the same results).
+    // workgroups that have work, so every die gets its share also when a
+    // replayed graph's grid is larger than the launch needs; any order gives
+    // the same results).
     int64_t first = blockIdx.x;
-    if (gridDim.x >= 8u) {
-        const uint32_t per = gridDim.x >> 3, extra = gridDim.x & 7u, x = blockIdx.x & 7u;
+    const int64_t used = std::min<int64_t>(gridDim.x, (nitems + WPB - 1) / WPB);
+    if (used >= 8 && (int64_t)blockIdx.x < used) {
+        const uint32_t g = (uint32_t)used, per = g >> 3, extra = g & 7u, x = blockIdx.x & 7u;
         first = (int64_t)(x * per + min(x, extra) + (blockIdx.x >> 3));
     }
     for (int64_t item = first * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems;
