@@ -438,7 +438,7 @@ int32_t mcl_get_weights_fused_max(void);
  * written to its own index, so every output is bit-identical with or without
  * the order; only the time differs.  The order costs four short launches and
  * 8 bytes per particle of workspace.  A negative min_evals turns it off; the
- * default is 2^32.  Process-wide; the sparse-map and trilinear lookups and
+ * default is 2^30.  Process-wide; the sparse-map and trilinear lookups and
  * mcl_sensor_update_noalloc never order.  Always MCL_OK. */
 mcl_status mcl_set_spatial_order_min(int64_t min_evals);
 

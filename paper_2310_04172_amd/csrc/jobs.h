@@ -35,7 +35,7 @@ constexpr int64_t kPoseTableMinEvals = int64_t(1) << 29;
 constexpr int kOrderSide = 64;
 constexpr int kOrderCells = kOrderSide * kOrderSide;
 constexpr int kOrderBlock = 4096;                 // particles per counting block (256 threads x 16)
-constexpr int64_t kOrderDefaultMin = int64_t(1) << 32;
+constexpr int64_t kOrderDefaultMin = int64_t(1) << 30;
 int64_t spatial_order_min();                      // < 0: never
 inline bool spatial_order(int64_t evals) {
     const int64_t m = spatial_order_min();

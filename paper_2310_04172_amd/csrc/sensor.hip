@@ -14,7 +14,11 @@
 //    few 128-byte lines of the flat bricks of the map;
 //  * a chunk's 64 lane sums are reduced across the wave by a fixed butterfly;
 //  * the scan is also split into pieces of 4 chunks (4096 points) so small
-//    particle counts still fill the GPU; pieces are combined pairwise.
+//    particle counts still fill the GPU; pieces are combined pairwise;
+//  * a large launch visits the particles in spatial order (sorted by map cell
+//    as their pose constants are written), and each die of the chip takes
+//    consecutive work items, so lookups made together share cache lines; each
+//    log-weight goes back to its particle's index.
 // The summation order is a function of K only (lane partials of 16 terms,
 // 6-level wave tree, 4 chunks per piece in order, pairwise over pieces): the
 // same particle gives the same bits whatever N, grid or batch it runs in.

@@ -137,7 +137,7 @@ def test_tick_and_tuning_argument_errors(mcl):
     assert mcl.set_weights_fused_max(prev) == 1000
     # the spatial order's threshold: any value, negative turns it off; host state only
     prev = mcl.get_spatial_order_min()
-    assert prev == 1 << 32
+    assert prev == 1 << 30
     assert lib.mcl_set_spatial_order_min(-1) == mcl.MCL_OK and mcl.get_spatial_order_min() == -1
     assert mcl.set_spatial_order_min(0) == -1 and mcl.get_spatial_order_min() == 0
     assert mcl.set_spatial_order_min(prev) == 0 and mcl.get_spatial_order_min() == prev

@@ -181,11 +181,11 @@ def test_global_workload_full_size(torch, mcl, order_min):
     the order at the default threshold; every log-weight equals the unordered
     launch's, bit for bit."""
     w = configs.config2()
-    assert (1 << 32) <= w.N * w.K
+    assert mcl.get_spatial_order_min() == 1 << 30 and (1 << 30) <= w.N * w.K
     say(f"case: spatial order, global workload N={w.N} K={w.K}")
     m = mcl.Map.from_tsdf(w.tmap)
     X, P = dev(torch, w.points), dev(torch, w.poses)
-    order_min(1 << 32)
+    order_min(1 << 30)
     a = mcl.sensor_update(m, X, P, w.sigma).cpu().numpy()
     order_min(-1)
     b = mcl.sensor_update(m, X, P, w.sigma).cpu().numpy()
