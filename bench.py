@@ -309,7 +309,11 @@ def run_single(args, w, workload_key, with_roofline=True, trilinear=False, spars
                                 "sensor update (sum reading)" if score_sum else "sensor update") +
                                " + normalise (f64 LSE) + resample (u64 systematic) + pose gather",
                        "workload_key": workload_key, "sensor_update_ms": sensor_ms,
-                       "launch": launch, "launch_autotuned": bool(args.autotune and not trilinear and not sparse)})
+                       "launch": launch, "launch_autotuned": bool(args.autotune and not trilinear and not sparse),
+                       # the particles are visited in spatial order (dense nearest lookups of at
+                       # least this many evaluations; same results either way)
+                       "spatial_order": bool(not trilinear and not sparse and 0 <= mcl.get_spatial_order_min() <= N * K),
+                       "spatial_order_min_evals": mcl.get_spatial_order_min()})
     out["latency_ms"] = spread(lat)
     if tick_lat:
         out["tick_graph_latency_ms"] = tick_lat

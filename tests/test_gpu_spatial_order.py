@@ -87,6 +87,8 @@ CASES = [
     (3000, 3000, "i8", "cluster"),    # one cell holds all, one piece: the sensor kernel writes back
     (4096, 4097, "f32", "uniform"),   # exactly one counting block, a ragged second piece
     (777, 1025, "i16", "edges"),      # particles outside the map and at NaN positions
+    (1, 5000, "i16", "uniform"),      # one particle: one counting block of one, a 63-lane empty group
+    (65, 300, "i8", "edges"),         # a full and a one-particle group, one short piece
 ]
 
 
