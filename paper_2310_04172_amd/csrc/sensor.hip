@@ -12,7 +12,7 @@
 //    evaluates the 16 points of every lane: 16 independent gathers in flight;
 //  * neighbouring lanes hold neighbouring beams, so one wave-wide gather touches
 //    few 128-byte lines of the flat bricks of the map;
-//  * a chunk's 64 lane sums are reduced across the wave by a fixed butterfly;
+//  * a chunk's 64 lane sums are reduced across the wave in a fixed pairwise tree;
 //  * the scan is also split into pieces of 4 chunks (4096 points) so small
 //    particle counts still fill the GPU; pieces are combined pairwise;
 //  * a large launch visits the particles in spatial order (sorted by map cell
@@ -35,12 +35,14 @@ __device__ inline float bcast(float x, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
-// Butterfly sum over the 64 lanes without LDS: DPP quad permutations (xor 1,
-// xor 2), half-row and row mirrors (pairing lane i with 7-i, 15-i once the
-// groups below are uniform) and the gfx950 row / half-wave swaps (xor 16,
-// xor 32).  Each step adds a lane's value and its partner's; IEEE addition is
-// commutative, so both lanes of a pair hold the same bits after every step and
-// all 64 lanes end with the same total, in a fixed order.
+// Sum over the 64 lanes without LDS, in a fixed pairwise tree: DPP quad
+// permutations (xor 1, xor 2) and the half-row and row mirrors (pairing lane i
+// with 7-i, 15-i once the groups below are uniform) leave every lane of row i
+// with its row's sum r_i; then each row adds the previous row's lane 15 (row 3
+// gets r2 + r3) and rows 2 and 3 add lane 31 (row 1's r0 + r1), so lane 63
+// holds (r0 + r1) + (r2 + r3), which is read into a scalar register.  IEEE
+// addition is commutative, so the order of a pair's operands does not matter;
+// rows other than row 3 end with partial or zero-filled sums that are never read.
 template <int CTRL>
 __device__ inline float dpp_add(float x) {
     return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
@@ -51,10 +53,9 @@ __device__ inline float wave_sum(float x) {
     x = dpp_add<0x4E>(x);   // quad_perm [2,3,0,1]
     x = dpp_add<0x141>(x);  // row_half_mirror
     x = dpp_add<0x140>(x);  // row_mirror
-    auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    x = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
-    auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
+    x = dpp_add<0x142>(x);  // row_bcast:15
+    x = dpp_add<0x143>(x);  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 // Raw map value as a 32-bit register (sign-extended integer or float bits).
@@ -378,6 +379,11 @@ __device__ __attribute__((always_inline)) inline void chunk_range(const SensorJo
                                    int p0, int p1, float &acc, const uint32_t *sbits, int n0, bool probe = false,
                                    int *nmixed = nullptr) {
     static_assert(!SUM || LK == kLookNearest || LK == kLookNearestLds, "the sum reading has the nearest lookup only");
+    // the run's bounds and the group's first particle are the same on every
+    // lane: said so, the particle loop and the table addresses are scalar work
+    p0 = __builtin_amdgcn_readfirstlane(p0);
+    p1 = __builtin_amdgcn_readfirstlane(p1);
+    n0 = __builtin_amdgcn_readfirstlane(n0);
     typedef const __attribute__((address_space(4))) float *cptr;
     float nx[12];  // with the table: the next particle's constants, loaded one particle ahead
     if constexpr (PCT) {
